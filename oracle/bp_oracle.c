@@ -1,0 +1,141 @@
+/*
+ * FP64 reference backprojection and forward projection (test infrastructure).
+ *
+ * This file is part of the CPU oracle.  Only the test-suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load it; the product library never
+ * does.  It shares no code, header or table with the HIP library.
+ *
+ * Operation (paper, Section 2.2 and the "LineRec" item of Section 3: direct
+ * discretisation of the backprojection line integral with linear
+ * interpolation):
+ *
+ *   f[z][iy][ix] = scale * sum_a ( (1-w) Q(j0) + w Q(j0+1) )
+ *     x = ix - floor(N/2),  y = iy - floor(N/2)
+ *     s = x cos(theta_a) + y sin(theta_a) + center      (detector coordinate)
+ *     j0 = floor(s),  w = s - j0
+ *     Q(j) = q[z][a][j] for 0 <= j < n_det, else 0
+ *
+ * The forward projector is the transpose of that map with scale 1: every
+ * voxel deposits (1-w) f into bin j0 and w f into bin j0+1 of each angle.
+ * Both are written in double precision with libm sin/cos, in the plainest
+ * loop order.  OpenMP only splits independent outputs over threads.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* q: [nz][na][n] filtered rows; f: [nz][N][N] output (overwritten). */
+void oracle_backproject(const double *q, int64_t nz, int64_t na, int64_t n,
+                        const double *angles, double center, int64_t N,
+                        double scale, double *f)
+{
+    const int64_t half = N / 2;
+    double *ct = (double *)malloc((size_t)na * sizeof(double));
+    double *st = (double *)malloc((size_t)na * sizeof(double));
+    for (int64_t a = 0; a < na; ++a) { ct[a] = cos(angles[a]); st[a] = sin(angles[a]); }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t iy = 0; iy < N; ++iy) {
+            const double y = (double)(iy - half);
+            for (int64_t ix = 0; ix < N; ++ix) {
+                const double x = (double)(ix - half);
+                double acc = 0.0;
+                for (int64_t a = 0; a < na; ++a) {
+                    const double s = x * ct[a] + y * st[a] + center;
+                    const double fl = floor(s);
+                    const int64_t j0 = (int64_t)fl;
+                    const double w = s - fl;
+                    const double *row = q + (z * na + a) * n;
+                    const double q0 = (j0 >= 0 && j0 < n) ? row[j0] : 0.0;
+                    const double q1 = (j0 + 1 >= 0 && j0 + 1 < n) ? row[j0 + 1] : 0.0;
+                    acc += (1.0 - w) * q0 + w * q1;
+                }
+                f[(z * N + iy) * N + ix] = scale * acc;
+            }
+        }
+    }
+    free(ct);
+    free(st);
+}
+
+/* Backprojection of one slice evaluated only at listed voxels (for sampled
+ * checks of large volumes).  q: [na][n]; out[k] is the value at (ix[k], iy[k]). */
+void oracle_backproject_points(const double *q, int64_t na, int64_t n,
+                               const double *angles, double center, int64_t N,
+                               double scale, const int64_t *ix, const int64_t *iy,
+                               int64_t npts, double *out)
+{
+    const int64_t half = N / 2;
+    double *ct = (double *)malloc((size_t)na * sizeof(double));
+    double *st = (double *)malloc((size_t)na * sizeof(double));
+    for (int64_t a = 0; a < na; ++a) { ct[a] = cos(angles[a]); st[a] = sin(angles[a]); }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < npts; ++k) {
+        const double x = (double)(ix[k] - half);
+        const double y = (double)(iy[k] - half);
+        double acc = 0.0;
+        for (int64_t a = 0; a < na; ++a) {
+            const double s = x * ct[a] + y * st[a] + center;
+            const double fl = floor(s);
+            const int64_t j0 = (int64_t)fl;
+            const double w = s - fl;
+            const double *row = q + a * n;
+            const double q0 = (j0 >= 0 && j0 < n) ? row[j0] : 0.0;
+            const double q1 = (j0 + 1 >= 0 && j0 + 1 < n) ? row[j0 + 1] : 0.0;
+            acc += (1.0 - w) * q0 + w * q1;
+        }
+        out[k] = scale * acc;
+    }
+    free(ct);
+    free(st);
+}
+
+/* f: [nz][N][N]; sino: [nz][na][n] output (overwritten).  Scatter form of the
+ * transpose: each (slice, angle) row is owned by one thread, so the order of
+ * additions into a bin is the fixed voxel order. */
+void oracle_radon(const double *f, int64_t nz, int64_t N, const double *angles,
+                  double center, int64_t na, int64_t n, double *sino)
+{
+    const int64_t half = N / 2;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t z = 0; z < nz; ++z) {
+        for (int64_t a = 0; a < na; ++a) {
+            double *row = sino + (z * na + a) * n;
+            memset(row, 0, (size_t)n * sizeof(double));
+            const double c = cos(angles[a]), sn = sin(angles[a]);
+            for (int64_t iy = 0; iy < N; ++iy) {
+                const double y = (double)(iy - half);
+                for (int64_t ix = 0; ix < N; ++ix) {
+                    const double x = (double)(ix - half);
+                    const double v = f[(z * N + iy) * N + ix];
+                    const double s = x * c + y * sn + center;
+                    const double fl = floor(s);
+                    const int64_t j0 = (int64_t)fl;
+                    const double w = s - fl;
+                    if (j0 >= 0 && j0 < n) row[j0] += (1.0 - w) * v;
+                    if (j0 + 1 >= 0 && j0 + 1 < n) row[j0 + 1] += w * v;
+                }
+            }
+        }
+    }
+}

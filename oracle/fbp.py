@@ -1,0 +1,339 @@
+"""FP64 reference implementation of the FBP hot path (TEST INFRASTRUCTURE ONLY).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may use this
+module.  It never imports the product package.
+
+Notation (paper, Section 2.2): raw projections P[a][z][j] (angle a, detector
+row z, detector column j), dark frames, flat frames, N_theta angles theta_a,
+rotation axis ``center`` in detector pixels.  The readings taken where the
+paper is silent are listed in each docstring.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+MIN_TRANSMISSION = 1e-6
+"""Lower clamp of the transmission before the logarithm (the paper is silent
+on photon-starved pixels; reading: clamp at 1e-6, so p <= -ln(1e-6))."""
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from .build import build_oracle
+            build_oracle()
+        lib = ctypes.CDLL(_LIB_PATH)
+        d = ctypes.c_double
+        i64 = ctypes.c_int64
+        pd = ctypes.POINTER(ctypes.c_double)
+        pi = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_backproject.argtypes = [pd, i64, i64, i64, pd, d, i64, d, pd]
+        lib.oracle_backproject.restype = None
+        lib.oracle_backproject_points.argtypes = [pd, i64, i64, pd, d, i64, d, pi, pi, i64, pd]
+        lib.oracle_backproject_points.restype = None
+        lib.oracle_radon.argtypes = [pd, i64, i64, pd, d, i64, i64, pd]
+        lib.oracle_radon.restype = None
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
+        _lib = lib
+    return _lib
+
+
+def _pd(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _pi(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def num_threads() -> int:
+    """Threads the C part of the oracle uses (OpenMP)."""
+    return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
+
+
+# --------------------------------------------------------------------------
+# Step 1: dark/flat correction and negative logarithm (Section 2.2).
+# --------------------------------------------------------------------------
+def dark_flat_mean(dark: np.ndarray, flat: np.ndarray):
+    """Per-pixel arithmetic mean of the dark and flat frame stacks.
+
+    dark: [n_dark][nz][n], flat: [n_flat][nz][n] (any integer type).
+    Reading: the paper says only "dark-flat field correction"; the frames are
+    averaged with the arithmetic mean.
+    """
+    d = np.asarray(dark, dtype=np.float64).mean(axis=0)
+    f = np.asarray(flat, dtype=np.float64).mean(axis=0)
+    return d, f
+
+
+def normalize(proj: np.ndarray, dark: np.ndarray, flat: np.ndarray) -> np.ndarray:
+    """p = -ln( max( (P - D) / max(F - D, 1), 1e-6 ) ), returned sinogram-major.
+
+    proj: [n_angles][nz][n] raw counts (projection-major, as recorded).
+    Returns p: [nz][n_angles][n] float64.
+    Readings: natural logarithm; a dead pixel (F - D <= 0) uses a denominator
+    of one count; photon starvation clamps the transmission at 1e-6.
+    """
+    d, f = dark_flat_mean(dark, flat)
+    P = np.asarray(proj, dtype=np.float64)
+    den = np.maximum(f - d, 1.0)
+    t = (P - d[None, :, :]) / den[None, :, :]
+    t = np.maximum(t, MIN_TRANSMISSION)
+    p = -np.log(t)
+    return np.ascontiguousarray(p.transpose(1, 0, 2))
+
+
+# --------------------------------------------------------------------------
+# Step 2: padded ramp filter along detector rows (Section 2.2).
+# --------------------------------------------------------------------------
+def pad_len(n: int) -> int:
+    """Padded row length: the power of two at or above 2 n.
+
+    Reading: the paper pads 16-bit data to powers of two; this build uses the
+    same power-of-two length for every storage type.
+    """
+    return 1 << int(math.ceil(math.log2(2 * n)))
+
+
+def ramp_kernel(L: int) -> np.ndarray:
+    """Band-limited ramp h[m] = integral over |w| <= 1/2 of |w| exp(2 pi i w m) dw.
+
+    Closed form: h[0] = 1/4, h[m] = -1/(pi^2 m^2) for odd m, 0 for even m != 0,
+    for m in [-L/2, L/2).  Returned in FFT order (index m mod L).
+    Reading: the paper names Shepp-Logan and Parzen windows but defines no
+    filter; the plain band-limited ramp (cycles per pixel) is used.
+    """
+    m = np.arange(L, dtype=np.int64)
+    m = np.where(m < L // 2, m, m - L)  # signed lag
+    h = np.zeros(L, dtype=np.float64)
+    h[m == 0] = 0.25
+    odd = (m % 2) != 0
+    h[odd] = -1.0 / (math.pi ** 2 * m[odd].astype(np.float64) ** 2)
+    return h
+
+
+def ramp_response(L: int) -> np.ndarray:
+    """H[k] = sum_m h[m] exp(-2 pi i k m / L), real and even (FFT of ``ramp_kernel``)."""
+    return np.fft.fft(ramp_kernel(L)).real
+
+
+def pad_rows(p: np.ndarray, L: int):
+    """Edge-replicating pad of the last axis from n to L, data at offset floor((L-n)/2).
+
+    Returns (u, off).  Reading: the paper pads before filtering to suppress
+    artefacts from matter outside the field of view, which implies a
+    non-zero (edge) pad rather than zeros.
+    """
+    n = p.shape[-1]
+    off = (L - n) // 2
+    u = np.empty(p.shape[:-1] + (L,), dtype=np.float64)
+    u[..., off:off + n] = p
+    u[..., :off] = p[..., :1]
+    u[..., off + n:] = p[..., -1:]
+    return u, off
+
+
+def filter_rows(p: np.ndarray, L: int | None = None) -> np.ndarray:
+    """q = crop( IFFT( H * FFT( pad(p) ) ) ) along the last axis, FP64."""
+    n = p.shape[-1]
+    L = pad_len(n) if L is None else L
+    u, off = pad_rows(np.asarray(p, dtype=np.float64), L)
+    H = ramp_response(L)
+    y = np.fft.ifft(np.fft.fft(u, axis=-1) * H, axis=-1).real
+    return np.ascontiguousarray(y[..., off:off + n])
+
+
+def filter_rows_direct(p: np.ndarray, L: int | None = None) -> np.ndarray:
+    """Same result as ``filter_rows`` by direct circular convolution with h.
+
+    y[off + j] = sum_k u[k] h[(off + j - k) mod L]; O(n L) per row, for small
+    sizes only.  Independent of the FFT route (used as its pin).
+    """
+    n = p.shape[-1]
+    L = pad_len(n) if L is None else L
+    u, off = pad_rows(np.asarray(p, dtype=np.float64), L)
+    h = ramp_kernel(L)
+    k = np.arange(L)
+    out = np.empty(p.shape[:-1] + (n,), dtype=np.float64)
+    for j in range(n):
+        out[..., j] = u @ h[(off + j - k) % L]
+    return out
+
+
+# --------------------------------------------------------------------------
+# Storage rounding (Section 2.1: 16-bit storage, 32-bit arithmetic).
+# --------------------------------------------------------------------------
+def round_f16(x: np.ndarray) -> np.ndarray:
+    """Round to IEEE binary16 with round-to-nearest-even (numpy's conversion)."""
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to bfloat16 with round-to-nearest-even (finite inputs).
+
+    bfloat16 keeps the upper 16 bits of an IEEE binary32; rounding adds
+    0x7FFF plus the lowest kept bit before truncation.
+    """
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# Step 3: backprojection with linear interpolation (LineRec) and its transpose.
+# --------------------------------------------------------------------------
+def backproject(q: np.ndarray, angles, center: float, N: int, scale: float | None = None) -> np.ndarray:
+    """f[z][iy][ix] = scale * sum_a ((1-w) Q(j0) + w Q(j0+1)), FP64 (C loop).
+
+    q: [nz][n_angles][n]; voxel centres x = ix - N//2, y = iy - N//2 (ix fast);
+    s = x cos + y sin + center; taps off the detector read zero.
+    scale defaults to pi / n_angles (uniform 180-degree scan).
+    """
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    if q.ndim == 2:
+        q = q[None]
+    nz, na, n = q.shape
+    ang = np.ascontiguousarray(angles, dtype=np.float64)
+    assert ang.shape == (na,)
+    if scale is None:
+        scale = math.pi / na
+    f = np.empty((nz, N, N), dtype=np.float64)
+    _load().oracle_backproject(_pd(q), nz, na, n, _pd(ang), float(center), N, float(scale), _pd(f))
+    return f
+
+
+def backproject_points(q: np.ndarray, angles, center: float, N: int, ix, iy,
+                       scale: float | None = None) -> np.ndarray:
+    """Backprojection of one slice q: [n_angles][n] at voxels (ix[k], iy[k])."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    na, n = q.shape
+    ang = np.ascontiguousarray(angles, dtype=np.float64)
+    ix = np.ascontiguousarray(ix, dtype=np.int64)
+    iy = np.ascontiguousarray(iy, dtype=np.int64)
+    if scale is None:
+        scale = math.pi / na
+    out = np.empty(ix.shape[0], dtype=np.float64)
+    _load().oracle_backproject_points(_pd(q), na, n, _pd(ang), float(center), N, float(scale),
+                                      _pi(ix), _pi(iy), ix.shape[0], _pd(out))
+    return out
+
+
+def radon(f: np.ndarray, angles, center: float, n: int) -> np.ndarray:
+    """(R f)[z][a][j] = sum over voxels of f * ((1-w)[j0 = j] + w[j0 + 1 = j]).
+
+    The transpose of ``backproject`` with scale 1 (voxel-driven scatter of the
+    same hat weights).  f: [nz][N][N] -> [nz][n_angles][n].
+    Reading: the paper defines no forward projector; the exact transpose of
+    the linear-interpolation backprojector is used.
+    """
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim == 2:
+        f = f[None]
+    nz, N, N2 = f.shape
+    assert N == N2
+    ang = np.ascontiguousarray(angles, dtype=np.float64)
+    na = ang.shape[0]
+    out = np.empty((nz, na, n), dtype=np.float64)
+    _load().oracle_radon(_pd(f), nz, N, _pd(ang), float(center), na, n, _pd(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# The composition.
+# --------------------------------------------------------------------------
+def _round_storage(x, storage):
+    if storage in (None, "f32"):
+        return x
+    if storage == "f16":
+        return round_f16(x)
+    if storage == "bf16":
+        return round_bf16(x)
+    raise ValueError(storage)
+
+
+def fbp(proj, dark, flat, angles, center: float, N: int | None = None, storage: str | None = None):
+    """FBP = backproject(filter(normalize(raw))), FP64, scale pi / n_angles.
+
+    ``storage`` in {None/'f32', 'f16', 'bf16'} rounds the filtered rows to that
+    type before backprojection (emulates reduced-precision storage with
+    arithmetic kept in higher precision).  'f32' applies no rounding: the FP32
+    GPU path is compared against the unrounded FP64 result.
+    """
+    p = normalize(proj, dark, flat)
+    n = p.shape[-1]
+    q = filter_rows(p)
+    q = _round_storage(q, storage)
+    return backproject(q, angles, center, n if N is None else N)
+
+
+def fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, storage=None):
+    """FBP of one slice at listed voxels.
+
+    proj_slice: [n_angles][n] raw counts of one detector row;
+    dark_slice/flat_slice: [n_frames][n].
+    """
+    p = normalize(np.asarray(proj_slice)[:, None, :], np.asarray(dark_slice)[:, None, :],
+                  np.asarray(flat_slice)[:, None, :])[0]
+    q = _round_storage(filter_rows(p), storage)
+    return backproject_points(q, angles, center, N, ix, iy)
+
+
+# --------------------------------------------------------------------------
+# Least squares with the projector pair.
+# --------------------------------------------------------------------------
+def power_lambda_max(angles, center, N, n, iters: int = 30, seed: int = 0) -> float:
+    """Largest eigenvalue of R^T R by power iteration from a seeded start (FP64)."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((1, N, N))
+    x /= np.linalg.norm(x)
+    lam = 0.0
+    for _ in range(iters):
+        y = backproject(radon(x, angles, center, n), angles, center, N, scale=1.0)
+        lam = float(np.vdot(x, y))
+        x = y / np.linalg.norm(y)
+    return lam
+
+
+def ls_gradient(x, y, angles, center):
+    """Gradient of ||R x - y||^2: 2 R^T (R x - y)."""
+    N = x.shape[-1]
+    n = y.shape[-1]
+    r = radon(x, angles, center, n) - y
+    return 2.0 * backproject(r, angles, center, N, scale=1.0)
+
+
+def ls_solve(y, angles, center, N, steps: int, eta: float, x0=None):
+    """Gradient descent x_{k+1} = x_k - eta * 2 R^T (R x_k - y), x_0 = 0.
+
+    Returns (x, losses) with losses[k] = ||R x_k - y||^2 before step k.
+    Reading: the paper has no iterative solver; this plain gradient method
+    with step eta = 1/(2 lambda_max(R^T R)) is the least-squares form used.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    if y.ndim == 2:
+        y = y[None]
+    x = np.zeros((y.shape[0], N, N)) if x0 is None else np.array(x0, dtype=np.float64)
+    n = y.shape[-1]
+    losses = []
+    for _ in range(steps):
+        r = radon(x, angles, center, n) - y
+        losses.append(float(np.sum(r * r)))
+        x = x - eta * 2.0 * backproject(r, angles, center, N, scale=1.0)
+    return x, losses
