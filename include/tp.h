@@ -1,0 +1,182 @@
+/*
+ * tp.h -- C ABI of libtp.so, the MI355X (gfx950) filtered-backprojection hot path
+ * for parallel-beam tomography (arXiv 2209.08450, "TomocuPy").
+ *
+ * Path: raw projections + dark/flat fields --(tp_normalize)--> sinogram
+ *       --(tp_filter)--> ramp-filtered rows --(tp_backproject)--> slices,
+ * fused as tp_fbp_chunk; tp_radon is the exact transpose of tp_backproject.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Device pointers are caller-owned; the library never frees or retains them
+ *   beyond the call.  `stream` is a hipStream_t passed as void* (NULL = the
+ *   null stream).  Every compute call only enqueues work on `stream` and
+ *   returns; results are visible after the caller synchronises that stream.
+ * - Arguments are validated on the host before anything is enqueued.  On a
+ *   bad argument a call returns TP_EINVAL (or TP_EUNSUPPORTED for a valid but
+ *   unimplemented choice), enqueues nothing, and tp_last_error() describes
+ *   the problem.  A failed launch returns TP_EHIP.  No call aborts, exits or
+ *   lets a C++ exception escape.
+ * - Geometry: detector column j sits at detector coordinate j; the rotation
+ *   axis is at `center` (in columns).  Voxel (ix, iy) of an N x N slice is
+ *   centred at x = ix - floor(N/2), y = iy - floor(N/2) (ix is the fast,
+ *   contiguous axis), and projects at angle theta to s = x cos + y sin + center.
+ *   Detector rows (slices) are independent.
+ * - Layouts (row-major, last index fastest):
+ *     raw projections  uint16 [n_angles][rows][n_det]   (projection-major, as recorded)
+ *     dark / flat      uint16 [frames][rows][n_det]
+ *     sinogram, rows   [rows][n_angles][n_det]           (sinogram-major)
+ *     volume           float  [rows][N][N]
+ * - Hot calls (normalize/filter/backproject/radon/fbp_chunk) never allocate
+ *   device memory once their tables exist (tp_plan_create builds the
+ *   geometry and filter tables of a plan; tp_filter_prepare those of a
+ *   standalone filter length), so they may be captured into a HIP graph.
+ */
+#ifndef TP_H
+#define TP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TP_OK = 0,
+    TP_EINVAL = -1,        /* invalid argument; nothing enqueued */
+    TP_EUNSUPPORTED = -2,  /* valid request this build does not implement */
+    TP_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    TP_ENOMEM = -4         /* device allocation failed (table building only) */
+} tp_status;
+
+/* Storage type of sinograms and filtered rows.  Arithmetic is FP32 for all. */
+typedef enum { TP_F32 = 0, TP_F16 = 1, TP_BF16 = 2 } tp_dtype;
+
+/* Row filter.  Only the band-limited ramp |w| (cycles/pixel) is implemented;
+ * the paper's Shepp-Logan and Parzen windows (Section 2.4 options) return
+ * TP_EUNSUPPORTED. */
+typedef enum { TP_RAMP = 0, TP_SHEPP = 1, TP_PARZEN = 2 } tp_filter_kind;
+
+/* Scan geometry (paper Section 2.4: angles, rotation axis, detector width). */
+typedef struct {
+    int32_t n_angles;       /* N_theta >= 1 */
+    int32_t n_det;          /* detector columns n >= 1 (filter length limit: n <= 8192) */
+    int32_t n_vox;          /* reconstructed slice is n_vox x n_vox; 0 => n_det */
+    double center;          /* rotation axis in detector columns (any value; rays off
+                               the detector contribute zero) */
+    const double* angles;   /* HOST pointer to n_angles radians, read during
+                               tp_plan_create only */
+} tp_geometry;
+
+/* A plan owns device-side tables for one geometry on the device that is
+ * current when it is created: FP32 (cos, sin) per angle and, per 32-voxel
+ * tile edge, the detector coordinate of the tile origin computed in FP64 and
+ * split into an integer and an FP32 fraction, plus the ramp filter's tables
+ * for pad length 2^ceil(log2(2 n_det)).  Use a plan only on that device. */
+typedef struct tp_plan tp_plan;
+
+tp_status tp_plan_create(const tp_geometry* g, tp_plan** out);
+/* Frees the plan's tables; the caller must ensure no enqueued work still uses them. */
+tp_status tp_plan_destroy(tp_plan* plan);
+
+/* Tuning of the backprojection kernel (results are bitwise identical for
+ * every legal choice: each slice always sums angles in order).
+ *   slices_per_block in {1, 2, 4, 8}: slices sharing one geometry evaluation;
+ *   angles_per_block in {8, 16, 32, 64}: angles staged in LDS per step. */
+tp_status tp_plan_set_tuning(tp_plan* plan, int32_t slices_per_block, int32_t angles_per_block);
+tp_status tp_plan_get_tuning(const tp_plan* plan, int32_t* slices_per_block, int32_t* angles_per_block);
+
+/* Build and cache the ramp-filter tables of one pad length on the current
+ * device (for tp_filter calls that will be graph-captured).  pad_len: power of
+ * two in [2, 16384]. */
+tp_status tp_filter_prepare(int32_t pad_len, tp_filter_kind kind);
+
+/* --------------------------------------------------------------------------
+ * Dark/flat correction and negative logarithm (paper Section 2.2):
+ *   D = mean over frames of dark, F = mean over frames of flat   (per pixel)
+ *   sino[r][a][j] = -ln( max( (P[a][r][j] - D) / max(F - D, 1), 1e-6 ) )
+ * proj:  dev, element (a, r, j) at proj[a*proj_stride + r*n_det + j];
+ *        proj_stride 0 => n_rows*n_det (contiguous).
+ * dark/flat: dev, frame f row r at ptr[f*frame_stride + r*n_det]; frame_stride
+ *        0 => n_rows*n_det.  n_dark, n_flat >= 1, each <= 256 (exact sums).
+ * sino:  dev [n_rows][n_angles][n_det] of out_dtype (RNE rounding for F16/BF16).
+ * workspace: dev, >= tp_normalize_workspace_bytes(n_rows, n_det) bytes,
+ *        256-byte aligned; holds D and max(F - D, 1) between two kernels.
+ * ------------------------------------------------------------------------ */
+size_t tp_normalize_workspace_bytes(int32_t n_rows, int32_t n_det);
+tp_status tp_normalize(const uint16_t* proj, int64_t proj_stride,
+                       const uint16_t* dark, int32_t n_dark,
+                       const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                       int32_t n_angles, int32_t n_rows, int32_t n_det,
+                       tp_dtype out_dtype, void* sino,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* --------------------------------------------------------------------------
+ * Ramp filter of detector rows by FFT (paper Section 2.2, padding per Section 3):
+ * each row p[0..n) is padded to L by replicating its end values, with the data
+ * at offset floor((L - n)/2); y = IFFT(H . FFT(u)), H[k] = DFT of the
+ * band-limited ramp h[0] = 1/4, h[odd m] = -1/(pi^2 m^2); q[j] = y[off + j].
+ * sino: dev [n_lines][n_det] of in_dtype;  filt: dev [n_lines][n_det] of
+ * out_dtype; filt may equal sino only when in_dtype == out_dtype (in place),
+ * otherwise the ranges must not overlap.  pad_len 0 => 2^ceil(log2(2 n_det));
+ * else a power of two with n_det <= pad_len <= 16384.
+ * ------------------------------------------------------------------------ */
+tp_status tp_filter(const void* sino, tp_dtype in_dtype, void* filt, tp_dtype out_dtype,
+                    int64_t n_lines, int32_t n_det, int32_t pad_len, tp_filter_kind kind,
+                    void* stream);
+
+/* --------------------------------------------------------------------------
+ * Backprojection with linear interpolation ("LineRec", paper Sections 2.2, 3):
+ *   vol[r][iy][ix] (+)= scale * sum_a ( (1-w) Q(j0) + w Q(j0+1) ),
+ *   s = x cos(theta_a) + y sin(theta_a) + center, j0 = floor(s), w = s - j0,
+ *   Q(j) = filt[r][a][j] for 0 <= j < n_det, else 0.
+ * FBP uses scale = pi / n_angles; the adjoint of tp_radon uses scale = 1.
+ * filt: dev [n_rows][n_angles][n_det] of in_dtype.  vol: dev float
+ * [n_rows][N][N]; accumulate 0 overwrites, 1 adds.  Arithmetic is FP32 with
+ * the detector coordinate split into an FP64-derived integer part and an
+ * FP32 offset below 64 columns.
+ * ------------------------------------------------------------------------ */
+tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtype,
+                         int32_t n_rows, float scale, float* vol, int32_t accumulate,
+                         void* stream);
+
+/* --------------------------------------------------------------------------
+ * Forward projection, the exact transpose of tp_backproject with scale 1:
+ *   sino[r][a][j] = sum over voxels of vol[r][iy][ix] * ( (1-w)[j0 == j] + w[j0+1 == j] )
+ * with (j0, w) computed by the same FP32 formula as tp_backproject, so
+ * <R x, y> = <x, R^T y> holds up to FP32 summation rounding.  Gather form
+ * (each output summed by one thread in a fixed order): deterministic.
+ * vol: dev float [n_rows][N][N];  sino: dev float [n_rows][n_angles][n_det], overwritten.
+ * ------------------------------------------------------------------------ */
+tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float* sino,
+                   void* stream);
+
+/* --------------------------------------------------------------------------
+ * One chunk of rows through the whole path: normalise -> filter -> backproject.
+ *   vol = (pi / n_angles) R^T ( H * normalize(proj, dark, flat) )
+ * The -log sinogram never leaves the chip: the filter kernel normalises raw
+ * counts in registers, filters in FP32 and stores only the filtered rows, in
+ * `storage` precision, into the workspace.  Inputs as for tp_normalize
+ * (n_angles, n_det from the plan); vol: dev float [n_rows][N][N] (overwritten).
+ * workspace: dev, 256-byte aligned, >= tp_fbp_workspace_bytes(plan, n_rows, storage).
+ * ------------------------------------------------------------------------ */
+size_t tp_fbp_workspace_bytes(const tp_plan* plan, int32_t n_rows, tp_dtype storage);
+tp_status tp_fbp_chunk(const tp_plan* plan,
+                       const uint16_t* proj, int64_t proj_stride,
+                       const uint16_t* dark, int32_t n_dark,
+                       const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                       int32_t n_rows, tp_filter_kind kind, tp_dtype storage,
+                       void* workspace, size_t workspace_bytes,
+                       float* vol, void* stream);
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* tp_last_error(void);
+/* Library version string. */
+const char* tp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TP_H */

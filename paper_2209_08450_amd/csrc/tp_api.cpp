@@ -1,0 +1,435 @@
+// Host side of libtp.so: argument validation, FP64-derived tables, plans and
+// dispatch to the HIP kernels.  Implements the C ABI declared in include/tp.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "tp_internal.h"
+
+namespace tp {
+size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_block);
+}
+
+struct tp_plan {
+    int device = -1;
+    int na = 0, n = 0, N = 0, nb = 0;
+    double center = 0.0;
+    void* dev_block = nullptr;  // one allocation holding every geometry table
+    tp::GeoTables geo{};
+    tp::FilterTables filt{};
+    int bp_k = 4;
+    int bp_a = 32;
+};
+
+namespace {
+
+constexpr const char* kVersion = "tp 0.1.0 (gfx950)";
+constexpr int kMaxPadLen = 16384;
+constexpr size_t kMaxLds = 160 * 1024;
+
+thread_local std::string g_err;
+
+tp_status fail(tp_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+tp_status hip_fail(hipError_t e, const char* what) {
+    return fail(TP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v) {
+    int r = 0;
+    while ((int64_t{1} << r) < v) ++r;
+    return r;
+}
+
+int default_pad_len(int n) { return 1 << ilog2(2 * static_cast<int64_t>(n)); }
+
+bool valid_dtype(tp_dtype d) { return d == TP_F32 || d == TP_F16 || d == TP_BF16; }
+
+size_t dtype_size(tp_dtype d) { return d == TP_F32 ? 4 : 2; }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
+
+// ---- ramp filter tables, cached per (device, L) ----
+struct FilterEntry {
+    float2* tw = nullptr;
+    float* H = nullptr;
+};
+std::mutex g_filter_mu;
+std::map<std::pair<int, int>, FilterEntry> g_filter_cache;
+
+// H[k] = sum_{m=-L/2}^{L/2-1} h[m] exp(-2 pi i k m / L) with h[0] = 1/4,
+// h[odd m] = -1/(pi^2 m^2), h[even m != 0] = 0: the DFT of the band-limited
+// ramp, real and even.  FP64 direct sum over the odd lags with an exact
+// integer phase index.
+void ramp_response_fp64(int L, std::vector<double>& H) {
+    std::vector<double> c(L);
+    for (int k = 0; k < L; ++k) c[k] = std::cos(2.0 * M_PI * static_cast<double>(k) / L);
+    H.assign(L, 0.25);
+    const double inv_pi2 = 1.0 / (M_PI * M_PI);
+    for (int m = -L / 2; m < L / 2; ++m) {
+        if ((m & 1) == 0) continue;
+        const double hm = -inv_pi2 / (static_cast<double>(m) * m);
+        const int64_t mm = ((m % L) + L) % L;
+        for (int k = 0; k < L; ++k) H[k] += hm * c[(static_cast<int64_t>(k) * mm) % L];
+    }
+}
+
+tp_status filter_tables(int L, tp::FilterTables* out, hipStream_t st_for_capture_check) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_filter_mu);
+    auto key = std::make_pair(dev, L);
+    auto it = g_filter_cache.find(key);
+    if (it == g_filter_cache.end()) {
+        if (st_for_capture_check != nullptr) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(st_for_capture_check, &cs) == hipSuccess &&
+                cs != hipStreamCaptureStatusNone)
+                return fail(TP_EUNSUPPORTED,
+                            "filter tables for pad length %d not built; call tp_filter_prepare before capture", L);
+        }
+        std::vector<double> H;
+        ramp_response_fp64(L, H);
+        std::vector<float2> tw(L);
+        std::vector<float> hf(L);
+        for (int k = 0; k < L; ++k) {
+            const double ang = -2.0 * M_PI * static_cast<double>(k) / L;
+            tw[k] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang)));
+            hf[k] = static_cast<float>(H[k] / L);
+        }
+        FilterEntry fe;
+        e = hipMalloc(&fe.tw, sizeof(float2) * L);
+        if (e != hipSuccess) return fail(TP_ENOMEM, "hipMalloc(filter twiddles): %s", hipGetErrorString(e));
+        e = hipMalloc(&fe.H, sizeof(float) * L);
+        if (e != hipSuccess) {
+            (void)hipFree(fe.tw);
+            return fail(TP_ENOMEM, "hipMalloc(filter response): %s", hipGetErrorString(e));
+        }
+        e = hipMemcpy(fe.tw, tw.data(), sizeof(float2) * L, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(fe.H, hf.data(), sizeof(float) * L, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(fe.tw);
+            (void)hipFree(fe.H);
+            return hip_fail(e, "hipMemcpy(filter tables)");
+        }
+        it = g_filter_cache.emplace(key, fe).first;
+    }
+    out->tw = it->second.tw;
+    out->H = it->second.H;
+    out->L = L;
+    out->log2L = ilog2(L);
+    return TP_OK;
+}
+
+tp_status check_raw(const uint16_t* proj, const uint16_t* dark, int32_t n_dark, const uint16_t* flat,
+                    int32_t n_flat, int64_t* proj_stride, int64_t* frame_stride, int32_t n_angles,
+                    int32_t n_rows, int32_t n_det) {
+    if (!proj || !dark || !flat) return fail(TP_EINVAL, "null raw-data pointer");
+    if (n_angles <= 0 || n_rows <= 0 || n_det <= 0)
+        return fail(TP_EINVAL, "sizes must be positive (n_angles=%d n_rows=%d n_det=%d)", n_angles, n_rows, n_det);
+    if (n_rows > 65535) return fail(TP_EINVAL, "n_rows=%d exceeds 65535 per call", n_rows);
+    if (n_dark < 1 || n_dark > 256 || n_flat < 1 || n_flat > 256)
+        return fail(TP_EINVAL, "n_dark=%d n_flat=%d must be in [1, 256]", n_dark, n_flat);
+    const int64_t slab = static_cast<int64_t>(n_rows) * n_det;
+    if (*proj_stride == 0) *proj_stride = slab;
+    if (*frame_stride == 0) *frame_stride = slab;
+    if (*proj_stride < slab) return fail(TP_EINVAL, "proj_stride %lld < n_rows*n_det", (long long)*proj_stride);
+    if (*frame_stride < slab)
+        return fail(TP_EINVAL, "frame_stride %lld < n_rows*n_det", (long long)*frame_stride);
+    return TP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tp_last_error(void) { return g_err.c_str(); }
+
+const char* tp_version(void) { return kVersion; }
+
+tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
+    if (!out) return fail(TP_EINVAL, "out is null");
+    *out = nullptr;
+    if (!g) return fail(TP_EINVAL, "geometry is null");
+    if (g->n_angles <= 0 || g->n_det <= 0 || g->n_vox < 0)
+        return fail(TP_EINVAL, "bad geometry sizes (n_angles=%d n_det=%d n_vox=%d)", g->n_angles, g->n_det,
+                    g->n_vox);
+    if (!g->angles) return fail(TP_EINVAL, "angles is null");
+    if (!std::isfinite(g->center)) return fail(TP_EINVAL, "center is not finite");
+    const int N = g->n_vox ? g->n_vox : g->n_det;
+    if (default_pad_len(g->n_det) > kMaxPadLen)
+        return fail(TP_EUNSUPPORTED, "n_det=%d needs pad length > %d", g->n_det, kMaxPadLen);
+    if (N > 32768) return fail(TP_EUNSUPPORTED, "n_vox=%d too large", N);
+    for (int a = 0; a < g->n_angles; ++a)
+        if (!std::isfinite(g->angles[a])) return fail(TP_EINVAL, "angle %d is not finite", a);
+    // the detector coordinate must stay well inside int32 and the FP32 offset small
+    if (std::fabs(g->center) > 1e6) return fail(TP_EINVAL, "center %g out of range", g->center);
+
+    const int na = g->n_angles;
+    const int nb = (N + tp::kGeoTile - 1) / tp::kGeoTile;
+    const int half = N / 2;
+    std::vector<float> cs(na), sn(na), xf(static_cast<size_t>(nb) * na), yf(static_cast<size_t>(nb) * na);
+    std::vector<int> xi(static_cast<size_t>(nb) * na), yi(static_cast<size_t>(nb) * na);
+    for (int a = 0; a < na; ++a) {
+        const double c = std::cos(g->angles[a]), s = std::sin(g->angles[a]);
+        cs[a] = static_cast<float>(c);
+        sn[a] = static_cast<float>(s);
+        for (int b = 0; b < nb; ++b) {
+            const double o = static_cast<double>(b * tp::kGeoTile - half);
+            const double X = o * c;
+            const double Y = o * s + g->center;
+            const double fx = std::floor(X), fy = std::floor(Y);
+            xi[static_cast<size_t>(b) * na + a] = static_cast<int>(fx);
+            xf[static_cast<size_t>(b) * na + a] = static_cast<float>(X - fx);
+            yi[static_cast<size_t>(b) * na + a] = static_cast<int>(fy);
+            yf[static_cast<size_t>(b) * na + a] = static_cast<float>(Y - fy);
+        }
+    }
+    const size_t s_ang = align256(sizeof(float) * na);
+    const size_t s_tab = align256(sizeof(float) * static_cast<size_t>(nb) * na);
+    const size_t total = 2 * s_ang + 4 * s_tab;
+
+    tp_plan* p = new (std::nothrow) tp_plan();
+    if (!p) return fail(TP_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    e = hipMalloc(&p->dev_block, total);
+    if (e != hipSuccess) {
+        delete p;
+        return fail(TP_ENOMEM, "hipMalloc(plan tables, %zu bytes): %s", total, hipGetErrorString(e));
+    }
+    char* base = static_cast<char*>(p->dev_block);
+    char* d_cs = base;
+    char* d_sn = d_cs + s_ang;
+    char* d_xi = d_sn + s_ang;
+    char* d_xf = d_xi + s_tab;
+    char* d_yi = d_xf + s_tab;
+    char* d_yf = d_yi + s_tab;
+    const size_t tb = sizeof(float) * static_cast<size_t>(nb) * na;
+    e = hipMemcpy(d_cs, cs.data(), sizeof(float) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_sn, sn.data(), sizeof(float) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_xi, xi.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_xf, xf.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_yi, yi.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_yf, yf.data(), tb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p->dev_block);
+        delete p;
+        return hip_fail(e, "hipMemcpy(plan tables)");
+    }
+    p->na = na;
+    p->n = g->n_det;
+    p->N = N;
+    p->nb = nb;
+    p->center = g->center;
+    p->geo.cs = reinterpret_cast<const float*>(d_cs);
+    p->geo.sn = reinterpret_cast<const float*>(d_sn);
+    p->geo.xi = reinterpret_cast<const int*>(d_xi);
+    p->geo.xf = reinterpret_cast<const float*>(d_xf);
+    p->geo.yi = reinterpret_cast<const int*>(d_yi);
+    p->geo.yf = reinterpret_cast<const float*>(d_yf);
+    p->geo.na = na;
+    p->geo.n = g->n_det;
+    p->geo.N = N;
+    p->geo.nb = nb;
+    p->geo.center_f = static_cast<float>(g->center);
+    tp_status st = filter_tables(default_pad_len(g->n_det), &p->filt, nullptr);
+    if (st != TP_OK) {
+        (void)hipFree(p->dev_block);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return TP_OK;
+}
+
+tp_status tp_plan_destroy(tp_plan* plan) {
+    if (!plan) return TP_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != plan->device) (void)hipSetDevice(plan->device);
+    hipError_t e = hipFree(plan->dev_block);
+    if (cur != plan->device) (void)hipSetDevice(cur);
+    delete plan;
+    if (e != hipSuccess) return hip_fail(e, "hipFree(plan tables)");
+    return TP_OK;
+}
+
+tp_status tp_plan_set_tuning(tp_plan* plan, int32_t slices_per_block, int32_t angles_per_block) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    const int k = slices_per_block, a = angles_per_block;
+    if (!(k == 1 || k == 2 || k == 4 || k == 8))
+        return fail(TP_EINVAL, "slices_per_block=%d not in {1,2,4,8}", k);
+    if (!(a == 8 || a == 16 || a == 32 || a == 64))
+        return fail(TP_EINVAL, "angles_per_block=%d not in {8,16,32,64}", a);
+    if (tp::backproject_lds_bytes(TP_F32, k, a) > kMaxLds)
+        return fail(TP_EINVAL, "slices_per_block=%d x angles_per_block=%d exceeds LDS", k, a);
+    plan->bp_k = k;
+    plan->bp_a = a;
+    return TP_OK;
+}
+
+tp_status tp_plan_get_tuning(const tp_plan* plan, int32_t* slices_per_block, int32_t* angles_per_block) {
+    if (!plan || !slices_per_block || !angles_per_block) return fail(TP_EINVAL, "null argument");
+    *slices_per_block = plan->bp_k;
+    *angles_per_block = plan->bp_a;
+    return TP_OK;
+}
+
+tp_status tp_filter_prepare(int32_t pad_len, tp_filter_kind kind) {
+    if (kind != TP_RAMP) return fail(TP_EUNSUPPORTED, "only the ramp filter is implemented");
+    if (!is_pow2(pad_len) || pad_len < 2 || pad_len > kMaxPadLen)
+        return fail(TP_EINVAL, "pad_len=%d must be a power of two in [2, %d]", pad_len, kMaxPadLen);
+    tp::FilterTables ft;
+    return filter_tables(pad_len, &ft, nullptr);
+}
+
+size_t tp_normalize_workspace_bytes(int32_t n_rows, int32_t n_det) {
+    if (n_rows <= 0 || n_det <= 0) return 0;
+    return 2 * align256(sizeof(float) * static_cast<size_t>(n_rows) * n_det);
+}
+
+tp_status tp_normalize(const uint16_t* proj, int64_t proj_stride, const uint16_t* dark, int32_t n_dark,
+                       const uint16_t* flat, int32_t n_flat, int64_t frame_stride, int32_t n_angles,
+                       int32_t n_rows, int32_t n_det, tp_dtype out_dtype, void* sino, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+    tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, n_angles, n_rows,
+                            n_det);
+    if (s != TP_OK) return s;
+    if (!valid_dtype(out_dtype)) return fail(TP_EINVAL, "bad out_dtype %d", out_dtype);
+    if (!sino) return fail(TP_EINVAL, "sino is null");
+    if (!workspace) return fail(TP_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(TP_EINVAL, "workspace not 256-byte aligned");
+    const size_t need = tp_normalize_workspace_bytes(n_rows, n_det);
+    if (workspace_bytes < need) return fail(TP_EINVAL, "workspace %zu < %zu bytes", workspace_bytes, need);
+    auto st = static_cast<hipStream_t>(stream);
+    float* dmean = static_cast<float*>(workspace);
+    float* den = reinterpret_cast<float*>(static_cast<char*>(workspace) + need / 2);
+    tp::RawInput in{proj, proj_stride, dark, flat, frame_stride, n_dark, n_flat};
+    hipError_t e = tp::launch_darkflat(in, n_rows, n_det, dmean, den, st);
+    if (e != hipSuccess) return hip_fail(e, "darkflat launch");
+    e = tp::launch_normalize(in, dmean, den, n_angles, n_rows, n_det, out_dtype, sino, st);
+    if (e != hipSuccess) return hip_fail(e, "normalize launch");
+    return TP_OK;
+}
+
+tp_status tp_filter(const void* sino, tp_dtype in_dtype, void* filt, tp_dtype out_dtype, int64_t n_lines,
+                    int32_t n_det, int32_t pad_len, tp_filter_kind kind, void* stream) {
+    if (kind != TP_RAMP) return fail(TP_EUNSUPPORTED, "only the ramp filter is implemented");
+    if (!sino || !filt) return fail(TP_EINVAL, "null buffer");
+    if (!valid_dtype(in_dtype) || !valid_dtype(out_dtype)) return fail(TP_EINVAL, "bad dtype");
+    if (n_lines <= 0 || n_det <= 0) return fail(TP_EINVAL, "n_lines and n_det must be positive");
+    if ((n_lines + 1) / 2 > 0x7fffffffLL) return fail(TP_EINVAL, "n_lines too large");
+    const int L = pad_len == 0 ? default_pad_len(n_det) : pad_len;
+    if (!is_pow2(L) || L < n_det || L > kMaxPadLen)
+        return fail(pad_len == 0 ? TP_EUNSUPPORTED : TP_EINVAL,
+                    "pad_len=%d must be a power of two with n_det <= pad_len <= %d", L, kMaxPadLen);
+    const size_t in_bytes = static_cast<size_t>(n_lines) * n_det * dtype_size(in_dtype);
+    const size_t out_bytes = static_cast<size_t>(n_lines) * n_det * dtype_size(out_dtype);
+    const char* a0 = static_cast<const char*>(sino);
+    const char* b0 = static_cast<const char*>(filt);
+    const bool overlap = a0 < b0 + out_bytes && b0 < a0 + in_bytes;
+    if (overlap && !(a0 == b0 && in_dtype == out_dtype))
+        return fail(TP_EINVAL, "filt overlaps sino (in place only with identical pointers and dtypes)");
+    auto st = static_cast<hipStream_t>(stream);
+    tp::FilterTables ft;
+    tp_status s = filter_tables(L, &ft, st);
+    if (s != TP_OK) return s;
+    hipError_t e = tp::launch_filter(sino, in_dtype, filt, out_dtype, n_lines, n_det, ft, st);
+    if (e != hipSuccess) return hip_fail(e, "filter launch");
+    return TP_OK;
+}
+
+tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtype, int32_t n_rows, float scale,
+                         float* vol, int32_t accumulate, void* stream) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (!filt || !vol) return fail(TP_EINVAL, "null buffer");
+    if (!valid_dtype(in_dtype)) return fail(TP_EINVAL, "bad dtype %d", in_dtype);
+    if (n_rows <= 0 || n_rows > 65535 * 8) return fail(TP_EINVAL, "n_rows=%d out of range", n_rows);
+    if (!(accumulate == 0 || accumulate == 1)) return fail(TP_EINVAL, "accumulate must be 0 or 1");
+    if (!std::isfinite(scale)) return fail(TP_EINVAL, "scale is not finite");
+    if ((n_rows + plan->bp_k - 1) / plan->bp_k > 65535)
+        return fail(TP_EINVAL, "n_rows=%d too large for slices_per_block=%d", n_rows, plan->bp_k);
+    if (tp::backproject_lds_bytes(in_dtype, plan->bp_k, plan->bp_a) > kMaxLds)
+        return fail(TP_EINVAL, "tuning exceeds LDS");
+    hipError_t e = tp::launch_backproject(plan->geo, filt, in_dtype, n_rows, scale, vol, accumulate, plan->bp_k,
+                                          plan->bp_a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "backproject launch");
+    return TP_OK;
+}
+
+tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float* sino, void* stream) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (!vol || !sino) return fail(TP_EINVAL, "null buffer");
+    if (n_rows <= 0 || (n_rows + 3) / 4 > 65535) return fail(TP_EINVAL, "n_rows=%d out of range", n_rows);
+    hipError_t e = tp::launch_radon(plan->geo, vol, n_rows, sino, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "radon launch");
+    return TP_OK;
+}
+
+size_t tp_fbp_workspace_bytes(const tp_plan* plan, int32_t n_rows, tp_dtype storage) {
+    if (!plan || n_rows <= 0 || !valid_dtype(storage)) return 0;
+    return tp_normalize_workspace_bytes(n_rows, plan->n) +
+           align256(static_cast<size_t>(n_rows) * plan->na * plan->n * dtype_size(storage));
+}
+
+tp_status tp_fbp_chunk(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride, const uint16_t* dark,
+                       int32_t n_dark, const uint16_t* flat, int32_t n_flat, int64_t frame_stride, int32_t n_rows,
+                       tp_filter_kind kind, tp_dtype storage, void* workspace, size_t workspace_bytes, float* vol,
+                       void* stream) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, plan->na, n_rows,
+                            plan->n);
+    if (s != TP_OK) return s;
+    if (kind != TP_RAMP) return fail(TP_EUNSUPPORTED, "only the ramp filter is implemented");
+    if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
+    if (!vol) return fail(TP_EINVAL, "vol is null");
+    if (!workspace) return fail(TP_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(TP_EINVAL, "workspace not 256-byte aligned");
+    const size_t need = tp_fbp_workspace_bytes(plan, n_rows, storage);
+    if (workspace_bytes < need) return fail(TP_EINVAL, "workspace %zu < %zu bytes", workspace_bytes, need);
+    if ((n_rows + plan->bp_k - 1) / plan->bp_k > 65535)
+        return fail(TP_EINVAL, "n_rows=%d too large for slices_per_block=%d", n_rows, plan->bp_k);
+    if (static_cast<int64_t>(n_rows) * ((plan->na + 1) / 2) > 0x7fffffffLL)
+        return fail(TP_EINVAL, "n_rows=%d x n_angles=%d too large for one call", n_rows, plan->na);
+    if (tp::backproject_lds_bytes(storage, plan->bp_k, plan->bp_a) > kMaxLds)
+        return fail(TP_EINVAL, "tuning exceeds LDS");
+    auto st = static_cast<hipStream_t>(stream);
+    const size_t dfb = tp_normalize_workspace_bytes(n_rows, plan->n);
+    float* dmean = static_cast<float*>(workspace);
+    float* den = reinterpret_cast<float*>(static_cast<char*>(workspace) + dfb / 2);
+    void* filt = static_cast<char*>(workspace) + dfb;
+    tp::RawInput in{proj, proj_stride, dark, flat, frame_stride, n_dark, n_flat};
+    hipError_t e = tp::launch_darkflat(in, n_rows, plan->n, dmean, den, st);
+    if (e != hipSuccess) return hip_fail(e, "darkflat launch");
+    e = tp::launch_norm_filter(in, dmean, den, plan->na, n_rows, plan->n, plan->filt, storage, filt, st);
+    if (e != hipSuccess) return hip_fail(e, "norm_filter launch");
+    e = tp::launch_backproject(plan->geo, filt, storage, n_rows, static_cast<float>(M_PI / plan->na), vol, 0,
+                               plan->bp_k, plan->bp_a, st);
+    if (e != hipSuccess) return hip_fail(e, "backproject launch");
+    return TP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Internal declarations shared by the HIP translation units of libtp.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "../../include/tp.h"
+
+namespace tp {
+
+// Edge of the square voxel tiles whose origins carry the FP64-derived
+// detector coordinate (integer + FP32 fraction).  Shared by the
+// backprojector and the forward projector so both take identical
+// floor/weight decisions.
+constexpr int kGeoTile = 32;
+// Detector window staged per (tile, angle): a 32x32 tile spans at most
+// 31*sqrt(2) < 44 columns, so floor() takes at most 45 values and the two
+// taps at most 46 bins.
+constexpr int kWin = 48;
+// Threads of the backprojection work-group (4 waves, 8x8 voxels per wave step).
+constexpr int kBpThreads = 256;
+
+struct GeoTables {
+    const float* cs;   // [na]      FP32 cos(theta)
+    const float* sn;   // [na]      FP32 sin(theta)
+    const int* xi;     // [nb][na]  floor((bx*32 - N/2) cos)
+    const float* xf;   // [nb][na]  fraction of the same, FP32
+    const int* yi;     // [nb][na]  floor((by*32 - N/2) sin + center)
+    const float* yf;   // [nb][na]
+    int na, n, N, nb;
+    float center_f;    // FP32 rotation axis (only for candidate search in the forward projector)
+};
+
+struct FilterTables {
+    const float2* tw;  // [L]  exp(-2 pi i k / L)
+    const float* H;    // [L]  H[k] / L (ramp response, inverse-FFT scale folded in)
+    int L, log2L;
+};
+
+// Raw-count inputs of the normalisation (dev pointers, element strides).
+struct RawInput {
+    const uint16_t* proj;
+    int64_t proj_stride;   // elements between consecutive projections
+    const uint16_t* dark;
+    const uint16_t* flat;
+    int64_t frame_stride;  // elements between consecutive dark/flat frames
+    int n_dark, n_flat;
+};
+
+// ---- launchers (each returns hipError_t of the launch) ----
+hipError_t launch_darkflat(const RawInput& in, int n_rows, int n_det, float* dmean, float* den,
+                           hipStream_t st);
+hipError_t launch_normalize(const RawInput& in, const float* dmean, const float* den, int n_angles,
+                            int n_rows, int n_det, tp_dtype out_dtype, void* sino, hipStream_t st);
+hipError_t launch_filter(const void* in, tp_dtype in_dt, void* out, tp_dtype out_dt, int64_t n_lines,
+                         int n_det, const FilterTables& ft, hipStream_t st);
+hipError_t launch_norm_filter(const RawInput& in, const float* dmean, const float* den, int n_angles,
+                              int n_rows, int n_det, const FilterTables& ft, tp_dtype out_dt, void* out,
+                              hipStream_t st);
+hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt, int n_rows, float scale,
+                              float* vol, int accumulate, int slices_per_block, int angles_per_block,
+                              hipStream_t st);
+hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st);
+
+// ---- storage conversions (round to nearest even) ----
+__device__ __forceinline__ float load_as_float(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float load_as_float(const __half* p, int64_t i) { return __half2float(p[i]); }
+__device__ __forceinline__ float load_as_float(const uint16_t* p, int64_t i) {  // bfloat16 bits
+    return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
+}
+__device__ __forceinline__ void store_from_float(float* p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void store_from_float(__half* p, int64_t i, float v) { p[i] = __float2half_rn(v); }
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) {
+    uint32_t b = __float_as_uint(v);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((b >> 16) | 0x40u);  // quiet NaN
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return static_cast<uint16_t>(b >> 16);
+}
+__device__ __forceinline__ void store_from_float(uint16_t* p, int64_t i, float v) { p[i] = f32_to_bf16_rne(v); }
+
+}  // namespace tp

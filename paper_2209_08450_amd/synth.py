@@ -252,7 +252,9 @@ def ellipsoid_scan_torch(seed: int, n_angles: int, n_rows: int, n_det: int, devi
     For paper-scale scans (e.g. 2048 angles x 2048 rows x 2048 columns).  The
     noise comes from torch's generator seeded with (seed, batch); it is not the
     numpy stream, so checks against the oracle copy the needed raw rows back to
-    the host.  ``out`` may supply a preallocated uint16 [n_angles][n_rows][n_det].
+    the host.  Device containers are int16 tensors holding the uint16 bit
+    patterns (view them as uint16 on the host).  ``out`` may supply a
+    preallocated int16 [n_angles][n_rows][n_det].
     """
     import torch
 
@@ -260,7 +262,7 @@ def ellipsoid_scan_torch(seed: int, n_angles: int, n_rows: int, n_det: int, devi
     half = n_det / 2
     ell = ellipsoids_3d(seed, n_ellipsoids)
     ang = uniform_angles(n_angles)
-    proj = out if out is not None else torch.empty((n_angles, n_rows, n_det), dtype=torch.uint16,
+    proj = out if out is not None else torch.empty((n_angles, n_rows, n_det), dtype=torch.int16,
                                                    device=device)
     gen = torch.Generator(device=device)
     for b, z0 in enumerate(range(0, n_rows, rows_per_batch)):
@@ -270,17 +272,17 @@ def ellipsoid_scan_torch(seed: int, n_angles: int, n_rows: int, n_det: int, devi
         lam = flat_level * torch.exp(-p)
         v = torch.poisson(lam, generator=gen)
         v += torch.poisson(torch.full_like(v, dark_level), generator=gen)
-        v = torch.clamp(v, 0, max_count).to(torch.int32).to(torch.uint16)
+        v = torch.clamp(v, 0, max_count).to(torch.int32).to(torch.int16)
         proj[:, z0:z1, :] = v.permute(1, 0, 2)
         del p, lam, v
         if progress is not None:
             progress(z1, n_rows)
     gen.manual_seed(int(np.random.SeedSequence([seed, 2]).generate_state(1)[0]))
     dk = torch.poisson(torch.full((n_dark, n_rows, n_det), dark_level, device=device), generator=gen)
-    dark = torch.clamp(dk, 0, max_count).to(torch.int32).to(torch.uint16)
+    dark = torch.clamp(dk, 0, max_count).to(torch.int32).to(torch.int16)
     fl = torch.poisson(torch.full((n_flat, n_rows, n_det), flat_level, device=device), generator=gen)
     fl += torch.poisson(torch.full_like(fl, dark_level), generator=gen)
-    flat = torch.clamp(fl, 0, max_count).to(torch.int32).to(torch.uint16)
+    flat = torch.clamp(fl, 0, max_count).to(torch.int32).to(torch.int16)
     return ScanData(proj, dark, flat, ang, float(center), n_det)
 
 

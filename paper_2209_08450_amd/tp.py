@@ -1,0 +1,291 @@
+"""ctypes binding of libtp.so (C ABI in include/tp.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current HIP device; work is
+enqueued on ``torch.cuda.current_stream()`` unless a stream is given.  A
+negative status raises ``TpError`` with the library's message.  There is no
+fallback: if libtp.so is missing this module fails to import.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import sys
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("TP_LIBRARY", os.path.join(_HERE, "libtp.so"))
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libtp.so not found at {LIB_PATH}; build it with "
+                      f"`python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TP_OK, TP_EINVAL, TP_EUNSUPPORTED, TP_EHIP, TP_ENOMEM = 0, -1, -2, -3, -4
+TP_F32, TP_F16, TP_BF16 = 0, 1, 2
+TP_RAMP, TP_SHEPP, TP_PARZEN = 0, 1, 2
+
+_c_i32, _c_i64, _c_sz, _c_vp, _c_f, _c_d = (ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
+                                            ctypes.c_void_p, ctypes.c_float, ctypes.c_double)
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_angles", ctypes.c_int32), ("n_det", ctypes.c_int32), ("n_vox", ctypes.c_int32),
+                ("center", ctypes.c_double), ("angles", ctypes.POINTER(ctypes.c_double))]
+
+
+def _proto(name, restype, *args):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(args)
+    return f
+
+
+_plan_create = _proto("tp_plan_create", _c_i32, ctypes.POINTER(Geometry), ctypes.POINTER(_c_vp))
+_plan_destroy = _proto("tp_plan_destroy", _c_i32, _c_vp)
+_plan_set_tuning = _proto("tp_plan_set_tuning", _c_i32, _c_vp, _c_i32, _c_i32)
+_plan_get_tuning = _proto("tp_plan_get_tuning", _c_i32, _c_vp, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32))
+_filter_prepare = _proto("tp_filter_prepare", _c_i32, _c_i32, _c_i32)
+_normalize_ws = _proto("tp_normalize_workspace_bytes", _c_sz, _c_i32, _c_i32)
+_normalize = _proto("tp_normalize", _c_i32, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32,
+                    _c_i32, _c_i32, _c_vp, _c_vp, _c_sz, _c_vp)
+_filter = _proto("tp_filter", _c_i32, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp)
+_backproject = _proto("tp_backproject", _c_i32, _c_vp, _c_vp, _c_i32, _c_i32, _c_f, _c_vp, _c_i32, _c_vp)
+_radon = _proto("tp_radon", _c_i32, _c_vp, _c_vp, _c_i32, _c_vp, _c_vp)
+_fbp_ws = _proto("tp_fbp_workspace_bytes", _c_sz, _c_vp, _c_i32, _c_i32)
+_fbp_chunk = _proto("tp_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32,
+                    _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp)
+_last_error = _proto("tp_last_error", ctypes.c_char_p)
+_version = _proto("tp_version", ctypes.c_char_p)
+
+
+class TpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"tp status {status}: {message}")
+        self.status = status
+
+
+def last_error() -> str:
+    return _last_error().decode()
+
+
+def version() -> str:
+    return _version().decode()
+
+
+def _check(status: int):
+    if status != TP_OK:
+        raise TpError(status, last_error())
+
+
+def raw_function(name: str):
+    """The exported C function ``name`` (for ABI tests)."""
+    return getattr(_lib, name)
+
+
+# ---------------------------------------------------------------------------
+# torch helpers (torch provides device memory and streams only)
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(dt) -> int:
+    torch = _torch()
+    if dt in (torch.float32, "f32", TP_F32):
+        return TP_F32
+    if dt in (torch.float16, "f16", TP_F16):
+        return TP_F16
+    if dt in (torch.bfloat16, "bf16", TP_BF16):
+        return TP_BF16
+    raise ValueError(f"unsupported storage dtype {dt!r}")
+
+
+def torch_dtype(code: int):
+    torch = _torch()
+    return {TP_F32: torch.float32, TP_F16: torch.float16, TP_BF16: torch.bfloat16}[code]
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _raw_strides(t, name, n_det):
+    """(pointer, outer stride) of a [outer][rows][n_det] uint16 view with packed rows."""
+    torch = _torch()
+    if t.dtype not in (torch.uint16, torch.int16):
+        raise ValueError(f"{name} must be uint16 raw counts")
+    if t.dim() != 3 or t.shape[2] != n_det or t.stride(2) != 1 or (t.shape[1] > 1 and t.stride(1) != n_det):
+        raise ValueError(f"{name} must be [k][rows][n_det] with contiguous rows")
+    return _dev(t, name), int(t.stride(0))
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+# Plans
+# ---------------------------------------------------------------------------
+class Plan:
+    """Geometry tables on the current device (tp_plan_create)."""
+
+    def __init__(self, angles, n_det: int, center: float, n_vox: int = 0):
+        self.angles = np.ascontiguousarray(angles, dtype=np.float64)
+        self.n_angles = int(self.angles.shape[0])
+        self.n_det = int(n_det)
+        self.n_vox = int(n_vox) if n_vox else int(n_det)
+        self.center = float(center)
+        g = Geometry(self.n_angles, self.n_det, int(n_vox), self.center,
+                     self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = _c_vp()
+        _check(_plan_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_tuning(self, slices_per_block: int, angles_per_block: int):
+        _check(_plan_set_tuning(self._h, int(slices_per_block), int(angles_per_block)))
+
+    def get_tuning(self):
+        k, a = _c_i32(), _c_i32()
+        _check(_plan_get_tuning(self._h, ctypes.byref(k), ctypes.byref(a)))
+        return int(k.value), int(a.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_plan_destroy(self._h))
+            self._h = _c_vp()
+
+    def __del__(self):
+        if sys.is_finalizing():  # the HIP runtime may already be gone
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fbp_workspace_bytes(self, n_rows: int, storage) -> int:
+        return int(_fbp_ws(self._h, int(n_rows), dtype_code(storage)))
+
+
+def filter_prepare(pad_len: int, kind: int = TP_RAMP):
+    _check(_filter_prepare(int(pad_len), int(kind)))
+
+
+def pad_len(n_det: int) -> int:
+    return 1 << int(math.ceil(math.log2(2 * n_det)))
+
+
+# ---------------------------------------------------------------------------
+# Hot-path calls
+# ---------------------------------------------------------------------------
+def normalize(proj, dark, flat, out_dtype="f32", out=None, workspace=None, stream=None):
+    """Raw uint16 [n_angles][rows][n_det] -> -log sinogram [rows][n_angles][n_det]."""
+    torch = _torch()
+    n_angles, n_rows, n_det = (int(s) for s in proj.shape)
+    pp, ps = _raw_strides(proj, "proj", n_det)
+    dp, fs = _raw_strides(dark, "dark", n_det)
+    fp, fs2 = _raw_strides(flat, "flat", n_det)
+    if fs != fs2:
+        raise ValueError("dark and flat must share one frame stride")
+    if dark.shape[1] != n_rows or flat.shape[1] != n_rows:
+        raise ValueError("dark/flat rows must match proj rows")
+    code = dtype_code(out_dtype)
+    if out is None:
+        out = torch.empty((n_rows, n_angles, n_det), dtype=torch_dtype(code), device=proj.device)
+    ws_need = int(_normalize_ws(n_rows, n_det))
+    if workspace is None:
+        workspace = _workspace(ws_need, proj.device)
+    _check(_normalize(pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_angles, n_rows, n_det, code,
+                      _dev(out, "out"), _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                      _stream_ptr(stream)))
+    return out
+
+
+def filter(sino, out_dtype=None, out=None, pad_len: int = 0, kind: int = TP_RAMP, stream=None):
+    """Ramp-filter every row of ``sino`` [..., n_det]; returns the filtered rows."""
+    torch = _torch()
+    if not sino.is_contiguous():
+        raise ValueError("sino must be contiguous")
+    in_code = dtype_code(sino.dtype)
+    out_code = in_code if out_dtype is None else dtype_code(out_dtype)
+    n_det = int(sino.shape[-1])
+    n_lines = int(sino.numel() // n_det)
+    if out is None:
+        out = torch.empty(sino.shape, dtype=torch_dtype(out_code), device=sino.device)
+    _check(_filter(_dev(sino, "sino"), in_code, _dev(out, "out"), out_code, n_lines, n_det, int(pad_len), int(kind),
+                   _stream_ptr(stream)))
+    return out
+
+
+def backproject(plan: Plan, filt, scale=None, out=None, accumulate: bool = False, stream=None):
+    """Filtered rows [rows][n_angles][n_det] -> volume [rows][N][N] (float32)."""
+    torch = _torch()
+    if filt.dim() != 3 or tuple(filt.shape[1:]) != (plan.n_angles, plan.n_det) or not filt.is_contiguous():
+        raise ValueError(f"filt must be contiguous [rows][{plan.n_angles}][{plan.n_det}]")
+    n_rows = int(filt.shape[0])
+    if scale is None:
+        scale = math.pi / plan.n_angles
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs out")
+        out = torch.empty((n_rows, plan.n_vox, plan.n_vox), dtype=torch.float32, device=filt.device)
+    if out.dtype != torch.float32 or not out.is_contiguous() or tuple(out.shape) != (n_rows, plan.n_vox, plan.n_vox):
+        raise ValueError("out must be contiguous float32 [rows][N][N]")
+    _check(_backproject(plan.handle, _dev(filt, "filt"), dtype_code(filt.dtype), n_rows, float(scale),
+                        _dev(out, "out"), 1 if accumulate else 0, _stream_ptr(stream)))
+    return out
+
+
+def radon(plan: Plan, vol, out=None, stream=None):
+    """Volume [rows][N][N] float32 -> projections [rows][n_angles][n_det] float32."""
+    torch = _torch()
+    if vol.dtype != torch.float32 or vol.dim() != 3 or tuple(vol.shape[1:]) != (plan.n_vox, plan.n_vox) \
+            or not vol.is_contiguous():
+        raise ValueError(f"vol must be contiguous float32 [rows][{plan.n_vox}][{plan.n_vox}]")
+    n_rows = int(vol.shape[0])
+    if out is None:
+        out = torch.empty((n_rows, plan.n_angles, plan.n_det), dtype=torch.float32, device=vol.device)
+    _check(_radon(plan.handle, _dev(vol, "vol"), n_rows, _dev(out, "out"), _stream_ptr(stream)))
+    return out
+
+
+def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=None, stream=None):
+    """Raw counts of a row chunk -> reconstructed slices [rows][N][N] (float32)."""
+    torch = _torch()
+    n_angles, n_rows, n_det = (int(s) for s in proj.shape)
+    if n_angles != plan.n_angles or n_det != plan.n_det:
+        raise ValueError("proj does not match the plan geometry")
+    pp, ps = _raw_strides(proj, "proj", n_det)
+    dp, fs = _raw_strides(dark, "dark", n_det)
+    fp, fs2 = _raw_strides(flat, "flat", n_det)
+    if fs != fs2:
+        raise ValueError("dark and flat must share one frame stride")
+    if dark.shape[1] != n_rows or flat.shape[1] != n_rows:
+        raise ValueError("dark/flat rows must match proj rows")
+    code = dtype_code(storage)
+    need = plan.fbp_workspace_bytes(n_rows, code)
+    if workspace is None:
+        workspace = _workspace(need, proj.device)
+    if out is None:
+        out = torch.empty((n_rows, plan.n_vox, plan.n_vox), dtype=torch.float32, device=proj.device)
+    _check(_fbp_chunk(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, TP_RAMP,
+                      code, _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                      _dev(out, "out"), _stream_ptr(stream)))
+    return out

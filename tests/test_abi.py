@@ -1,0 +1,113 @@
+"""The C ABI: the library loads, exports every declared symbol, and rejects bad
+arguments on the host (status + message, nothing enqueued).  No GPU needed:
+every call here fails validation before touching the HIP runtime."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tp.h")
+
+
+@pytest.fixture(scope="module")
+def tp():
+    from paper_2209_08450_amd import tp as mod
+    return mod
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_hot_path_calls():
+    names = declared_functions()
+    for n in ["tp_normalize", "tp_filter", "tp_backproject", "tp_radon", "tp_fbp_chunk"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(tp):
+    lib = ctypes.CDLL(tp.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version(tp):
+    assert "gfx950" in tp.version()
+
+
+def test_null_and_size_errors(tp):
+    nul = ctypes.c_void_p()
+    st = tp._filter(nul, tp.TP_F32, nul, tp.TP_F32, 4, 16, 0, tp.TP_RAMP, nul)
+    assert st == tp.TP_EINVAL and "null" in tp.last_error()
+    dummy = ctypes.c_void_p(0x100000)
+    st = tp._filter(dummy, tp.TP_F32, ctypes.c_void_p(0x900000), tp.TP_F32, 0, 16, 0, tp.TP_RAMP, nul)
+    assert st == tp.TP_EINVAL and "positive" in tp.last_error()
+    st = tp._filter(dummy, tp.TP_F32, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 24, tp.TP_RAMP, nul)
+    assert st == tp.TP_EINVAL and "power of two" in tp.last_error()
+    st = tp._filter(dummy, tp.TP_F32, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 8, tp.TP_RAMP, nul)
+    assert st == tp.TP_EINVAL  # pad shorter than the row
+    st = tp._filter(dummy, tp.TP_F32, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 0, tp.TP_PARZEN, nul)
+    assert st == tp.TP_EUNSUPPORTED
+    st = tp._filter(dummy, 7, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 0, tp.TP_RAMP, nul)
+    assert st == tp.TP_EINVAL and "dtype" in tp.last_error()
+
+
+def test_filter_alias_rules(tp):
+    nul = ctypes.c_void_p()
+    a = ctypes.c_void_p(0x100000)
+    # partial overlap is rejected, and so is in-place with different dtypes
+    st = tp._filter(a, tp.TP_F32, ctypes.c_void_p(0x100000 + 32), tp.TP_F32, 4, 16, 0, tp.TP_RAMP, nul)
+    assert st == tp.TP_EINVAL and "overlap" in tp.last_error()
+    st = tp._filter(a, tp.TP_F32, a, tp.TP_F16, 4, 16, 0, tp.TP_RAMP, nul)
+    assert st == tp.TP_EINVAL and "overlap" in tp.last_error()
+
+
+def test_plan_validation(tp):
+    ang = np.zeros(4)
+    g = tp.Geometry(4, 16, 0, 8.0, None)
+    h = ctypes.c_void_p()
+    assert tp._plan_create(ctypes.byref(g), ctypes.byref(h)) == tp.TP_EINVAL
+    assert "angles" in tp.last_error()
+    g = tp.Geometry(0, 16, 0, 8.0, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert tp._plan_create(ctypes.byref(g), ctypes.byref(h)) == tp.TP_EINVAL
+    g = tp.Geometry(4, 16, 0, float("nan"), ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert tp._plan_create(ctypes.byref(g), ctypes.byref(h)) == tp.TP_EINVAL
+    bad = np.array([0.0, np.inf, 1.0, 2.0])
+    g = tp.Geometry(4, 16, 0, 8.0, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert tp._plan_create(ctypes.byref(g), ctypes.byref(h)) == tp.TP_EINVAL
+    g = tp.Geometry(4, 9000, 0, 8.0, ang.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert tp._plan_create(ctypes.byref(g), ctypes.byref(h)) == tp.TP_EUNSUPPORTED
+
+
+def test_plan_null_handles(tp):
+    nul = ctypes.c_void_p()
+    assert tp._plan_set_tuning(nul, 4, 32) == tp.TP_EINVAL
+    assert tp._backproject(nul, nul, 0, 1, 1.0, nul, 0, nul) == tp.TP_EINVAL
+    assert tp._radon(nul, nul, 1, nul, nul) == tp.TP_EINVAL
+    assert tp._plan_destroy(nul) == tp.TP_OK
+
+
+def test_filter_prepare_validation(tp):
+    assert tp._filter_prepare(3, tp.TP_RAMP) == tp.TP_EINVAL
+    assert tp._filter_prepare(32768, tp.TP_RAMP) == tp.TP_EINVAL
+    assert tp._filter_prepare(64, tp.TP_SHEPP) == tp.TP_EUNSUPPORTED
+
+
+def test_normalize_validation(tp):
+    nul = ctypes.c_void_p()
+    p = ctypes.c_void_p(0x100000)
+    assert tp._normalize(nul, 0, p, 1, p, 1, 0, 4, 2, 8, 0, p, p, 1 << 20, nul) == tp.TP_EINVAL
+    assert tp._normalize(p, 0, p, 0, p, 1, 0, 4, 2, 8, 0, p, p, 1 << 20, nul) == tp.TP_EINVAL
+    assert tp._normalize(p, 0, p, 1, p, 300, 0, 4, 2, 8, 0, p, p, 1 << 20, nul) == tp.TP_EINVAL
+    assert tp._normalize(p, 8, p, 1, p, 1, 0, 4, 2, 8, 0, p, p, 1 << 20, nul) == tp.TP_EINVAL  # stride < rows*n
+    assert tp._normalize(p, 0, p, 1, p, 1, 0, 4, 2, 8, 0, p, p, 16, nul) == tp.TP_EINVAL  # workspace too small
+    assert tp._normalize(p, 0, p, 1, p, 1, 0, 4, 2, 8, 0, p, ctypes.c_void_p(0x100010), 1 << 20,
+                         nul) == tp.TP_EINVAL  # misaligned workspace
+    assert tp._normalize(p, 0, p, 1, p, 1, 0, 4, 70000, 8, 0, p, p, 1 << 30, nul) == tp.TP_EINVAL
+    assert tp._normalize_ws(2, 8) == 512
+    assert tp._normalize_ws(0, 8) == 0

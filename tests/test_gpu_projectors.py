@@ -1,0 +1,171 @@
+"""GPU parity of tp_backproject and tp_radon against the FP64 oracle, the exact
+transposition of the pair, and the bitwise invariance under tuning."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_08450_amd import synth
+from tests._util import note, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2209_08450_amd import tp as mod
+    return mod
+
+
+GEOMS = [
+    # (n_angles, n_det, n_vox, center, rows)
+    (180, 256, 256, 128.0, 5),     # several tiles, ragged slice group
+    (37, 100, 90, 47.3, 3),        # odd angles, ragged tiles, N != n
+    (16, 64, 64, 29.75, 9),
+    (1, 40, 33, 19.0, 1),
+    (64, 128, 160, 64.0, 2),       # image larger than the detector: off-detector taps
+    (24, 70, 70, 200.0, 2),        # axis far off the detector
+]
+
+
+@pytest.mark.parametrize("g", GEOMS)
+def test_backproject_matches_oracle(tp, g):
+    na, n, N, c, rows = g
+    rng = np.random.default_rng(na * 7 + n)
+    ang = synth.uniform_angles(na) + 0.013
+    q = rng.standard_normal((rows, na, n))
+    plan = tp.Plan(ang, n, c, N)
+    note(f"backproject f32 {g}")
+    got = to_host(tp.backproject(plan, to_dev(q.astype(np.float32))))
+    want = oracle.backproject(q.astype(np.float32).astype(np.float64), ang, c, N)
+    assert got.shape == want.shape
+    if np.linalg.norm(want) == 0:  # every ray misses the detector
+        assert np.all(got == 0)
+    else:
+        assert rel_l2(got, want) < 1e-5
+
+
+def test_backproject_constant_rows_give_pi(tp):
+    na, n = 90, 128
+    ang = synth.uniform_angles(na)
+    plan = tp.Plan(ang, n, n / 2)
+    note("backproject q=1")
+    f = to_host(tp.backproject(plan, to_dev(np.ones((2, na, n), np.float32))))
+    yy, xx = np.mgrid[0:n, 0:n]
+    inner = np.hypot(xx - n // 2, yy - n // 2) < n / 2 - 2
+    assert np.max(np.abs(f[:, inner] - math.pi)) < 2e-6
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_backproject_half_storage(tp, dt):
+    import torch
+    na, n, N, c = 45, 96, 96, 47.5
+    rng = np.random.default_rng(5)
+    ang = synth.uniform_angles(na)
+    q = rng.standard_normal((3, na, n)).astype(np.float32)
+    t = to_dev(q).to(tp.torch_dtype(tp.dtype_code(dt)))
+    stored = to_host(t).astype(np.float64)
+    plan = tp.Plan(ang, n, c, N)
+    note(f"backproject {dt}")
+    got = to_host(tp.backproject(plan, t))
+    assert rel_l2(got, oracle.backproject(stored, ang, c, N)) < 1e-5
+    torch.cuda.synchronize()
+
+
+def test_backproject_accumulate_and_scale(tp):
+    import torch
+    na, n = 20, 64
+    rng = np.random.default_rng(6)
+    ang = synth.uniform_angles(na)
+    q = rng.standard_normal((2, na, n)).astype(np.float32)
+    plan = tp.Plan(ang, n, 31.5)
+    note("backproject accumulate")
+    out = torch.full((2, n, n), 3.0, device="cuda")
+    tp.backproject(plan, to_dev(q), scale=0.5, out=out, accumulate=True)
+    want = 3.0 + oracle.backproject(q.astype(np.float64), ang, 31.5, n, scale=0.5)
+    assert rel_l2(to_host(out), want) < 1e-6
+
+
+def test_tuning_variants_are_bitwise_identical(tp):
+    import torch
+    na, n, N, c, rows = 70, 120, 110, 61.2, 11
+    rng = np.random.default_rng(8)
+    ang = synth.uniform_angles(na) + 0.2
+    q = to_dev(rng.standard_normal((rows, na, n)).astype(np.float32))
+    qh = q.half()
+    plan = tp.Plan(ang, n, c, N)
+    ref = ref_h = None
+    for k, a in [(4, 32), (1, 8), (2, 16), (8, 32), (8, 16), (4, 64), (1, 64)]:
+        plan.set_tuning(k, a)
+        assert plan.get_tuning() == (k, a)
+        note(f"backproject tuning K={k} A={a}")
+        f = tp.backproject(plan, q)
+        fh = tp.backproject(plan, qh)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref, ref_h = f.clone(), fh.clone()
+        else:
+            assert torch.equal(f, ref), (k, a)
+            assert torch.equal(fh, ref_h), (k, a)
+
+
+@pytest.mark.parametrize("g", GEOMS)
+def test_radon_matches_oracle(tp, g):
+    na, n, N, c, rows = g
+    rng = np.random.default_rng(na + 3 * n)
+    ang = synth.uniform_angles(na) + 0.013
+    x = rng.standard_normal((rows, N, N)).astype(np.float32)
+    plan = tp.Plan(ang, n, c, N)
+    note(f"radon {g}")
+    got = to_host(tp.radon(plan, to_dev(x)))
+    want = oracle.radon(x.astype(np.float64), ang, c, n)
+    if np.linalg.norm(want) == 0:
+        assert np.all(got == 0)
+    else:
+        assert rel_l2(got, want) < 1e-5
+
+
+@pytest.mark.parametrize("g", GEOMS[:3])
+def test_adjoint_dot_product(tp, g):
+    na, n, N, c, rows = g
+    rng = np.random.default_rng(17)
+    ang = synth.uniform_angles(na) + 0.013
+    x = rng.standard_normal((rows, N, N)).astype(np.float32)
+    y = rng.standard_normal((rows, na, n)).astype(np.float32)
+    plan = tp.Plan(ang, n, c, N)
+    note(f"adjoint {g}")
+    Rx = to_host(tp.radon(plan, to_dev(x))).astype(np.float64)
+    Rty = to_host(tp.backproject(plan, to_dev(y), scale=1.0)).astype(np.float64)
+    lhs = np.vdot(Rx, y.astype(np.float64))
+    rhs = np.vdot(x.astype(np.float64), Rty)
+    assert abs(lhs - rhs) / max(abs(lhs), abs(rhs)) < 1e-5
+
+
+def test_radon_is_exact_transpose_of_backproject(tp):
+    # Build both system matrices from unit vectors: with one nonzero input the
+    # FP32 sums are exact, so the matrices must agree bitwise.
+    N, n, na, c = 12, 18, 5, 8.6
+    ang = synth.uniform_angles(na) + 0.1
+    plan = tp.Plan(ang, n, c, N)
+    units_img = np.eye(N * N, dtype=np.float32).reshape(N * N, N, N)
+    units_sino = np.eye(na * n, dtype=np.float32).reshape(na * n, na, n)
+    note("transpose check")
+    A_radon = to_host(tp.radon(plan, to_dev(units_img))).reshape(N * N, na * n)      # rows: voxels
+    A_bp = to_host(tp.backproject(plan, to_dev(units_sino), scale=1.0)).reshape(na * n, N * N)
+    assert np.array_equal(A_radon, A_bp.T)
+    # and both equal the FP64 hat weights up to FP32 rounding of (1-w, w)
+    A64 = oracle.radon(np.eye(N * N).reshape(N * N, N, N), ang, c, n).reshape(N * N, na * n)
+    assert np.max(np.abs(A_radon - A64)) < 1e-5
+
+
+def test_radon_mass_conservation(tp):
+    N, n, na = 64, 128, 33
+    rng = np.random.default_rng(19)
+    f = rng.uniform(0, 1, (2, N, N)).astype(np.float32)
+    plan = tp.Plan(synth.uniform_angles(na), n, n / 2, N)
+    note("radon mass")
+    r = to_host(tp.radon(plan, to_dev(f))).astype(np.float64)
+    assert np.allclose(r.sum(axis=2), f.astype(np.float64).sum(axis=(1, 2))[:, None], rtol=2e-6)
