@@ -1,0 +1,262 @@
+#!/usr/bin/env python
+"""Benchmark: filtered backprojection of a 2048^3 volume on one MI355X.
+
+Workload (the paper's N = 2048 case, Section 3): 2048 projections over 180
+degrees x 2048 detector rows x 2048 columns of 12-bit counts from a seeded
+200-ellipsoid phantom (20 darks, 20 flats), reconstructed to 2048^3 float32.
+Inputs are generated on the GPU and resident in HBM before timing starts.  A
+step is one full FBP of the volume: for each chunk of rows, dark/flat means,
+fused normalise + ramp filter, backprojection (tp_fbp_chunk).  Both storage
+precisions of the filtered rows are timed: FP16 (the reported value) and FP32.
+
+Printed: ONE JSON line on stdout (progress goes to stderr) with the metric,
+per-precision seconds per volume, the FP16/FP32 speed-up, the relative L2 error
+of each against the FP64 oracle on full sampled slices, a roofline entry for
+the dominant kernel (backprojection) from HIP events around each launch, and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gvoxel-angle updates/s and s per 2048^3 FBP, FP16 vs FP32 at stated L2 error"
+UNIT = "Gvoxel-angle updates/s"
+# Algorithmic work of one voxel-angle update of the backprojection: detector
+# coordinate (1 FMA = 2), interpolation fraction (1), linear interpolation
+# (subtract + FMA = 3), accumulation (1).
+FLOP_PER_UPDATE = 7
+# MI355X fp32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2048, help="detector columns = voxels per side")
+    ap.add_argument("--angles", type=int, default=2048)
+    ap.add_argument("--rows", type=int, default=2048)
+    ap.add_argument("--chunk", type=int, default=256, help="rows per tp_fbp_chunk call")
+    ap.add_argument("--storage", default="f16,f32", help="storage precisions to time (first is reported)")
+    ap.add_argument("--tuning", default="", help="backprojection tuning K,A (default: plan default)")
+    ap.add_argument("--parity-rows", type=int, default=2, help="full slices checked against the oracle")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU-baseline budget: oracle slices are added until this much time is spent (0: skip)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2209_08450_amd", "csrc", "k_backproject.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(storage: str, chunk: int, n: int, angles: int):
+    """HBM traffic per backprojection launch from committed rocprofv3 counters,
+    if they were taken on the current kernel source and this launch shape."""
+    p = os.path.join(ROOT, "profiles", "traffic_backproject.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    e = d.get(storage)
+    if not e or d.get("kernel_sha") != kernel_source_hash():
+        return None
+    if (e.get("chunk"), e.get("n"), e.get("angles")) != (chunk, n, angles):
+        return None
+    return float(e["bytes_per_launch"])
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(slices are independent, see DESIGN.md for how the path shards)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2209_08450_amd import synth, tp
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, na, rows, chunk = args.n, args.angles, args.rows, min(args.chunk, args.rows)
+    storages = [s.strip() for s in args.storage.split(",") if s.strip()]
+    center = n / 2.0
+
+    # ---------------- inputs, resident in HBM ----------------
+    t0 = time.time()
+    log(f"generating {na} x {rows} x {n} 12-bit scan on the GPU")
+    last = [time.time()]
+
+    def progress(done, total):
+        if time.time() - last[0] > 10:
+            log(f"  generated rows {done}/{total}")
+            last[0] = time.time()
+
+    scan = synth.ellipsoid_scan_torch(seed=2, n_angles=na, n_rows=rows, n_det=n, device=dev, center=center,
+                                      progress=progress)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f} s: proj {tuple(scan.proj.shape)} "
+        f"({scan.proj.numel() * 2 / 1e9:.1f} GB)")
+
+    plan = tp.Plan(scan.angles, n, center)
+    if args.tuning:
+        k, a = (int(v) for v in args.tuning.split(","))
+        plan.set_tuning(k, a)
+    tuning = plan.get_tuning()
+    vol = torch.empty((rows, n, n), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(plan.fbp_workspace_bytes(chunk, s) for s in storages), dtype=torch.uint8, device=dev)
+    chunks = [(z0, min(rows, z0 + chunk)) for z0 in range(0, rows, chunk)]
+    stream = torch.cuda.current_stream()
+    updates = float(n) * n * na * rows
+
+    parity_z = [int(z) for z in np.linspace(rows // 8, rows - rows // 8, args.parity_rows).round()] \
+        if args.parity_rows > 0 else []
+    results = {}
+    for st in storages:
+        # events per chunk: before darkflat, before norm+filter, before BP, after BP
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in chunks]
+        for row in evs:
+            for e in row:
+                e.record(stream)  # create the underlying HIP events
+
+        def step(record):
+            for ci, (z0, z1) in enumerate(chunks):
+                tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st,
+                             out=vol[z0:z1], workspace=ws, events=evs[ci] if record else None)
+
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        log(f"[{st}] warmup done; timing {args.steps} steps")
+        stage = np.zeros(3)
+        bp_times = []
+        t_start = time.perf_counter()
+        for s_i in range(args.steps):
+            step(True)
+            torch.cuda.synchronize()
+            for row in evs:
+                d = [row[i].elapsed_time(row[i + 1]) for i in range(3)]
+                stage += d
+                bp_times.append(d[2])
+            log(f"[{st}] step {s_i + 1}/{args.steps} done")
+        t_total = time.perf_counter() - t_start
+        sec = t_total / args.steps
+        samples = {z: vol[z].detach().cpu().numpy().astype(np.float64) for z in parity_z}
+        results[st] = {
+            "s_per_volume": sec,
+            "gups": updates / sec / 1e9,
+            "stage_ms_per_step": {"darkflat": stage[0] / args.steps, "norm_filter": stage[1] / args.steps,
+                                  "backproject": stage[2] / args.steps},
+            "bp_launch_ms": float(np.mean(bp_times)),
+            "samples": samples,
+        }
+        log(f"[{st}] {sec:.3f} s per volume, {updates / sec / 1e9:.1f} Gupd/s, "
+            f"BP launch {np.mean(bp_times):.2f} ms")
+
+    # ---------------- FP64 oracle: parity slices and CPU baseline ----------------
+    import oracle
+
+    def oracle_slice(z):
+        p = scan.proj[:, z, :].cpu().numpy().view(np.uint16)[:, None, :]
+        d = scan.dark[:, z, :].cpu().numpy().view(np.uint16)[:, None, :]
+        f = scan.flat[:, z, :].cpu().numpy().view(np.uint16)[:, None, :]
+        t1 = time.perf_counter()
+        v = oracle.fbp(p, d, f, scan.angles, center)[0]
+        return v, time.perf_counter() - t1
+
+    rel = {st: None for st in storages}
+    cpu_t, cpu_slices = 0.0, 0
+    ref = {}
+    for z in parity_z:
+        log(f"oracle FBP of slice {z} ({oracle.num_threads()} threads)")
+        ref[z], dt = oracle_slice(z)
+        cpu_t += dt
+        cpu_slices += 1
+    for st in storages:
+        if parity_z:
+            num = sum(np.sum((results[st]["samples"][z] - ref[z]) ** 2) for z in parity_z)
+            den = sum(np.sum(ref[z] ** 2) for z in parity_z)
+            rel[st] = float(math.sqrt(num / den))
+            log(f"[{st}] rel-L2 vs FP64 oracle on slices {parity_z}: {rel[st]:.3e}")
+    cpu = None
+    if args.cpu_seconds > 0:
+        extra = [z for z in range(0, rows, max(1, rows // 16)) if z not in parity_z]
+        while (cpu_t < args.cpu_seconds or cpu_slices == 0) and extra:
+            z = extra.pop(0)
+            log(f"oracle FBP of slice {z} for the CPU baseline")
+            _, dt = oracle_slice(z)
+            cpu_t += dt
+            cpu_slices += 1
+        cpu_updates = float(n) * n * na * cpu_slices
+        cpu = {"value": round(cpu_updates / cpu_t / 1e9, 4), "unit": UNIT, "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{cpu_slices} full slices of the workload ({na} angles x {n} cols -> {n}^2; "
+                         f"normalise, filter, backproject in FP64), {cpu_t:.1f} s",
+               "s_per_volume_extrapolated": round(cpu_t / cpu_slices * rows, 1)}
+
+    # ---------------- report ----------------
+    head = storages[0]
+    r = results[head]
+    bp_updates = float(n) * n * na * chunk
+    achieved = FLOP_PER_UPDATE * bp_updates / (r["bp_launch_ms"] * 1e-3) / 1e12
+    traffic = load_traffic(head, chunk, n, na)
+    out = {
+        "metric": METRIC,
+        "value": round(r["gups"], 3),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["s_per_volume"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"fbp {n}x{n}x{rows} volume from {na} angles x {rows} rows x {n} cols "
+                               f"12-bit ellipsoid scan, ramp filter, linear-interpolation backprojection",
+                   "storage": head, "chunk_rows": chunk, "bp_tuning": list(tuning)},
+        "s_per_volume": {st: round(results[st]["s_per_volume"], 4) for st in storages},
+        "gups": {st: round(results[st]["gups"], 2) for st in storages},
+        "rel_l2_vs_fp64_oracle": rel,
+        "stage_ms_per_step": {st: {k: round(v, 2) for k, v in results[st]["stage_ms_per_step"].items()}
+                              for st in storages},
+        "roofline": {"bound": "alu", "kernel": "k_backproject", "achieved": round(achieved, 2),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                     "traffic": traffic,
+                     "launch_ms": round(r["bp_launch_ms"], 3),
+                     "flop_per_launch": FLOP_PER_UPDATE * bp_updates},
+        "cpu_baseline": cpu,
+        "paper_context": {"linerec_fp32_2048cubed_total_s_A100_incl_io": 80.0},
+    }
+    if "f16" in results and "f32" in results:
+        out["speedup_f16_vs_f32"] = round(results["f32"]["s_per_volume"] / results["f16"]["s_per_volume"], 3)
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,19 @@ tp_status tp_fbp_chunk(const tp_plan* plan,
                        void* workspace, size_t workspace_bytes,
                        float* vol, void* stream);
 
+/* As tp_fbp_chunk, and additionally records caller-created hipEvent_t handles
+ * (passed as void*) on `stream`: events[0] before the dark/flat means,
+ * events[1] before the fused normalise+filter, events[2] before the
+ * backprojection, events[3] after it.  Any entry may be NULL; events may be
+ * NULL.  For per-stage timing (the paper's timeline breakdown, Section 2.3). */
+tp_status tp_fbp_chunk_events(const tp_plan* plan,
+                              const uint16_t* proj, int64_t proj_stride,
+                              const uint16_t* dark, int32_t n_dark,
+                              const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                              int32_t n_rows, tp_filter_kind kind, tp_dtype storage,
+                              void* workspace, size_t workspace_bytes,
+                              float* vol, void* stream, void* const* events);
+
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* tp_last_error(void);
 /* Library version string. */

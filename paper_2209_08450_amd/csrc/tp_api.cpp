@@ -399,6 +399,14 @@ tp_status tp_fbp_chunk(const tp_plan* plan, const uint16_t* proj, int64_t proj_s
                        int32_t n_dark, const uint16_t* flat, int32_t n_flat, int64_t frame_stride, int32_t n_rows,
                        tp_filter_kind kind, tp_dtype storage, void* workspace, size_t workspace_bytes, float* vol,
                        void* stream) {
+    return tp_fbp_chunk_events(plan, proj, proj_stride, dark, n_dark, flat, n_flat, frame_stride, n_rows, kind,
+                               storage, workspace, workspace_bytes, vol, stream, nullptr);
+}
+
+tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride, const uint16_t* dark,
+                              int32_t n_dark, const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                              int32_t n_rows, tp_filter_kind kind, tp_dtype storage, void* workspace,
+                              size_t workspace_bytes, float* vol, void* stream, void* const* events) {
     if (!plan) return fail(TP_EINVAL, "plan is null");
     tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, plan->na, n_rows,
                             plan->n);
@@ -422,13 +430,22 @@ tp_status tp_fbp_chunk(const tp_plan* plan, const uint16_t* proj, int64_t proj_s
     float* den = reinterpret_cast<float*>(static_cast<char*>(workspace) + dfb / 2);
     void* filt = static_cast<char*>(workspace) + dfb;
     tp::RawInput in{proj, proj_stride, dark, flat, frame_stride, n_dark, n_flat};
-    hipError_t e = tp::launch_darkflat(in, n_rows, plan->n, dmean, den, st);
+    auto mark = [&](int i) -> hipError_t {
+        if (!events || !events[i]) return hipSuccess;
+        return hipEventRecord(static_cast<hipEvent_t>(events[i]), st);
+    };
+    hipError_t e = mark(0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    e = tp::launch_darkflat(in, n_rows, plan->n, dmean, den, st);
     if (e != hipSuccess) return hip_fail(e, "darkflat launch");
+    if ((e = mark(1)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     e = tp::launch_norm_filter(in, dmean, den, plan->na, n_rows, plan->n, plan->filt, storage, filt, st);
     if (e != hipSuccess) return hip_fail(e, "norm_filter launch");
+    if ((e = mark(2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     e = tp::launch_backproject(plan->geo, filt, storage, n_rows, static_cast<float>(M_PI / plan->na), vol, 0,
                                plan->bp_k, plan->bp_a, st);
     if (e != hipSuccess) return hip_fail(e, "backproject launch");
+    if ((e = mark(3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return TP_OK;
 }
 

@@ -58,6 +58,8 @@ _radon = _proto("tp_radon", _c_i32, _c_vp, _c_vp, _c_i32, _c_vp, _c_vp)
 _fbp_ws = _proto("tp_fbp_workspace_bytes", _c_sz, _c_vp, _c_i32, _c_i32)
 _fbp_chunk = _proto("tp_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32,
                     _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp)
+_fbp_chunk_events = _proto("tp_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
+                           _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp, ctypes.POINTER(_c_vp))
 _last_error = _proto("tp_last_error", ctypes.c_char_p)
 _version = _proto("tp_version", ctypes.c_char_p)
 
@@ -266,8 +268,13 @@ def radon(plan: Plan, vol, out=None, stream=None):
     return out
 
 
-def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=None, stream=None):
-    """Raw counts of a row chunk -> reconstructed slices [rows][N][N] (float32)."""
+def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=None, stream=None, events=None):
+    """Raw counts of a row chunk -> reconstructed slices [rows][N][N] (float32).
+
+    ``events``: optional list of four recorded-once ``torch.cuda.Event`` objects
+    (or None entries) marked before the dark/flat means, the fused
+    normalise+filter and the backprojection, and after it.
+    """
     torch = _torch()
     n_angles, n_rows, n_det = (int(s) for s in proj.shape)
     if n_angles != plan.n_angles or n_det != plan.n_det:
@@ -285,7 +292,18 @@ def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=N
         workspace = _workspace(need, proj.device)
     if out is None:
         out = torch.empty((n_rows, plan.n_vox, plan.n_vox), dtype=torch.float32, device=proj.device)
-    _check(_fbp_chunk(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, TP_RAMP,
-                      code, _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
-                      _dev(out, "out"), _stream_ptr(stream)))
+    if events is None:
+        _check(_fbp_chunk(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, TP_RAMP,
+                          code, _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                          _dev(out, "out"), _stream_ptr(stream)))
+    else:
+        if len(events) != 4:
+            raise ValueError("events must hold four entries")
+        arr = (_c_vp * 4)(*[_c_vp(e.cuda_event) if e is not None else _c_vp() for e in events])
+        if any(e is not None and not e.cuda_event for e in events):
+            raise ValueError("record each event once before passing it (torch creates it lazily)")
+        _check(_fbp_chunk_events(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows,
+                                 TP_RAMP, code, _dev(workspace, "workspace"),
+                                 workspace.numel() * workspace.element_size(), _dev(out, "out"),
+                                 _stream_ptr(stream), arr))
     return out
