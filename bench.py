@@ -123,8 +123,9 @@ def main():
     plan = tp.Plan(scan.angles, n, center)
     if args.tuning:
         k, a = (int(v) for v in args.tuning.split(","))
-        plan.set_tuning(k, a)
-    tuning = plan.get_tuning()
+        for st in storages:
+            plan.set_tuning(st, k, a)
+    tuning = {st: list(plan.get_tuning(st)) for st in storages}
     vol = torch.empty((rows, n, n), dtype=torch.float32, device=dev)
     ws = torch.empty(max(plan.fbp_workspace_bytes(chunk, s) for s in storages), dtype=torch.uint8, device=dev)
     chunks = [(z0, min(rows, z0 + chunk)) for z0 in range(0, rows, chunk)]
@@ -237,7 +238,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"fbp {n}x{n}x{rows} volume from {na} angles x {rows} rows x {n} cols "
                                f"12-bit ellipsoid scan, ramp filter, linear-interpolation backprojection",
-                   "storage": head, "chunk_rows": chunk, "bp_tuning": list(tuning)},
+                   "storage": head, "chunk_rows": chunk, "bp_tuning": tuning},
         "s_per_volume": {st: round(results[st]["s_per_volume"], 4) for st in storages},
         "gups": {st: round(results[st]["gups"], 2) for st in storages},
         "rel_l2_vs_fp64_oracle": rel,

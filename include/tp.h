@@ -80,12 +80,17 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out);
 /* Frees the plan's tables; the caller must ensure no enqueued work still uses them. */
 tp_status tp_plan_destroy(tp_plan* plan);
 
-/* Tuning of the backprojection kernel (results are bitwise identical for
- * every legal choice: each slice always sums angles in order).
- *   slices_per_block in {1, 2, 4, 8}: slices sharing one geometry evaluation;
- *   angles_per_block in {8, 16, 32, 64}: angles staged in LDS per step. */
-tp_status tp_plan_set_tuning(tp_plan* plan, int32_t slices_per_block, int32_t angles_per_block);
-tp_status tp_plan_get_tuning(const tp_plan* plan, int32_t* slices_per_block, int32_t* angles_per_block);
+/* Tuning of the backprojection kernel for one storage type of its input
+ * (results are bitwise identical for every legal choice: each slice always
+ * sums its angles in order).
+ *   slices_per_block in {1, 2, 4, 8}: slices sharing one coordinate evaluation;
+ *   angles_per_block in {8, 16, 32, 64}: angles staged in LDS per step;
+ *   the staged block, angles x 48 bins x slices x 4 bytes (2 for F16), must
+ *   fit in 160 KiB.  Defaults: F16 (8, 32); F32 and BF16 (8, 16). */
+tp_status tp_plan_set_tuning(tp_plan* plan, tp_dtype storage, int32_t slices_per_block,
+                             int32_t angles_per_block);
+tp_status tp_plan_get_tuning(const tp_plan* plan, tp_dtype storage, int32_t* slices_per_block,
+                             int32_t* angles_per_block);
 
 /* Build and cache the ramp-filter tables of one pad length on the current
  * device (for tp_filter calls that will be graph-captured).  pad_len: power of

@@ -15,60 +15,70 @@
 // Backprojection work-group: one 32x32 voxel tile x K slices, 256 threads.
 // Thread (wave w, lane l) owns voxels (l%8 + 8i, l/8 + 8w), i = 0..3, so each
 // wave step covers an 8x8 block whose taps fall in a window of about 13
-// detector bins -- distinct LDS banks, or broadcasts.  For a block of A angles
-// the work-group stages, per slice and angle, the 48-bin window of filtered
-// values the tile can touch as (Q[j], Q[j+1]) pairs in LDS; the inner loop is
-// then one LDS read and two FMAs per voxel, slice and angle, with floor,
-// fraction and address shared by the K slices.  The staged window starts at
-// bi + floor(min over the tile corners of the FP32 offset); fma is monotone
-// in each argument, so every voxel's floor lies in [0, 45) of the window.
+// detector bins.  For a block of A angles, each wave stages whole angles: lane
+// b loads bin ws + b of the K slices' filtered rows and writes them as one
+// contiguous group, so LDS holds [angle][bin][slice] (bf16 widened to FP32).
+// The window starts at ws = bi + floor(min over the tile corners of the
+// FP32 offset); fma is monotone in each argument, so every voxel's floor
+// lies in [0, 45) of the 48-bin window and both taps are staged.  The inner
+// loop per voxel and angle: offset (1 FMA), fraction, floor, address, 1 - w,
+// one read of the two bins' K-slice groups (16-byte LDS reads), then two
+// FMAs per slice (v_fma_mix_f32 reads FP16 operands directly).  Every slice
+// sums its angles in order, so results do not depend on K or A.
 #include "tp_internal.h"
 
 namespace tp {
 namespace {
 
-template <typename T> struct Stage;  // LDS pair type per storage type
-template <> struct Stage<float> {
-    using P = float2;
-    __device__ static P make(float a, float b) { return make_float2(a, b); }
-    __device__ static float lo(P p) { return p.x; }
-    __device__ static float hi(P p) { return p.y; }
-};
-template <> struct Stage<__half> {
-    using P = __half2;
-    __device__ static P make(float a, float b) { return __halves2half2(__float2half_rn(a), __float2half_rn(b)); }
-    __device__ static float lo(P p) { return __low2float(p); }
-    __device__ static float hi(P p) { return __high2float(p); }
-};
-template <> struct Stage<uint16_t> {  // bfloat16 storage: widened to FP32 pairs in LDS
-    using P = float2;
-    __device__ static P make(float a, float b) { return make_float2(a, b); }
-    __device__ static float lo(P p) { return p.x; }
-    __device__ static float hi(P p) { return p.y; }
-};
+template <typename T> struct Lds { using U = T; };          // LDS element per storage type
+template <> struct Lds<uint16_t> { using U = float; };     // bf16 widened
 
 template <typename T> __device__ __forceinline__ float ld(const T* p, int j) { return load_as_float(p, j); }
 
-template <typename T, int K>
+__device__ __forceinline__ float lds_val(const float* v, int i) { return v[i]; }
+__device__ __forceinline__ float lds_val(const __half* v, int i) { return __half2float(v[i]); }
+
+// Copy BYTES between LDS and registers in chunks of CHUNK bytes (the
+// alignment both addresses are known to have, at most 16).
+template <int BYTES, int CHUNK>
+__device__ __forceinline__ void copy_group(void* dst, const void* src) {
+    static_assert(BYTES % CHUNK == 0, "size must be a multiple of the chunk");
+    if constexpr (CHUNK >= 16) {
+#pragma unroll
+        for (int v = 0; v < BYTES / 16; ++v) reinterpret_cast<uint4*>(dst)[v] = reinterpret_cast<const uint4*>(src)[v];
+    } else if constexpr (CHUNK == 8) {
+#pragma unroll
+        for (int v = 0; v < BYTES / 8; ++v) reinterpret_cast<uint2*>(dst)[v] = reinterpret_cast<const uint2*>(src)[v];
+    } else if constexpr (CHUNK == 4) {
+#pragma unroll
+        for (int v = 0; v < BYTES / 4; ++v)
+            reinterpret_cast<uint32_t*>(dst)[v] = reinterpret_cast<const uint32_t*>(src)[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < BYTES / 2; ++v)
+            reinterpret_cast<uint16_t*>(dst)[v] = reinterpret_cast<const uint16_t*>(src)[v];
+    }
+}
+
+template <typename T, int K, int A>
 __global__ void __launch_bounds__(kBpThreads)
-k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, int A, float scale,
-              float* __restrict__ vol, int accumulate) {
-    using S = Stage<T>;
-    using P = typename S::P;
+k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, float* __restrict__ vol,
+              int accumulate) {
+    using U = typename Lds<T>::U;
+    constexpr int BIN = K * static_cast<int>(sizeof(U));  // bytes of one (angle, bin) group
     extern __shared__ __align__(16) unsigned char smem[];
-    P* sQ = reinterpret_cast<P*>(smem);                                // [K][A][kWin]
-    float4* sGeo = reinterpret_cast<float4*>(sQ + K * A * kWin);        // [A] {bf, cos, sin, floor(min)}
-    int* sWs = reinterpret_cast<int*>(sGeo + A);                        // [A] window start bin
+    // smem: [A][kWin][K] values of U, then sGeo
+    float4* sGeo = reinterpret_cast<float4*>(smem + A * kWin * BIN);          // [A] {bf, cos, sin, byte base}
 
     const int na = g.na, n = g.n, nb = g.nb;
     const int bx = blockIdx.x % nb, by = blockIdx.x / nb;
     const int z0 = blockIdx.y * K;
+    const int kz = min(K, n_rows - z0);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const float dy = static_cast<float>((lane >> 3) + 8 * wv);
     const float dx0 = static_cast<float>(lane & 7);
-    const float dxs[4] = {dx0, dx0 + 8.0f, dx0 + 16.0f, dx0 + 24.0f};
-    const int kstride = A * kWin;
+    const T* rows0 = filt + static_cast<int64_t>(z0) * na * n;
 
     float acc[4][K];
 #pragma unroll
@@ -78,52 +88,47 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, int A, float 
 
     for (int a0 = 0; a0 < na; a0 += A) {
         const int nA = min(A, na - a0);
-        if (tid < nA) {
-            const int a = a0 + tid;
-            const float cs = g.cs[a], sn = g.sn[a];
-            const int bi = g.xi[bx * na + a] + g.yi[by * na + a];
-            const float bf = g.xf[bx * na + a] + g.yf[by * na + a];
-            const float ty = __builtin_fmaf(sn >= 0.0f ? 0.0f : 31.0f, sn, bf);
-            const float smin = __builtin_fmaf(cs >= 0.0f ? 0.0f : 31.0f, cs, ty);
-            const float fmin = floorf(smin);
-            sGeo[tid] = make_float4(bf, cs, sn, fmin);
-            sWs[tid] = bi + static_cast<int>(fmin);
-        }
-        __syncthreads();
-        // Stage K x nA windows: one wave per (slice, angle) row, lanes 0..48 load
-        // Q[ws + lane]; the pair's upper element comes from the next lane.
-        for (int row = wv; row < K * nA; row += kBpThreads / 64) {
-            const int k = row / nA;
-            const int a = row - k * nA;
-            const int z = z0 + k;
-            const int j = sWs[a] + lane;
-            float q = 0.0f;
-            if (z < n_rows && lane <= kWin && j >= 0 && j < n)
-                q = ld(filt + (static_cast<int64_t>(z) * na + a0 + a) * n, j);
-            const float q1 = __shfl_down(q, 1);
-            if (lane < kWin) sQ[k * kstride + a * kWin + lane] = S::make(q, q1);
+        // stage: wave wv takes angles wv, wv+4, ...; lane b holds bin ws + b
+        for (int a = wv; a < nA; a += kBpThreads / 64) {
+            const int ag = a0 + a;
+            const float cs = g.cs[ag], sn = g.sn[ag];
+            const int bi = g.xi[bx * na + ag] + g.yi[by * na + ag];
+            const float bf = g.xf[bx * na + ag] + g.yf[by * na + ag];
+            const float smin = tile_offset(cs >= 0.0f ? 0.0f : 31.0f, sn >= 0.0f ? 0.0f : 31.0f, cs, sn, bf);
+            const int fmin = coord_floor(smin);
+            if (lane == 0) sGeo[a] = make_float4(bf, cs, sn, __int_as_float((a * kWin - fmin) * BIN));
+            if (lane < kWin) {
+                const int j = bi + fmin + lane;
+                const bool on = j >= 0 && j < n;
+                U q[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    float v = 0.0f;
+                    if (on && k < kz) v = ld(rows0 + (static_cast<int64_t>(k) * na + ag) * n, j);
+                    q[k] = static_cast<U>(v);
+                }
+                copy_group<BIN, (BIN < 16 ? BIN : 16)>(smem + (a * kWin + lane) * BIN, q);
+            }
         }
         __syncthreads();
         for (int a = 0; a < nA; ++a) {
             const float4 ge = sGeo[a];
-            const float t = __builtin_fmaf(dy, ge.z, ge.x);
-            const P* rowp = sQ + a * kWin;
+            const int base = __float_as_int(ge.w);
+            U r[4][2 * K];  // bins (j, j+1) of K slices per voxel
+            float w[4], omw[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float s = __builtin_fmaf(dxs[i], ge.y, t);
-                const float fl = floorf(s);
-                const float w = s - fl;
-                const float omw = 1.0f - w;
-                // in [0, 44] by the monotonicity argument; the clamp (one
-                // v_med3) only guards the staged window
-                const int jl = min(max(static_cast<int>(fl - ge.w), 0), kWin - 2);
-                const P* pp = rowp + jl;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const P pr = pp[k * kstride];
-                    acc[i][k] = __builtin_fmaf(S::hi(pr), w, __builtin_fmaf(S::lo(pr), omw, acc[i][k]));
-                }
+                const float s = tile_offset(dx0 + 8.0f * i, dy, ge.y, ge.z, ge.x);
+                w[i] = coord_frac(s);
+                omw[i] = 1.0f - w[i];
+                copy_group<2 * BIN, (BIN < 16 ? BIN : 16)>(r[i], smem + base + coord_floor(s) * BIN);
             }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    acc[i][k] = __builtin_fmaf(lds_val(r[i], K + k), w[i],
+                                               __builtin_fmaf(lds_val(r[i], k), omw[i], acc[i][k]));
         }
         __syncthreads();
     }
@@ -136,9 +141,8 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, int A, float 
         if (x >= N || y >= N) continue;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int z = z0 + k;
-            if (z >= n_rows) continue;
-            const int64_t idx = (static_cast<int64_t>(z) * N + y) * N + x;
+            if (k >= kz) continue;
+            const int64_t idx = (static_cast<int64_t>(z0 + k) * N + y) * N + x;
             const float v = scale * acc[i][k];
             vol[idx] = accumulate ? vol[idx] + v : v;
         }
@@ -186,10 +190,9 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
             const float dx = static_cast<float>(ix & 31), dy = static_cast<float>(iy & 31);
             const int bi = g.xi[bx * na + a] + g.yi[by * na + a];
             const float bf = g.xf[bx * na + a] + g.yf[by * na + a];
-            const float s = __builtin_fmaf(dx, cs, __builtin_fmaf(dy, sn, bf));
-            const float fl = floorf(s);
-            const int j0 = bi + static_cast<int>(fl);
-            const float w = s - fl;
+            const float s = tile_offset(dx, dy, cs, sn, bf);
+            const int j0 = bi + coord_floor(s);
+            const float w = coord_frac(s);
             float wt;
             if (j0 == j) wt = 1.0f - w;
             else if (j0 + 1 == j) wt = w;
@@ -208,32 +211,44 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
 }
 
 size_t bp_lds_bytes(tp_dtype dt, int K, int A) {
-    const size_t pair = (dt == TP_F16) ? 4 : 8;
-    return pair * K * A * kWin + static_cast<size_t>(A) * (sizeof(float4) + sizeof(int));
+    const size_t elem = (dt == TP_F16) ? 2 : 4;  // bf16 is widened to FP32 in LDS
+    return elem * K * A * kWin + static_cast<size_t>(A) * sizeof(float4);
 }
 
-template <typename T, int K>
+template <typename T, int K, int A>
 hipError_t launch_bp_t(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
-                       int accumulate, int A, size_t lds, hipStream_t st) {
+                       int accumulate, size_t lds, hipStream_t st) {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_backproject<T, K>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_backproject<T, K, A>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     const dim3 grid(static_cast<unsigned>(g.nb * g.nb), static_cast<unsigned>((n_rows + K - 1) / K));
-    hipLaunchKernelGGL((k_backproject<T, K>), grid, dim3(kBpThreads), lds, st, g, static_cast<const T*>(filt),
-                       n_rows, A, scale, vol, accumulate);
+    hipLaunchKernelGGL((k_backproject<T, K, A>), grid, dim3(kBpThreads), lds, st, g, static_cast<const T*>(filt),
+                       n_rows, scale, vol, accumulate);
     return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t launch_bp_a(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
+                       int accumulate, int A, size_t lds, hipStream_t st) {
+    switch (A) {
+        case 8: return launch_bp_t<T, K, 8>(g, filt, n_rows, scale, vol, accumulate, lds, st);
+        case 16: return launch_bp_t<T, K, 16>(g, filt, n_rows, scale, vol, accumulate, lds, st);
+        case 32: return launch_bp_t<T, K, 32>(g, filt, n_rows, scale, vol, accumulate, lds, st);
+        case 64: return launch_bp_t<T, K, 64>(g, filt, n_rows, scale, vol, accumulate, lds, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_bp_k(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
                        int accumulate, int K, int A, size_t lds, hipStream_t st) {
     switch (K) {
-        case 1: return launch_bp_t<T, 1>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
-        case 2: return launch_bp_t<T, 2>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
-        case 4: return launch_bp_t<T, 4>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
-        case 8: return launch_bp_t<T, 8>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
+        case 1: return launch_bp_a<T, 1>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
+        case 2: return launch_bp_a<T, 2>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
+        case 4: return launch_bp_a<T, 4>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
+        case 8: return launch_bp_a<T, 8>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
     }
     return hipErrorInvalidValue;
 }

@@ -14,10 +14,6 @@
 
 #include "tp_internal.h"
 
-namespace tp {
-size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_block);
-}
-
 struct tp_plan {
     int device = -1;
     int na = 0, n = 0, N = 0, nb = 0;
@@ -25,8 +21,9 @@ struct tp_plan {
     void* dev_block = nullptr;  // one allocation holding every geometry table
     tp::GeoTables geo{};
     tp::FilterTables filt{};
-    int bp_k = 4;
-    int bp_a = 32;
+    // backprojection tuning per storage type (F32, F16, BF16)
+    int bp_k[3] = {8, 8, 8};
+    int bp_a[3] = {16, 32, 16};
 };
 
 namespace {
@@ -277,24 +274,28 @@ tp_status tp_plan_destroy(tp_plan* plan) {
     return TP_OK;
 }
 
-tp_status tp_plan_set_tuning(tp_plan* plan, int32_t slices_per_block, int32_t angles_per_block) {
+tp_status tp_plan_set_tuning(tp_plan* plan, tp_dtype storage, int32_t slices_per_block,
+                             int32_t angles_per_block) {
     if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
     const int k = slices_per_block, a = angles_per_block;
     if (!(k == 1 || k == 2 || k == 4 || k == 8))
         return fail(TP_EINVAL, "slices_per_block=%d not in {1,2,4,8}", k);
     if (!(a == 8 || a == 16 || a == 32 || a == 64))
         return fail(TP_EINVAL, "angles_per_block=%d not in {8,16,32,64}", a);
-    if (tp::backproject_lds_bytes(TP_F32, k, a) > kMaxLds)
+    if (tp::backproject_lds_bytes(storage, k, a) > kMaxLds)
         return fail(TP_EINVAL, "slices_per_block=%d x angles_per_block=%d exceeds LDS", k, a);
-    plan->bp_k = k;
-    plan->bp_a = a;
+    plan->bp_k[storage] = k;
+    plan->bp_a[storage] = a;
     return TP_OK;
 }
 
-tp_status tp_plan_get_tuning(const tp_plan* plan, int32_t* slices_per_block, int32_t* angles_per_block) {
+tp_status tp_plan_get_tuning(const tp_plan* plan, tp_dtype storage, int32_t* slices_per_block,
+                             int32_t* angles_per_block) {
     if (!plan || !slices_per_block || !angles_per_block) return fail(TP_EINVAL, "null argument");
-    *slices_per_block = plan->bp_k;
-    *angles_per_block = plan->bp_a;
+    if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
+    *slices_per_block = plan->bp_k[storage];
+    *angles_per_block = plan->bp_a[storage];
     return TP_OK;
 }
 
@@ -370,12 +371,11 @@ tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtyp
     if (n_rows <= 0 || n_rows > 65535 * 8) return fail(TP_EINVAL, "n_rows=%d out of range", n_rows);
     if (!(accumulate == 0 || accumulate == 1)) return fail(TP_EINVAL, "accumulate must be 0 or 1");
     if (!std::isfinite(scale)) return fail(TP_EINVAL, "scale is not finite");
-    if ((n_rows + plan->bp_k - 1) / plan->bp_k > 65535)
-        return fail(TP_EINVAL, "n_rows=%d too large for slices_per_block=%d", n_rows, plan->bp_k);
-    if (tp::backproject_lds_bytes(in_dtype, plan->bp_k, plan->bp_a) > kMaxLds)
-        return fail(TP_EINVAL, "tuning exceeds LDS");
-    hipError_t e = tp::launch_backproject(plan->geo, filt, in_dtype, n_rows, scale, vol, accumulate, plan->bp_k,
-                                          plan->bp_a, static_cast<hipStream_t>(stream));
+    const int K = plan->bp_k[in_dtype], A = plan->bp_a[in_dtype];
+    if ((n_rows + K - 1) / K > 65535)
+        return fail(TP_EINVAL, "n_rows=%d too large for slices_per_block=%d", n_rows, K);
+    hipError_t e = tp::launch_backproject(plan->geo, filt, in_dtype, n_rows, scale, vol, accumulate, K, A,
+                                          static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "backproject launch");
     return TP_OK;
 }
@@ -418,12 +418,11 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(TP_EINVAL, "workspace not 256-byte aligned");
     const size_t need = tp_fbp_workspace_bytes(plan, n_rows, storage);
     if (workspace_bytes < need) return fail(TP_EINVAL, "workspace %zu < %zu bytes", workspace_bytes, need);
-    if ((n_rows + plan->bp_k - 1) / plan->bp_k > 65535)
-        return fail(TP_EINVAL, "n_rows=%d too large for slices_per_block=%d", n_rows, plan->bp_k);
+    const int K = plan->bp_k[storage], A = plan->bp_a[storage];
+    if ((n_rows + K - 1) / K > 65535)
+        return fail(TP_EINVAL, "n_rows=%d too large for slices_per_block=%d", n_rows, K);
     if (static_cast<int64_t>(n_rows) * ((plan->na + 1) / 2) > 0x7fffffffLL)
         return fail(TP_EINVAL, "n_rows=%d x n_angles=%d too large for one call", n_rows, plan->na);
-    if (tp::backproject_lds_bytes(storage, plan->bp_k, plan->bp_a) > kMaxLds)
-        return fail(TP_EINVAL, "tuning exceeds LDS");
     auto st = static_cast<hipStream_t>(stream);
     const size_t dfb = tp_normalize_workspace_bytes(n_rows, plan->n);
     float* dmean = static_cast<float*>(workspace);
@@ -442,8 +441,8 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
     e = tp::launch_norm_filter(in, dmean, den, plan->na, n_rows, plan->n, plan->filt, storage, filt, st);
     if (e != hipSuccess) return hip_fail(e, "norm_filter launch");
     if ((e = mark(2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = tp::launch_backproject(plan->geo, filt, storage, n_rows, static_cast<float>(M_PI / plan->na), vol, 0,
-                               plan->bp_k, plan->bp_a, st);
+    e = tp::launch_backproject(plan->geo, filt, storage, n_rows, static_cast<float>(M_PI / plan->na), vol, 0, K, A,
+                               st);
     if (e != hipSuccess) return hip_fail(e, "backproject launch");
     if ((e = mark(3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return TP_OK;

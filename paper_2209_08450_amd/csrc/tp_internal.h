@@ -61,7 +61,25 @@ hipError_t launch_norm_filter(const RawInput& in, const float* dmean, const floa
 hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt, int n_rows, float scale,
                               float* vol, int accumulate, int slices_per_block, int angles_per_block,
                               hipStream_t st);
+size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_block);
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st);
+
+// ---- detector coordinate decisions shared by backprojection and radon ----
+// Offset of voxel (dx, dy) within its 32x32 tile at one angle; bf is the
+// FP32 fraction of the tile origin's coordinate.  Explicit FMAs: no
+// reassociation, so both kernels round identically.
+__device__ __forceinline__ float tile_offset(float dx, float dy, float cs, float sn, float bf) {
+    return __builtin_fmaf(dx, cs, __builtin_fmaf(dy, sn, bf));
+}
+// floor(s) as an integer in one instruction.
+__device__ __forceinline__ int coord_floor(float s) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(s));
+    return r;
+}
+// Interpolation weight of the upper tap: s - floor(s), clamped below 1.0 by
+// the hardware instruction (only differs for |s| < 2^-24 below an integer).
+__device__ __forceinline__ float coord_frac(float s) { return __builtin_amdgcn_fractf(s); }
 
 // ---- storage conversions (round to nearest even) ----
 __device__ __forceinline__ float load_as_float(const float* p, int64_t i) { return p[i]; }

@@ -46,8 +46,9 @@ def _proto(name, restype, *args):
 
 _plan_create = _proto("tp_plan_create", _c_i32, ctypes.POINTER(Geometry), ctypes.POINTER(_c_vp))
 _plan_destroy = _proto("tp_plan_destroy", _c_i32, _c_vp)
-_plan_set_tuning = _proto("tp_plan_set_tuning", _c_i32, _c_vp, _c_i32, _c_i32)
-_plan_get_tuning = _proto("tp_plan_get_tuning", _c_i32, _c_vp, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32))
+_plan_set_tuning = _proto("tp_plan_set_tuning", _c_i32, _c_vp, _c_i32, _c_i32, _c_i32)
+_plan_get_tuning = _proto("tp_plan_get_tuning", _c_i32, _c_vp, _c_i32, ctypes.POINTER(_c_i32),
+                          ctypes.POINTER(_c_i32))
 _filter_prepare = _proto("tp_filter_prepare", _c_i32, _c_i32, _c_i32)
 _normalize_ws = _proto("tp_normalize_workspace_bytes", _c_sz, _c_i32, _c_i32)
 _normalize = _proto("tp_normalize", _c_i32, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32,
@@ -161,12 +162,13 @@ class Plan:
     def handle(self):
         return self._h
 
-    def set_tuning(self, slices_per_block: int, angles_per_block: int):
-        _check(_plan_set_tuning(self._h, int(slices_per_block), int(angles_per_block)))
+    def set_tuning(self, storage, slices_per_block: int, angles_per_block: int):
+        """Backprojection (slices per block, angles per block) for one storage type."""
+        _check(_plan_set_tuning(self._h, dtype_code(storage), int(slices_per_block), int(angles_per_block)))
 
-    def get_tuning(self):
+    def get_tuning(self, storage):
         k, a = _c_i32(), _c_i32()
-        _check(_plan_get_tuning(self._h, ctypes.byref(k), ctypes.byref(a)))
+        _check(_plan_get_tuning(self._h, dtype_code(storage), ctypes.byref(k), ctypes.byref(a)))
         return int(k.value), int(a.value)
 
     def close(self):
