@@ -294,3 +294,29 @@ def noisy_line_integrals(p: np.ndarray, flat_level: float, rng: np.random.Genera
     """
     p = np.asarray(p, dtype=np.float64)
     return p + np.sqrt(np.exp(p) / flat_level) * rng.standard_normal(p.shape)
+
+
+def noisy_line_integrals_torch(p, flat_level: float, generator):
+    """Torch version of ``noisy_line_integrals`` on p's device."""
+    import torch
+    e = torch.randn(p.shape, generator=generator, device=p.device, dtype=p.dtype)
+    return p + torch.sqrt(torch.exp(p) / flat_level) * e
+
+
+def ls_problem_torch(seed: int, n_slices: int, n_vox: int, n_angles: int, device, flat_level: float = 4000.0,
+                     n_ellipsoids: int = 200):
+    """Noisy line integrals y [n_slices][n_angles][n_vox] of the central slices of
+    an ellipsoid phantom on an n_vox^3 grid, in pixel units (the FP32 least-squares
+    data of the differentiation workload).  Returns (y, angles, center)."""
+    import torch
+    half = n_vox / 2
+    center = n_vox / 2
+    ell = ellipsoids_3d(seed, n_ellipsoids)
+    ang = uniform_angles(n_angles)
+    z0 = n_vox // 2 - n_slices // 2
+    p = chord_sinogram_volume(ell, range(z0, z0 + n_slices), n_vox, ang, n_vox, center, half, device=device,
+                              dtype=torch.float32)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(np.random.SeedSequence([seed, 3]).generate_state(1)[0]))
+    y = noisy_line_integrals_torch(p, flat_level, g) * half  # pixel units: line integral of a per-pixel density
+    return y.contiguous(), ang, center

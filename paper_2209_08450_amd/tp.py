@@ -176,8 +176,8 @@ class Plan:
             _check(_plan_destroy(self._h))
             self._h = _c_vp()
 
-    def __del__(self):
-        if sys.is_finalizing():  # the HIP runtime may already be gone
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():  # the HIP runtime may already be gone
             return
         try:
             self.close()

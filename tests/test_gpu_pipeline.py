@@ -1,0 +1,122 @@
+"""GPU tests of the three-stream chunk pipeline and the autotuner."""
+import numpy as np
+import pytest
+
+from paper_2209_08450_amd import synth
+from tests._util import note, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2209_08450_amd import pipeline, tp, tune
+    s = synth.ellipsoid_scan_np(seed=7, n_angles=90, n_rows=100, n_det=128, center=63.5, n_dark=3, n_flat=4)
+    return tp, pipeline, tune, s
+
+
+def _monolithic(tp, plan, s, storage):
+    out = tp.fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), storage)
+    return to_host(out)
+
+
+def _source(s):
+    proj = s.proj.view(np.int16)
+    dark = s.dark.view(np.int16)
+    flat = s.flat.view(np.int16)
+
+    def fill(z0, z1, p, d, f):
+        np.copyto(p.numpy(), proj[:, z0:z1, :])
+        np.copyto(d.numpy(), dark[:, z0:z1, :])
+        np.copyto(f.numpy(), flat[:, z0:z1, :])
+    return fill
+
+
+def _sink(result):
+    def put(z0, z1, vol):
+        result[z0:z1] = vol.numpy()
+    return put
+
+
+@pytest.mark.parametrize("graphs,poison,storage", [(True, False, "f16"), (False, True, "f16"),
+                                                   (True, True, "f32"), (True, False, "bf16")])
+def test_pipeline_bitwise_equals_monolithic(env, graphs, poison, storage):
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    want = _monolithic(tp, plan, s, storage)
+    chunks = pipeline.uneven_chunks(100, (7, 13, 32))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, storage=storage, use_graphs=graphs,
+                                poison=poison)
+    got = np.full((100, 128, 128), np.nan, np.float32)
+    note(f"pipeline graphs={graphs} poison={poison} {storage}")
+    st = pl.run(chunks, _source(s), _sink(got))
+    assert st.chunks == len(chunks) and st.rows == 100
+    if graphs:
+        assert st.graph_replays == len(chunks)
+    assert np.array_equal(got, want)
+
+
+def test_graph_replays_repeat_with_eager_work_between(env):
+    import torch
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    want = _monolithic(tp, plan, s, "f16")
+    chunks = pipeline.uneven_chunks(100, (32, 64))
+    pl = pipeline.ChunkPipeline(plan, max_rows=64, n_dark=3, n_flat=4, storage="f16", use_graphs=True)
+    for rep in range(3):
+        note(f"pipeline replay round {rep}")
+        got = np.zeros((100, 128, 128), np.float32)
+        pl.run(chunks, _source(s), _sink(got))
+        assert np.array_equal(got, want), rep
+        # eager work and synchronisation of the program between replays
+        _monolithic(tp, plan, s, "f32")
+        torch.cuda.synchronize()
+    assert pl.stats.graphs_captured == len({(k % 2, z1 - z0) for k, (z0, z1) in enumerate(chunks)})
+
+
+def test_source_failure_names_chunk_and_pipeline_recovers(env):
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    chunks = pipeline.uneven_chunks(100, (32,))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, storage="f16")
+    good = _source(s)
+
+    def bad(z0, z1, p, d, f):
+        if z0 >= 64:
+            raise OSError("read failed")
+        good(z0, z1, p, d, f)
+
+    note("pipeline source failure")
+    with pytest.raises(RuntimeError, match=r"chunk 2 \(rows \[64, 96\)\)"):
+        pl.run(chunks, bad, lambda *a: None)
+    got = np.zeros((100, 128, 128), np.float32)
+    pl.run(chunks, good, _sink(got))
+    assert np.array_equal(got, _monolithic(tp, plan, s, "f16"))
+
+
+def test_sink_failure_is_reported(env):
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    pl = pipeline.ChunkPipeline(plan, max_rows=50, n_dark=3, n_flat=4, storage="f16")
+
+    def sink(z0, z1, vol):
+        if z0 == 50:
+            raise ValueError("disk full")
+
+    note("pipeline sink failure")
+    with pytest.raises(RuntimeError, match=r"rows \[50, 100\)"):
+        pl.run([(0, 50), (50, 100)], _source(s), sink)
+
+
+def test_autotuner_on_device(env, tmp_path):
+    import torch
+    tp, _, tune, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    q = to_dev(np.random.default_rng(0).standard_normal((9, 90, 128)).astype(np.float32)).half()
+    ref = tp.backproject(plan, q)
+    note("autotuner f16")
+    k, a = tune.tune_backproject(plan, "f16", rows=8, reps=2, path=str(tmp_path / "t.json"))
+    assert (k, a) in tune.candidates("f16") and plan.get_tuning("f16") == (k, a)
+    assert torch.equal(tp.backproject(plan, q), ref)
