@@ -151,56 +151,82 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
 
 // Forward projection, gather form: wave = one angle, lanes = 64 consecutive
 // detector bins, K slices.  Each bin sweeps the image along the axis the ray
-// is closer to (rows when |cos| >= |sin|), takes the few voxels whose
-// coordinate can fall in [j - 1, j + 1), recomputes their exact (j0, w) with
-// the backprojector's expression and adds (1 - w) or w times the voxel.
+// is closer to (rows when |cos| >= |sin|).  On each line the voxels whose
+// coordinate can fall in [j - 1, j + 1) lie within 1/|c| <= sqrt(2) of the
+// line's crossing point; a fixed window of kCand candidates starting just
+// below it covers them with margin (the crossing point is an FP32 estimate,
+// good to ~1e-3 of a voxel), so every lane runs the same unrolled loop.  Each
+// candidate's exact (j0, w) comes from the backprojector's expression with
+// the tile tables of this angle staged in LDS; weights are (1 - w) for
+// j0 == j, w for j0 + 1 == j, else 0.  No atomics; every output is summed
+// by one lane in a fixed order.
+constexpr int kCand = 5;
+
 template <int K>
 __global__ void __launch_bounds__(256)
 k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restrict__ sino) {
+    // per wave: this angle's tile tables xi, xf, yi, yf (nb entries each)
+    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int jgroups = (g.n + 63) >> 6;
     const int a = (blockIdx.x / jgroups) * 4 + wv;
     const int j = (blockIdx.x % jgroups) * 64 + lane;
     const int z0 = blockIdx.y * K;
-    if (a >= g.na || j >= g.n) return;  // no block-level synchronisation below
-    const int na = g.na, N = g.N, half = N / 2;
+    const int na = g.na, N = g.N, nb = g.nb, half = N / 2;
+    int* sxi = reinterpret_cast<int*>(smem) + wv * 4 * nb;
+    float* sxf = reinterpret_cast<float*>(sxi + nb);
+    int* syi = reinterpret_cast<int*>(sxf + nb);
+    float* syf = reinterpret_cast<float*>(syi + nb);
+    if (a < na) {
+        for (int b = lane; b < nb; b += 64) {
+            sxi[b] = g.xi[b * na + a];
+            sxf[b] = g.xf[b * na + a];
+            syi[b] = g.yi[b * na + a];
+            syf[b] = g.yf[b * na + a];
+        }
+    }
+    __syncthreads();
+    if (a >= na || j >= g.n) return;  // no synchronisation below
     const float cs = g.cs[a], sn = g.sn[a];
     const bool rows_major = fabsf(cs) >= fabsf(sn);
     const float cmaj = rows_major ? cs : sn;   // coefficient of the swept (minor) coordinate
     const float cmin = rows_major ? sn : cs;   // coefficient of the major coordinate
-    const float reach = 1.0f / fabsf(cmaj);
+    const float inv = 1.0f / cmaj;
+    const float start = static_cast<float>(half) - 1.0f / fabsf(cmaj) - 0.01f;
+    const int nz = min(K, n_rows - z0);
+    const int64_t slab = static_cast<int64_t>(N) * N;
+    const float* v0p = vol + static_cast<int64_t>(z0) * slab;
     float acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0f;
-    int nz = min(K, n_rows - z0);
 
     for (int m = 0; m < N; ++m) {
-        // approximate centre of the footprint on this line (FP32; a superset of
-        // candidates is taken, the exact test below decides)
         const float um = static_cast<float>(m - half) * cmin + g.center_f;
-        const float c = (static_cast<float>(j) - um) / cmaj + static_cast<float>(half);
-        int lo = static_cast<int>(floorf(c - reach)) - 1;
-        int hi = static_cast<int>(floorf(c + reach)) + 1;
-        lo = max(lo, 0);
-        hi = min(hi, N - 1);
-        for (int v = lo; v <= hi; ++v) {
-            const int ix = rows_major ? v : m;
-            const int iy = rows_major ? m : v;
-            const int bx = ix >> 5, by = iy >> 5;
-            const float dx = static_cast<float>(ix & 31), dy = static_cast<float>(iy & 31);
-            const int bi = g.xi[bx * na + a] + g.yi[by * na + a];
-            const float bf = g.xf[bx * na + a] + g.yf[by * na + a];
+        const int lo = coord_floor(__builtin_fmaf(static_cast<float>(j) - um, inv, start));
+        const int bm = m >> 5;
+        const float dm = static_cast<float>(m & 31);
+#pragma unroll
+        for (int t = 0; t < kCand; ++t) {
+            const int v = lo + t;
+            const bool inside = v >= 0 && v < N;
+            const int vc = min(max(v, 0), N - 1);
+            const int bv = vc >> 5;
+            const float dv = static_cast<float>(vc & 31);
+            const int bx = rows_major ? bv : bm, by = rows_major ? bm : bv;
+            const float dx = rows_major ? dv : dm, dy = rows_major ? dm : dv;
+            const int bi = sxi[bx] + syi[by];
+            const float bf = sxf[bx] + syf[by];
             const float s = tile_offset(dx, dy, cs, sn, bf);
             const int j0 = bi + coord_floor(s);
             const float w = coord_frac(s);
-            float wt;
-            if (j0 == j) wt = 1.0f - w;
-            else if (j0 + 1 == j) wt = w;
-            else continue;
-            const int64_t off = static_cast<int64_t>(iy) * N + ix;
+            float wt = (j0 == j) ? 1.0f - w : ((j0 + 1 == j) ? w : 0.0f);
+            wt = inside ? wt : 0.0f;
+            const int ix = rows_major ? vc : m, iy = rows_major ? m : vc;
+            const float* p = v0p + static_cast<int64_t>(iy) * N + ix;
+            if (wt != 0.0f) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (k < nz) acc[k] = __builtin_fmaf(wt, vol[(static_cast<int64_t>(z0 + k) * N) * N + off], acc[k]);
+                for (int k = 0; k < K; ++k)
+                    if (k < nz) acc[k] = __builtin_fmaf(wt, p[k * slab], acc[k]);
             }
         }
     }
@@ -280,8 +306,14 @@ hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt,
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st) {
     constexpr int K = 4;
     const int jgroups = (g.n + 63) / 64;
+    const size_t lds = static_cast<size_t>(4) * 4 * g.nb * sizeof(int);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid(static_cast<unsigned>(jgroups * ((g.na + 3) / 4)), static_cast<unsigned>((n_rows + K - 1) / K));
-    hipLaunchKernelGGL((k_radon<K>), grid, dim3(256), 0, st, g, vol, n_rows, sino);
+    hipLaunchKernelGGL((k_radon<K>), grid, dim3(256), lds, st, g, vol, n_rows, sino);
     return hipGetLastError();
 }
 

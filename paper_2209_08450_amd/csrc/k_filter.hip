@@ -178,6 +178,258 @@ k_norm_filter(RawInput in, const float* __restrict__ dmean, const float* __restr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant for 1024 <= L <= 8192 (16384 would spill): B = L/16 threads, thread t
+// holds the 16 elements t + B*s (s = 0..15) in registers.  Stockham passes of
+// radix 16 (and one radix 2/4/8 pass when log2 L is not a multiple of 4):
+// in a radix-R pass thread t runs 16/R butterflies j = t + B*c; butterfly j
+// needs elements j + (L/R) r = t + B*(c + (16/R) r), i.e. its own slots, so
+// every pass reads registers, and only the pass outputs are exchanged
+// through LDS (written at the Stockham destinations, read back at t + B*s).
+// After the last pass the outputs j + (L/R) r are again the thread's own
+// slots, in natural order, so the spectrum is multiplied by H and the
+// inverse transform starts without an exchange; loading (with normalisation
+// and edge padding) and the cropped store go straight between HBM and
+// registers.
+// ---------------------------------------------------------------------------
+template <int R> struct Dft;
+template <> struct Dft<2> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+template <> struct Dft<4> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const float2 a2 = cadd(v[1], v[3]), a3 = cmul_mi(csub(v[1], v[3]));
+        v[0] = cadd(a0, a2);
+        v[1] = cadd(a1, a3);
+        v[2] = csub(a0, a2);
+        v[3] = csub(a1, a3);
+    }
+};
+// exp(-2 pi i k / R) for R in {8, 16}, k < R/2 (FP32 roundings of the exact values)
+template <int R>
+__device__ __forceinline__ float2 wconst(int k) {
+    constexpr float c1 = 0.923879532511286756f, s1 = 0.382683432365089772f, h = 0.707106781186547524f;
+    if (R == 8) {
+        switch (k) {
+            case 0: return make_float2(1.0f, 0.0f);
+            case 1: return make_float2(h, -h);
+            case 2: return make_float2(0.0f, -1.0f);
+            default: return make_float2(-h, -h);
+        }
+    }
+    switch (k) {
+        case 0: return make_float2(1.0f, 0.0f);
+        case 1: return make_float2(c1, -s1);
+        case 2: return make_float2(h, -h);
+        case 3: return make_float2(s1, -c1);
+        case 4: return make_float2(0.0f, -1.0f);
+        case 5: return make_float2(-s1, -c1);
+        case 6: return make_float2(-h, -h);
+        default: return make_float2(-c1, -s1);
+    }
+}
+template <int R> struct Dft {
+    __device__ __forceinline__ static void run(float2* v) {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        Dft<R / 2>::run(e);
+        Dft<R / 2>::run(o);
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            const float2 t = (k == 0) ? o[k] : cmul(o[k], wconst<R>(k));
+            v[k] = cadd(e[k], t);
+            v[k + R / 2] = csub(e[k], t);
+        }
+    }
+};
+
+constexpr int kRegPts = 16;
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+// One Stockham pass of radix R over the 16 register slots; Ns = product of
+// the previous radices.  If LAST, outputs stay in the slots; otherwise they
+// are written to LDS at their Stockham destinations.
+template <int L, int R, bool LAST>
+__device__ __forceinline__ void reg_pass(float2 (&x)[kRegPts], float2* lds, int Ns, const float2* __restrict__ tw) {
+    constexpr int B = L / kRegPts;
+    constexpr int NBF = kRegPts / R;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < NBF; ++c) {
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = x[c + NBF * r];
+        const int j = t + B * c;
+        const int k = j & (Ns - 1);
+        if (Ns > 1) {
+            const int step = k * (L / (Ns * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[step * r]);
+        }
+        Dft<R>::run(v);
+        if (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[c + NBF * r] = v[r];
+        } else {
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_pad(base + Ns * r)] = v[r];
+        }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void reg_exchange(float2 (&x)[kRegPts], float2* lds) {
+    constexpr int B = L / kRegPts;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) x[s] = lds[lds_pad(threadIdx.x + B * s)];
+    __syncthreads();
+}
+
+// Forward DFT of the register-held sequence (slots: element t + B*s in, X[t + B*s] out).
+template <int L>
+__device__ __forceinline__ void reg_fft(float2 (&x)[kRegPts], float2* lds, const float2* __restrict__ tw) {
+    static_assert(L >= 1024 && L <= 16384, "register FFT covers 1024..16384");
+    constexpr int log2L = (L == 1024) ? 10 : (L == 2048) ? 11 : (L == 4096) ? 12 : (L == 8192) ? 13 : 14;
+    constexpr int rem = 1 << (log2L - 8 - ((log2L >= 12) ? 4 : 0));  // radix of the pass after the 16s
+    if constexpr (log2L < 12) {
+        // 16 x 16 x rem, rem in {4, 8}
+        reg_pass<L, 16, false>(x, lds, 1, tw);
+        reg_exchange<L>(x, lds);
+        reg_pass<L, 16, false>(x, lds, 16, tw);
+        reg_exchange<L>(x, lds);
+        reg_pass<L, rem, true>(x, lds, 256, tw);
+    } else if constexpr (log2L == 12) {
+        reg_pass<L, 16, false>(x, lds, 1, tw);
+        reg_exchange<L>(x, lds);
+        reg_pass<L, 16, false>(x, lds, 16, tw);
+        reg_exchange<L>(x, lds);
+        reg_pass<L, 16, true>(x, lds, 256, tw);
+    } else {
+        // 16 x 16 x 16 x rem, rem in {2, 4}
+        reg_pass<L, 16, false>(x, lds, 1, tw);
+        reg_exchange<L>(x, lds);
+        reg_pass<L, 16, false>(x, lds, 16, tw);
+        reg_exchange<L>(x, lds);
+        reg_pass<L, 16, false>(x, lds, 256, tw);
+        reg_exchange<L>(x, lds);
+        reg_pass<L, (L >> 12), true>(x, lds, 4096, tw);
+    }
+}
+
+// Multiply the spectrum by H/L and conjugate, transform again: slots then hold
+// y = conj of (IFFT(H . FFT(u)) * L) / L, i.e. (row0, -row1).
+template <int L>
+__device__ __forceinline__ void reg_filter(float2 (&x)[kRegPts], float2* lds, const FilterTables& ft) {
+    constexpr int B = L / kRegPts;
+    reg_fft<L>(x, lds, ft.tw);
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const float h = ft.H[threadIdx.x + B * s];
+        x[s] = make_float2(x[s].x * h, 0.0f - x[s].y * h);
+    }
+    // no barrier needed: the forward transform's last LDS reads were followed
+    // by one, and its last pass ran in registers
+    reg_fft<L>(x, lds, ft.tw);
+}
+
+template <int L, typename TI, typename TO>
+__global__ void __launch_bounds__(L / kRegPts)
+k_filter_reg(const TI* in, TO* out, int64_t n_lines, int n, int off, FilterTables ft) {
+    extern __shared__ float2 lds[];
+    constexpr int B = L / kRegPts;
+    const int t = threadIdx.x;
+    const int64_t l0 = 2 * static_cast<int64_t>(blockIdx.x);
+    const bool has1 = l0 + 1 < n_lines;
+    const TI* r0 = in + l0 * n;
+    const TI* r1 = r0 + n;
+    const float e00 = load_as_float(r0, 0), e01 = load_as_float(r0, n - 1);
+    const float e10 = has1 ? load_as_float(r1, 0) : 0.0f, e11 = has1 ? load_as_float(r1, n - 1) : 0.0f;
+    float2 x[kRegPts];
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int j = t + B * s - off;
+        if (j < 0) x[s] = make_float2(e00, e10);
+        else if (j >= n) x[s] = make_float2(e01, e11);
+        else x[s] = make_float2(load_as_float(r0, j), has1 ? load_as_float(r1, j) : 0.0f);
+    }
+    reg_filter<L>(x, lds, ft);
+    TO* o0 = out + l0 * n;
+    TO* o1 = o0 + n;
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int j = t + B * s - off;
+        if (j >= 0 && j < n) {
+            store_from_float(o0, j, x[s].x);
+            if (has1) store_from_float(o1, j, 0.0f - x[s].y);
+        }
+    }
+}
+
+__device__ __forceinline__ float neglog(float P, float d, float e) {
+    return 0.0f - logf(fmaxf((P - d) / e, kMinTransmission));
+}
+
+template <int L, typename TO>
+__global__ void __launch_bounds__(L / kRegPts)
+k_norm_filter_reg(RawInput in, const float* __restrict__ dmean, const float* __restrict__ den, int n_angles, int n,
+                  int off, FilterTables ft, TO* out) {
+    extern __shared__ float2 lds[];
+    constexpr int B = L / kRegPts;
+    const int t = threadIdx.x;
+    const int pairs = (n_angles + 1) >> 1;
+    const int r = blockIdx.x / pairs;
+    const int a0 = 2 * (blockIdx.x - r * pairs);
+    const bool has1 = a0 + 1 < n_angles;
+    const uint16_t* p0 = in.proj + a0 * in.proj_stride + static_cast<int64_t>(r) * n;
+    const uint16_t* p1 = p0 + in.proj_stride;
+    const float* dm = dmean + static_cast<int64_t>(r) * n;
+    const float* dn = den + static_cast<int64_t>(r) * n;
+    // edge values for the padding
+    const float e00 = neglog(static_cast<float>(p0[0]), dm[0], dn[0]);
+    const float e01 = neglog(static_cast<float>(p0[n - 1]), dm[n - 1], dn[n - 1]);
+    const float e10 = has1 ? neglog(static_cast<float>(p1[0]), dm[0], dn[0]) : 0.0f;
+    const float e11 = has1 ? neglog(static_cast<float>(p1[n - 1]), dm[n - 1], dn[n - 1]) : 0.0f;
+    float2 x[kRegPts];
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int j = t + B * s - off;
+        if (j < 0) {
+            x[s] = make_float2(e00, e10);
+        } else if (j >= n) {
+            x[s] = make_float2(e01, e11);
+        } else {
+            const float d = dm[j], e = dn[j];
+            x[s] = make_float2(neglog(static_cast<float>(p0[j]), d, e),
+                               has1 ? neglog(static_cast<float>(p1[j]), d, e) : 0.0f);
+        }
+    }
+    reg_filter<L>(x, lds, ft);
+    TO* o0 = out + (static_cast<int64_t>(r) * n_angles + a0) * n;
+    TO* o1 = o0 + n;
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int j = t + B * s - off;
+        if (j >= 0 && j < n) {
+            store_from_float(o0, j, x[s].x);
+            if (has1) store_from_float(o1, j, 0.0f - x[s].y);
+        }
+    }
+}
+
+size_t reg_lds_bytes(int L) { return static_cast<size_t>(L + L / 16) * sizeof(float2); }
+
 int filter_block(int L) {
     int b = L / 16;
     if (b < 64) b = 64;
@@ -192,16 +444,41 @@ hipError_t ensure_lds(K kernel, size_t bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
+template <int L, typename K>
+hipError_t launch_reg(K kernel, dim3 grid, hipStream_t st, size_t& lds) {
+    lds = reg_lds_bytes(L);
+    return ensure_lds(kernel, lds);
+}
+
 template <typename TI, typename TO>
 hipError_t launch_filter_t(const void* in, void* out, int64_t n_lines, int n, const FilterTables& ft,
                            hipStream_t st) {
-    const size_t lds = static_cast<size_t>(ft.L) * sizeof(float2);
-    hipError_t e = ensure_lds(k_filter<TI, TO>, lds);
-    if (e != hipSuccess) return e;
     const int off = (ft.L - n) / 2;
     const int64_t blocks = (n_lines + 1) / 2;
-    hipLaunchKernelGGL((k_filter<TI, TO>), dim3(static_cast<unsigned>(blocks)), dim3(filter_block(ft.L)),
-                       lds, st, static_cast<const TI*>(in), static_cast<TO*>(out), n_lines, n, off, ft);
+    const dim3 grid(static_cast<unsigned>(blocks));
+    const TI* pin = static_cast<const TI*>(in);
+    TO* pout = static_cast<TO*>(out);
+    size_t lds = 0;
+    hipError_t e = hipSuccess;
+#define TP_REG_CASE(LL)                                                                                    \
+    case LL:                                                                                              \
+        e = launch_reg<LL>(k_filter_reg<LL, TI, TO>, grid, st, lds);                                      \
+        if (e != hipSuccess) return e;                                                                    \
+        hipLaunchKernelGGL((k_filter_reg<LL, TI, TO>), grid, dim3(LL / kRegPts), lds, st, pin, pout, n_lines, \
+                           n, off, ft);                                                                   \
+        return hipGetLastError();
+    switch (ft.L) {
+        TP_REG_CASE(1024)
+        TP_REG_CASE(2048)
+        TP_REG_CASE(4096)
+        TP_REG_CASE(8192)
+        default: break;
+    }
+#undef TP_REG_CASE
+    lds = static_cast<size_t>(ft.L) * sizeof(float2);
+    e = ensure_lds(k_filter<TI, TO>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_filter<TI, TO>), grid, dim3(filter_block(ft.L)), lds, st, pin, pout, n_lines, n, off, ft);
     return hipGetLastError();
 }
 
@@ -219,13 +496,32 @@ hipError_t launch_filter_in(const void* in, tp_dtype out_dt, void* out, int64_t 
 template <typename TO>
 hipError_t launch_norm_filter_t(const RawInput& in, const float* dmean, const float* den, int n_angles,
                                 int n_rows, int n, const FilterTables& ft, void* out, hipStream_t st) {
-    const size_t lds = static_cast<size_t>(ft.L) * sizeof(float2);
-    hipError_t e = ensure_lds(k_norm_filter<TO>, lds);
-    if (e != hipSuccess) return e;
     const int off = (ft.L - n) / 2;
     const int64_t blocks = static_cast<int64_t>(n_rows) * ((n_angles + 1) / 2);
-    hipLaunchKernelGGL((k_norm_filter<TO>), dim3(static_cast<unsigned>(blocks)), dim3(filter_block(ft.L)),
-                       lds, st, in, dmean, den, n_angles, n, off, ft, static_cast<TO*>(out));
+    const dim3 grid(static_cast<unsigned>(blocks));
+    TO* pout = static_cast<TO*>(out);
+    size_t lds = 0;
+    hipError_t e = hipSuccess;
+#define TP_REG_CASE(LL)                                                                                    \
+    case LL:                                                                                              \
+        e = launch_reg<LL>(k_norm_filter_reg<LL, TO>, grid, st, lds);                                     \
+        if (e != hipSuccess) return e;                                                                    \
+        hipLaunchKernelGGL((k_norm_filter_reg<LL, TO>), grid, dim3(LL / kRegPts), lds, st, in, dmean, den, \
+                           n_angles, n, off, ft, pout);                                                   \
+        return hipGetLastError();
+    switch (ft.L) {
+        TP_REG_CASE(1024)
+        TP_REG_CASE(2048)
+        TP_REG_CASE(4096)
+        TP_REG_CASE(8192)
+        default: break;
+    }
+#undef TP_REG_CASE
+    lds = static_cast<size_t>(ft.L) * sizeof(float2);
+    e = ensure_lds(k_norm_filter<TO>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_norm_filter<TO>), grid, dim3(filter_block(ft.L)), lds, st, in, dmean, den, n_angles, n,
+                       off, ft, pout);
     return hipGetLastError();
 }
 

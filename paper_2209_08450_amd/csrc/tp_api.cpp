@@ -175,7 +175,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     const int N = g->n_vox ? g->n_vox : g->n_det;
     if (default_pad_len(g->n_det) > kMaxPadLen)
         return fail(TP_EUNSUPPORTED, "n_det=%d needs pad length > %d", g->n_det, kMaxPadLen);
-    if (N > 32768) return fail(TP_EUNSUPPORTED, "n_vox=%d too large", N);
+    if (N > 32768) return fail(TP_EUNSUPPORTED, "n_vox=%d too large (limit 32768)", N);
     for (int a = 0; a < g->n_angles; ++a)
         if (!std::isfinite(g->angles[a])) return fail(TP_EINVAL, "angle %d is not finite", a);
     // the detector coordinate must stay well inside int32 and the FP32 offset small
