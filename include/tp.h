@@ -83,10 +83,10 @@ tp_status tp_plan_destroy(tp_plan* plan);
 /* Tuning of the backprojection kernel for one storage type of its input
  * (results are bitwise identical for every legal choice: each slice always
  * sums its angles in order).
- *   slices_per_block in {1, 2, 4, 8}: slices sharing one coordinate evaluation;
+ *   slices_per_block in {1, 2, 4, 8, 16}: slices sharing one coordinate evaluation;
  *   angles_per_block in {8, 16, 32, 64}: angles staged in LDS per step;
  *   the staged block, angles x 48 bins x slices x 4 bytes (2 for F16), must
- *   fit in 160 KiB.  Defaults: F16 (8, 32); F32 and BF16 (8, 16). */
+ *   fit in 160 KiB.  Defaults: F16 (16, 16); F32 and BF16 (8, 16). */
 tp_status tp_plan_set_tuning(tp_plan* plan, tp_dtype storage, int32_t slices_per_block,
                              int32_t angles_per_block);
 tp_status tp_plan_get_tuning(const tp_plan* plan, tp_dtype storage, int32_t* slices_per_block,

@@ -25,6 +25,8 @@
 // one read of the two bins' K-slice groups (16-byte LDS reads), then two
 // FMAs per slice (v_fma_mix_f32 reads FP16 operands directly).  Every slice
 // sums its angles in order, so results do not depend on K or A.
+#include <type_traits>
+
 #include "tp_internal.h"
 
 namespace tp {
@@ -103,9 +105,12 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
                 U q[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    float v = 0.0f;
-                    if (on && k < kz) v = ld(rows0 + (static_cast<int64_t>(k) * na + ag) * n, j);
-                    q[k] = static_cast<U>(v);
+                    const T* row = rows0 + (static_cast<int64_t>(k) * na + ag) * n;
+                    if constexpr (std::is_same<T, U>::value) {
+                        q[k] = (on && k < kz) ? row[j] : static_cast<U>(0.0f);  // raw copy
+                    } else {
+                        q[k] = (on && k < kz) ? ld(row, j) : 0.0f;  // bf16 widened
+                    }
                 }
                 copy_group<BIN, (BIN < 16 ? BIN : 16)>(smem + (a * kWin + lane) * BIN, q);
             }
@@ -275,6 +280,7 @@ hipError_t launch_bp_k(const GeoTables& g, const void* filt, int n_rows, float s
         case 2: return launch_bp_a<T, 2>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
         case 4: return launch_bp_a<T, 4>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
         case 8: return launch_bp_a<T, 8>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
+        case 16: return launch_bp_a<T, 16>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
     }
     return hipErrorInvalidValue;
 }

@@ -22,8 +22,8 @@ struct tp_plan {
     tp::GeoTables geo{};
     tp::FilterTables filt{};
     // backprojection tuning per storage type (F32, F16, BF16)
-    int bp_k[3] = {8, 8, 8};
-    int bp_a[3] = {16, 32, 16};
+    int bp_k[3] = {8, 16, 8};
+    int bp_a[3] = {16, 16, 16};
 };
 
 namespace {
@@ -279,8 +279,8 @@ tp_status tp_plan_set_tuning(tp_plan* plan, tp_dtype storage, int32_t slices_per
     if (!plan) return fail(TP_EINVAL, "plan is null");
     if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
     const int k = slices_per_block, a = angles_per_block;
-    if (!(k == 1 || k == 2 || k == 4 || k == 8))
-        return fail(TP_EINVAL, "slices_per_block=%d not in {1,2,4,8}", k);
+    if (!(k == 1 || k == 2 || k == 4 || k == 8 || k == 16))
+        return fail(TP_EINVAL, "slices_per_block=%d not in {1,2,4,8,16}", k);
     if (!(a == 8 || a == 16 || a == 32 || a == 64))
         return fail(TP_EINVAL, "angles_per_block=%d not in {8,16,32,64}", a);
     if (tp::backproject_lds_bytes(storage, k, a) > kMaxLds)

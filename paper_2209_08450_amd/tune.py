@@ -13,7 +13,7 @@ import json
 import os
 import tempfile
 
-SLICES = (1, 2, 4, 8)
+SLICES = (1, 2, 4, 8, 16)
 ANGLES = (8, 16, 32, 64)
 LDS_BYTES = 160 * 1024
 WINDOW = 48

@@ -98,7 +98,7 @@ def test_tuning_variants_are_bitwise_identical(tp):
     plan = tp.Plan(ang, n, c, N)
     for st, q in (("f32", q32), ("f16", q32.half()), ("bf16", q32.bfloat16())):
         ref = None
-        for k in (1, 2, 4, 8):
+        for k in (1, 2, 4, 8, 16):
             for a in (8, 16, 32, 64):
                 try:
                     plan.set_tuning(st, k, a)

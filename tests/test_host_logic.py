@@ -27,7 +27,7 @@ def test_tuner_legal_candidates():
     c32 = tune.candidates("f32")
     assert (8, 64) in c16 and (8, 64) in c32  # 8*64*48*4 + 1 KiB = 99 KiB fits 160 KiB
     assert all(tune.legal("f32", k, a) for k, a in c32)
-    assert len(c16) == 16
+    assert len(c16) == 20 and (16, 64) in c16 and (16, 64) not in c32
 
 
 class FakePlan:
