@@ -62,6 +62,9 @@ def parse():
                     help="instead: the host-to-host three-stream pipeline over uneven chunks "
                          "(defaults become 3000 angles x 2048 rows x 4096 columns, FP16 storage)")
     ap.add_argument("--pattern", default="32,64,128", help="chunk sizes of the pipeline mode")
+    ap.add_argument("--single-launch", action="store_true",
+                    help="instead: one tp_fbp_chunk of the timed launch shape, then a 1 GiB device copy "
+                         "(a short program for hardware-counter runs; the copy calibrates the byte counters)")
     return ap.parse_args()
 
 
@@ -97,6 +100,8 @@ def main():
         sys.exit(2)
     if args.pipeline:
         return main_pipeline(args)
+    if args.single_launch:
+        return main_single_launch(args)
 
     import numpy as np
     import torch
@@ -262,6 +267,30 @@ def main():
     if "f16" in results and "f32" in results:
         out["speedup_f16_vs_f32"] = round(results["f32"]["s_per_volume"] / results["f16"]["s_per_volume"], 3)
     print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def main_single_launch(args):
+    import torch
+
+    from paper_2209_08450_amd import synth, tp
+
+    st = args.storage.split(",")[0]
+    n, na, rows = args.n, args.angles, args.chunk
+    scan = synth.ellipsoid_scan_torch(seed=2, n_angles=na, n_rows=rows, n_det=n, device="cuda", center=n / 2.0)
+    plan = tp.Plan(scan.angles, n, n / 2.0)
+    vol = torch.empty((rows, n, n), dtype=torch.float32, device="cuda")
+    ws = torch.empty(plan.fbp_workspace_bytes(rows, st), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    tp.fbp_chunk(plan, scan.proj, scan.dark, scan.flat, st, out=vol, workspace=ws)
+    torch.cuda.synchronize()
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)  # 1 GiB read + 1 GiB written
+    torch.cuda.synchronize()
+    print(json.dumps({"single_launch": {"storage": st, "rows": rows, "n": n, "angles": na,
+                                        "tuning": list(plan.get_tuning(st)), "copy_bytes": 1 << 30}}), flush=True)
     plan.close()
 
 
