@@ -62,6 +62,31 @@ __device__ __forceinline__ void copy_group(void* dst, const void* src) {
     }
 }
 
+// Tile of work-group `wg` among nb x nb tiles.  Work-groups are dispatched
+// round-robin over the 8 XCDs, so wg % 8 names the XCD; each XCD gets one
+// eighth of the grid (nb/2 x nb/4 tiles) and walks it in Morton order, so the
+// ~160 work-groups resident on an XCD at a time form a compact cluster whose
+// detector windows overlap in that XCD's L2.  Bijective for power-of-two
+// nb >= 8; other sizes use row-major order.
+__device__ __forceinline__ void tile_of(int wg, int nb, int& bx, int& by) {
+    if (nb >= 8 && (nb & (nb - 1)) == 0) {
+        const int part = wg & 7, q = wg >> 3;
+        const int hr = nb >> 2;                      // part is (2 hr) x hr tiles
+        const int sq = hr * hr;
+        const int half_x = q / sq;                   // left or right square of the part
+        int r = q - half_x * sq, sx = 0, sy = 0;
+        for (int bit = 0; (1 << (2 * bit)) < sq; ++bit) {
+            sx |= ((r >> (2 * bit)) & 1) << bit;
+            sy |= ((r >> (2 * bit + 1)) & 1) << bit;
+        }
+        bx = (part & 1) * (2 * hr) + half_x * hr + sx;
+        by = (part >> 1) * hr + sy;
+    } else {
+        bx = wg % nb;
+        by = wg / nb;
+    }
+}
+
 template <typename T, int K, int A>
 __global__ void __launch_bounds__(kBpThreads)
 k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, float* __restrict__ vol,
@@ -73,7 +98,8 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
     float4* sGeo = reinterpret_cast<float4*>(smem + A * kWin * BIN);          // [A] {bf, cos, sin, byte base}
 
     const int na = g.na, n = g.n, nb = g.nb;
-    const int bx = blockIdx.x % nb, by = blockIdx.x / nb;
+    int bx, by;
+    tile_of(blockIdx.x, nb, bx, by);
     const int z0 = blockIdx.y * K;
     const int kz = min(K, n_rows - z0);
     const int tid = threadIdx.x;
@@ -154,90 +180,157 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
     }
 }
 
-// Forward projection, gather form: wave = one angle, lanes = 64 consecutive
-// detector bins, K slices.  Each bin sweeps the image along the axis the ray
-// is closer to (rows when |cos| >= |sin|).  On each line the voxels whose
-// coordinate can fall in [j - 1, j + 1) lie within 1/|c| <= sqrt(2) of the
-// line's crossing point; a fixed window of kCand candidates starting just
-// below it covers them with margin (the crossing point is an FP32 estimate,
-// good to ~1e-3 of a voxel), so every lane runs the same unrolled loop.  Each
-// candidate's exact (j0, w) comes from the backprojector's expression with
-// the tile tables of this angle staged in LDS; weights are (1 - w) for
-// j0 == j, w for j0 + 1 == j, else 0.  No atomics; every output is summed
-// by one lane in a fixed order.
+// Forward projection, gather form.  Work-group: 4 waves = 4 neighbouring
+// angles that sweep the same axis (the plan lists angles grouped by sweep
+// axis and sorted), lanes = 64 consecutive detector bins, K slices.  Each bin
+// sweeps the image along the axis the ray is closer to (rows when |cos| >=
+// |sin|).  On each line the voxels whose coordinate can fall in [j-1, j+1)
+// lie within 1/|c| <= sqrt(2) of the line's crossing point; a fixed window of
+// kCand candidates starting just below it covers them with margin (the
+// crossing point is an FP32 estimate good to ~1e-3 voxel), so every lane runs
+// the same unrolled loop.  Each candidate's exact (j0, w) comes from the
+// backprojector's expression with the angle's tile tables staged in LDS;
+// weights are (1-w) for j0 == j, w for j0+1 == j, else 0.
+// Lines are processed in blocks of kRadonLines: the work-group stages the
+// strip its 4 angles x 64 bins can touch on those lines (all K slices,
+// [line][position][slice]) into LDS with coalesced loads, so each voxel is
+// fetched once per work-group instead of once per bin and angle.  A strip
+// wider than kRadonStrip (sparse angle sets) is read from global memory
+// instead, with the same arithmetic and order.  No atomics: every output is
+// summed by one lane, lines ascending, candidates ascending.
 constexpr int kCand = 5;
+constexpr int kRadonSlices = 8;
+constexpr int kRadonLines = 4;
+constexpr int kRadonStrip = 128;
 
 template <int K>
 __global__ void __launch_bounds__(256)
 k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restrict__ sino) {
-    // per wave: this angle's tile tables xi, xf, yi, yf (nb entries each)
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_lo[4][4];
+    const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
+    float* strip = reinterpret_cast<float*>(smem);                        // [lines][kRadonStrip][K]
+    int* tabs = reinterpret_cast<int*>(strip + kRadonLines * kRadonStrip * K);  // [4 waves][4][nb]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int jgroups = (g.n + 63) >> 6;
-    const int a = (blockIdx.x / jgroups) * 4 + wv;
-    const int j = (blockIdx.x % jgroups) * 64 + lane;
+    const int jb = (blockIdx.x % jgroups) * 64;
+    const int grp = blockIdx.x / jgroups;
+    const int groups_rows = (g.n_rows_major + 3) / 4;
+    const bool rows_major = grp < groups_rows;
+    const int e0 = rows_major ? grp * 4 : g.n_rows_major + (grp - groups_rows) * 4;
+    const int e_end = rows_major ? min(g.n_rows_major, e0 + 4) : min(na, e0 + 4);
+    const int e = e0 + wv;
+    const bool active = e < e_end;
+    const int a = active ? g.order[e] : g.order[e0];
+    const int j = jb + lane;
     const int z0 = blockIdx.y * K;
-    const int na = g.na, N = g.N, nb = g.nb, half = N / 2;
-    int* sxi = reinterpret_cast<int*>(smem) + wv * 4 * nb;
+    const int nz = min(K, n_rows - z0);
+    int* sxi = tabs + wv * 4 * nb;
     float* sxf = reinterpret_cast<float*>(sxi + nb);
     int* syi = reinterpret_cast<int*>(sxf + nb);
     float* syf = reinterpret_cast<float*>(syi + nb);
-    if (a < na) {
-        for (int b = lane; b < nb; b += 64) {
-            sxi[b] = g.xi[b * na + a];
-            sxf[b] = g.xf[b * na + a];
-            syi[b] = g.yi[b * na + a];
-            syf[b] = g.yf[b * na + a];
-        }
+    for (int b = lane; b < nb; b += 64) {
+        sxi[b] = g.xi[b * na + a];
+        sxf[b] = g.xf[b * na + a];
+        syi[b] = g.yi[b * na + a];
+        syf[b] = g.yf[b * na + a];
     }
-    __syncthreads();
-    if (a >= na || j >= g.n) return;  // no synchronisation below
     const float cs = g.cs[a], sn = g.sn[a];
-    const bool rows_major = fabsf(cs) >= fabsf(sn);
     const float cmaj = rows_major ? cs : sn;   // coefficient of the swept (minor) coordinate
-    const float cmin = rows_major ? sn : cs;   // coefficient of the major coordinate
+    const float cmin = rows_major ? sn : cs;   // coefficient of the line (major) coordinate
     const float inv = 1.0f / cmaj;
     const float start = static_cast<float>(half) - 1.0f / fabsf(cmaj) - 0.01f;
-    const int nz = min(K, n_rows - z0);
     const int64_t slab = static_cast<int64_t>(N) * N;
-    const float* v0p = vol + static_cast<int64_t>(z0) * slab;
+    const float* vz = vol + static_cast<int64_t>(z0) * slab;
     float acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0f;
 
-    for (int m = 0; m < N; ++m) {
-        const float um = static_cast<float>(m - half) * cmin + g.center_f;
-        const int lo = coord_floor(__builtin_fmaf(static_cast<float>(j) - um, inv, start));
-        const int bm = m >> 5;
-        const float dm = static_cast<float>(m & 31);
-#pragma unroll
-        for (int t = 0; t < kCand; ++t) {
-            const int v = lo + t;
-            const bool inside = v >= 0 && v < N;
-            const int vc = min(max(v, 0), N - 1);
-            const int bv = vc >> 5;
-            const float dv = static_cast<float>(vc & 31);
-            const int bx = rows_major ? bv : bm, by = rows_major ? bm : bv;
-            const float dx = rows_major ? dv : dm, dy = rows_major ? dm : dv;
-            const int bi = sxi[bx] + syi[by];
-            const float bf = sxf[bx] + syf[by];
-            const float s = tile_offset(dx, dy, cs, sn, bf);
-            const int j0 = bi + coord_floor(s);
-            const float w = coord_frac(s);
-            float wt = (j0 == j) ? 1.0f - w : ((j0 + 1 == j) ? w : 0.0f);
-            wt = inside ? wt : 0.0f;
-            const int ix = rows_major ? vc : m, iy = rows_major ? m : vc;
-            const float* p = v0p + static_cast<int64_t>(iy) * N + ix;
-            if (wt != 0.0f) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (k < nz) acc[k] = __builtin_fmaf(wt, p[k * slab], acc[k]);
+    for (int m0 = 0; m0 < N; m0 += kRadonLines) {
+        const int mr = min(kRadonLines, N - m0);
+        // candidate starts at the block's corners (first/last bin, first/last line)
+        if (lane < 4) {
+            const int jj = min((lane & 1) ? jb + 63 : jb, g.n - 1);
+            const int mm = (lane & 2) ? m0 + mr - 1 : m0;
+            const float um = static_cast<float>(mm - half) * cmin + g.center_f;
+            s_lo[wv][lane] = coord_floor(__builtin_fmaf(static_cast<float>(jj) - um, inv, start));
+        }
+        __syncthreads();
+        int xmin = 1 << 30, xmax = -(1 << 30);
+        for (int w = 0; w < 4; ++w) {
+            if (e0 + w >= e_end) continue;
+            for (int c = 0; c < 4; ++c) {
+                xmin = min(xmin, s_lo[w][c]);
+                xmax = max(xmax, s_lo[w][c] + kCand - 1);
             }
         }
-    }
+        xmin = max(xmin - 1, 0);  // one voxel of margin for the FP32 corner estimates
+        xmax = min(xmax + 1, N - 1);
+        const int width = xmax - xmin + 1;
+        const bool staged = width > 0 && width <= kRadonStrip;
+        if (staged) {
+            for (int idx = threadIdx.x; idx < mr * width; idx += 256) {
+                const int r = idx / width, x = idx - r * width;
+                const int ix = rows_major ? xmin + x : m0 + r;
+                const int iy = rows_major ? m0 + r : xmin + x;
+                const float* p = vz + static_cast<int64_t>(iy) * N + ix;
+                float v[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (k < nz) sino[(static_cast<int64_t>(z0 + k) * na + a) * g.n + j] = acc[k];
+                for (int k = 0; k < K; ++k) v[k] = (k < nz) ? p[k * slab] : 0.0f;
+                float4* dst = reinterpret_cast<float4*>(strip + (r * kRadonStrip + x) * K);
+#pragma unroll
+                for (int q = 0; q < K / 4; ++q) dst[q] = reinterpret_cast<const float4*>(v)[q];
+            }
+        }
+        __syncthreads();
+        if (active && j < g.n) {
+            for (int r = 0; r < mr; ++r) {
+                const int m = m0 + r;
+                const float um = static_cast<float>(m - half) * cmin + g.center_f;
+                const int lo = coord_floor(__builtin_fmaf(static_cast<float>(j) - um, inv, start));
+                const int bm = m >> 5;
+                const float dm = static_cast<float>(m & 31);
+#pragma unroll
+                for (int t = 0; t < kCand; ++t) {
+                    const int v = lo + t;
+                    const bool inside = v >= 0 && v < N;
+                    const int vc = min(max(v, 0), N - 1);
+                    const int bv = vc >> 5;
+                    const float dv = static_cast<float>(vc & 31);
+                    const int bx = rows_major ? bv : bm, by = rows_major ? bm : bv;
+                    const float dx = rows_major ? dv : dm, dy = rows_major ? dm : dv;
+                    const int bi = sxi[bx] + syi[by];
+                    const float bf = sxf[bx] + syf[by];
+                    const float s = tile_offset(dx, dy, cs, sn, bf);
+                    const int j0 = bi + coord_floor(s);
+                    const float w = coord_frac(s);
+                    float wt = (j0 == j) ? 1.0f - w : ((j0 + 1 == j) ? w : 0.0f);
+                    wt = inside ? wt : 0.0f;
+                    if (wt != 0.0f) {
+                        float val[K];
+                        if (staged) {
+                            const int xo = min(max(vc - xmin, 0), kRadonStrip - 1);
+                            const float4* src = reinterpret_cast<const float4*>(strip + (r * kRadonStrip + xo) * K);
+#pragma unroll
+                            for (int q = 0; q < K / 4; ++q) reinterpret_cast<float4*>(val)[q] = src[q];
+                        } else {
+                            const int ix = rows_major ? vc : m, iy = rows_major ? m : vc;
+                            const float* p = vz + static_cast<int64_t>(iy) * N + ix;
+#pragma unroll
+                            for (int k = 0; k < K; ++k) val[k] = (k < nz) ? p[k * slab] : 0.0f;
+                        }
+#pragma unroll
+                        for (int k = 0; k < K; ++k) acc[k] = __builtin_fmaf(wt, val[k], acc[k]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active && j < g.n) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k < nz) sino[(static_cast<int64_t>(z0 + k) * na + a) * g.n + j] = acc[k];
     }
 }
 
@@ -310,15 +403,16 @@ hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt,
 }
 
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st) {
-    constexpr int K = 4;
+    constexpr int K = kRadonSlices;
     const int jgroups = (g.n + 63) / 64;
-    const size_t lds = static_cast<size_t>(4) * 4 * g.nb * sizeof(int);
+    const int groups = (g.n_rows_major + 3) / 4 + (g.na - g.n_rows_major + 3) / 4;
+    const size_t lds = sizeof(float) * kRadonLines * kRadonStrip * K + sizeof(int) * 16 * static_cast<size_t>(g.nb);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
-    const dim3 grid(static_cast<unsigned>(jgroups * ((g.na + 3) / 4)), static_cast<unsigned>((n_rows + K - 1) / K));
+    const dim3 grid(static_cast<unsigned>(jgroups * groups), static_cast<unsigned>((n_rows + K - 1) / K));
     hipLaunchKernelGGL((k_radon<K>), grid, dim3(256), lds, st, g, vol, n_rows, sino);
     return hipGetLastError();
 }

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -201,9 +202,20 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
             yf[static_cast<size_t>(b) * na + a] = static_cast<float>(Y - fy);
         }
     }
+    // forward-projector grouping: angles sweeping rows first, then columns, each sorted by angle
+    std::vector<int> order;
+    order.reserve(na);
+    for (int a = 0; a < na; ++a)
+        if (std::fabs(cs[a]) >= std::fabs(sn[a])) order.push_back(a);
+    const int n_rows_major = static_cast<int>(order.size());
+    for (int a = 0; a < na; ++a)
+        if (!(std::fabs(cs[a]) >= std::fabs(sn[a]))) order.push_back(a);
+    auto by_angle = [&](int p, int q) { return g->angles[p] < g->angles[q] || (g->angles[p] == g->angles[q] && p < q); };
+    std::sort(order.begin(), order.begin() + n_rows_major, by_angle);
+    std::sort(order.begin() + n_rows_major, order.end(), by_angle);
     const size_t s_ang = align256(sizeof(float) * na);
     const size_t s_tab = align256(sizeof(float) * static_cast<size_t>(nb) * na);
-    const size_t total = 2 * s_ang + 4 * s_tab;
+    const size_t total = 3 * s_ang + 4 * s_tab;
 
     tp_plan* p = new (std::nothrow) tp_plan();
     if (!p) return fail(TP_ENOMEM, "host allocation failed");
@@ -224,6 +236,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     char* d_xf = d_xi + s_tab;
     char* d_yi = d_xf + s_tab;
     char* d_yf = d_yi + s_tab;
+    char* d_order = d_yf + s_tab;
     const size_t tb = sizeof(float) * static_cast<size_t>(nb) * na;
     e = hipMemcpy(d_cs, cs.data(), sizeof(float) * na, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_sn, sn.data(), sizeof(float) * na, hipMemcpyHostToDevice);
@@ -231,6 +244,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     if (e == hipSuccess) e = hipMemcpy(d_xf, xf.data(), tb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_yi, yi.data(), tb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_yf, yf.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_order, order.data(), sizeof(int) * na, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p->dev_block);
         delete p;
@@ -252,6 +266,8 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     p->geo.N = N;
     p->geo.nb = nb;
     p->geo.center_f = static_cast<float>(g->center);
+    p->geo.order = reinterpret_cast<const int*>(d_order);
+    p->geo.n_rows_major = n_rows_major;
     tp_status st = filter_tables(default_pad_len(g->n_det), &p->filt, nullptr);
     if (st != TP_OK) {
         (void)hipFree(p->dev_block);
@@ -383,7 +399,7 @@ tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtyp
 tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float* sino, void* stream) {
     if (!plan) return fail(TP_EINVAL, "plan is null");
     if (!vol || !sino) return fail(TP_EINVAL, "null buffer");
-    if (n_rows <= 0 || (n_rows + 3) / 4 > 65535) return fail(TP_EINVAL, "n_rows=%d out of range", n_rows);
+    if (n_rows <= 0 || (n_rows + 7) / 8 > 65535) return fail(TP_EINVAL, "n_rows=%d out of range", n_rows);
     hipError_t e = tp::launch_radon(plan->geo, vol, n_rows, sino, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "radon launch");
     return TP_OK;

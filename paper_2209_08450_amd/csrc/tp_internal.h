@@ -30,6 +30,9 @@ struct GeoTables {
     const float* yf;   // [nb][na]
     int na, n, N, nb;
     float center_f;    // FP32 rotation axis (only for candidate search in the forward projector)
+    const int* order;  // [na] angle indices: first the n_rows_major angles with |cos| >= |sin|,
+                       // then the rest, each group sorted by angle (forward projector grouping)
+    int n_rows_major;
 };
 
 struct FilterTables {
