@@ -62,6 +62,8 @@ def parse():
                     help="instead: the host-to-host three-stream pipeline over uneven chunks "
                          "(defaults become 3000 angles x 2048 rows x 4096 columns, FP16 storage)")
     ap.add_argument("--pattern", default="32,64,128", help="chunk sizes of the pipeline mode")
+    ap.add_argument("--no-ls", action="store_true",
+                    help="skip the differentiation section (forward projector, adjoint, 30 LS steps)")
     ap.add_argument("--single-launch", action="store_true",
                     help="instead: one tp_fbp_chunk of the timed launch shape, then a 1 GiB device copy "
                          "(a short program for hardware-counter runs; the copy calibrates the byte counters)")
@@ -228,6 +230,11 @@ def main():
                          f"normalise, filter, backproject in FP64), {cpu_t:.1f} s",
                "s_per_volume_extrapolated": round(cpu_t / cpu_slices * rows, 1)}
 
+    # ---------------- differentiation form: forward projector and least squares ----------------
+    ls = None
+    if not args.no_ls:
+        ls = bench_ls(plan_cls=tp.Plan, log=log)
+
     # ---------------- report ----------------
     head = storages[0]
     r = results[head]
@@ -262,12 +269,75 @@ def main():
                      "launch_ms": round(r["bp_launch_ms"], 3),
                      "flop_per_launch": FLOP_PER_UPDATE * bp_updates},
         "cpu_baseline": cpu,
+        "differentiation": ls,
         "paper_context": {"linerec_fp32_2048cubed_total_s_A100_incl_io": 80.0},
     }
     if "f16" in results and "f32" in results:
         out["speedup_f16_vs_f32"] = round(results["f32"]["s_per_volume"] / results["f16"]["s_per_volume"], 3)
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def bench_ls(plan_cls, log, n_slices=128, n_vox=1024, n_angles=900, steps=30):
+    """Forward projector R (tp_radon), its adjoint (tp_backproject, scale 1) and
+    30 gradient least-squares steps on 128 slices of 1024^2 from 900 angles of
+    noisy ellipsoid data; parity of R on one slice against the FP64 oracle and
+    the oracle's R timed on the host."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2209_08450_amd import autograd, synth, tp
+
+    y, ang, c = synth.ls_problem_torch(seed=4, n_slices=n_slices, n_vox=n_vox, n_angles=n_angles, device="cuda")
+    plan = plan_cls(ang, n_vox, c)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.rand((n_slices, n_vox, n_vox), generator=g, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_r = timed(lambda: tp.radon(plan, x))
+    t_bp = timed(lambda: tp.backproject(plan, y, scale=1.0))
+    upd = float(n_slices) * n_vox * n_vox * n_angles
+    log(f"forward projector {t_r:.2f} ms, adjoint {t_bp:.2f} ms per call ({n_slices}x{n_vox}^2x{n_angles})")
+    eta = autograd.step_size(plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, losses = autograd.ls_solve(plan, y, steps=steps, eta=eta)
+    torch.cuda.synchronize()
+    t_ls = time.perf_counter() - t0
+    log(f"{steps} LS steps: {t_ls:.2f} s, loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    # parity of R on one slice, and the oracle's R on the host
+    z = n_slices // 2
+    xs = x[z:z + 1].cpu().numpy().astype(np.float64)
+    got = tp.radon(plan, x[z:z + 1].contiguous()).cpu().numpy().astype(np.float64)
+    t1 = time.perf_counter()
+    want = oracle.radon(xs, ang, c, n_vox)
+    t_cpu = time.perf_counter() - t1
+    rel = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    achieved = FLOP_PER_UPDATE * upd / (t_r * 1e-3) / 1e12
+    plan.close()
+    return {
+        "workload": f"{n_slices} slices x {n_vox}^2 from {n_angles} angles, noisy ellipsoid line integrals",
+        "radon_ms": round(t_r, 3), "radon_gups": round(upd / t_r / 1e6, 1),
+        "adjoint_ms": round(t_bp, 3), "adjoint_gups": round(upd / t_bp / 1e6, 1),
+        "ls_steps": steps, "ls_s": round(t_ls, 3), "loss_first": losses[0], "loss_last": losses[-1],
+        "loss_monotone": all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:])),
+        "radon_rel_l2_vs_fp64_oracle_one_slice": rel,
+        "radon_roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4)},
+        "radon_cpu_oracle": {"value": round(float(n_vox) * n_vox * n_angles / t_cpu / 1e9, 3), "unit": UNIT,
+                             "cores": oracle.num_threads(), "sample": f"one slice, {t_cpu:.1f} s"},
+    }
 
 
 def main_single_launch(args):

@@ -173,3 +173,34 @@ def test_radon_mass_conservation(tp):
     note("radon mass")
     r = to_host(tp.radon(plan, to_dev(f))).astype(np.float64)
     assert np.allclose(r.sum(axis=2), f.astype(np.float64).sum(axis=(1, 2))[:, None], rtol=2e-6)
+
+
+def test_radon_sparse_angles_use_global_fallback(tp):
+    # 8 angles over 180 degrees on a 512^2 image: the strip a work-group's 4
+    # angles cross is far wider than the LDS buffer, so candidates are read
+    # from global memory; results must match the oracle all the same
+    N = n = 512
+    ang = synth.uniform_angles(8) + 0.05
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal((2, N, N)).astype(np.float32)
+    plan = tp.Plan(ang, n, n / 2 + 0.3, N)
+    note("radon sparse angles (global fallback)")
+    got = to_host(tp.radon(plan, to_dev(x)))
+    assert rel_l2(got, oracle.radon(x.astype(np.float64), ang, n / 2 + 0.3, n)) < 1e-5
+
+
+def test_unsorted_nonuniform_angles(tp):
+    # arbitrary order, full circle, repeated angle: the plan's grouping of
+    # angles by sweep axis must not change either projector's results
+    N, n = 96, 110
+    rng = np.random.default_rng(29)
+    ang = rng.uniform(0, 2 * math.pi, 41)
+    ang[7] = ang[3]
+    c = 54.6
+    plan = tp.Plan(ang, n, c, N)
+    x = rng.standard_normal((3, N, N)).astype(np.float32)
+    q = rng.standard_normal((3, 41, n)).astype(np.float32)
+    note("unsorted angles")
+    assert rel_l2(to_host(tp.radon(plan, to_dev(x))), oracle.radon(x.astype(np.float64), ang, c, n)) < 1e-5
+    assert rel_l2(to_host(tp.backproject(plan, to_dev(q), scale=1.0)),
+                  oracle.backproject(q.astype(np.float64), ang, c, N, scale=1.0)) < 1e-5
