@@ -15,6 +15,9 @@ Functions follow the paper (arXiv 2209.08450):
 * ``pad_len`` / ``ramp_kernel`` / ``ramp_response`` / ``filter_rows`` /
   ``filter_rows_direct`` -- padded one-dimensional filtering of detector rows
   by FFT (Section 2.2; padding discussion in Section 3).
+* ``filter_window`` / ``filter_kernel`` / ``filter_response`` -- the
+  Shepp-Logan and Parzen windows on the ramp (the filter choices of the
+  command-line interface, Section 2.4; Parzen for every result of Section 3).
 * ``backproject`` / ``backproject_points`` -- direct discretisation of the
   backprojection line integral with linear interpolation ("LineRec",
   Sections 2.2 and 3).
@@ -35,6 +38,10 @@ from .fbp import (  # noqa: F401
     pad_len,
     ramp_kernel,
     ramp_response,
+    FILTERS,
+    filter_window,
+    filter_kernel,
+    filter_response,
     pad_rows,
     filter_rows,
     filter_rows_direct,

@@ -133,6 +133,83 @@ def ramp_response(L: int) -> np.ndarray:
     return np.fft.fft(ramp_kernel(L)).real
 
 
+FILTERS = ("ramp", "shepp", "parzen")
+"""Filter windows: the paper's tool offers Shepp-Logan and Parzen (its default,
+used for every measurement in Section 3); plain ramp is the unwindowed case."""
+
+
+def filter_window(x: float, kind: str) -> float:
+    """Window W(x) on the ramp, x = |w| / (1/2) in [0, 1] (w in cycles per pixel).
+
+    Reading: the paper names the windows but gives no formula; the textbook
+    forms are taken.
+      ramp:   W = 1.
+      shepp:  W = sinc(x/2) = sin(pi x/2) / (pi x/2), so |w| W = |sin(pi w)| / pi,
+              the response of the Shepp-Logan kernel.
+      parzen: W = 1 - 6x^2 + 6|x|^3 for x <= 1/2, 2 (1 - x)^3 for 1/2 < x <= 1
+              (the Parzen / de la Vallee Poussin window, zero at Nyquist).
+    """
+    x = abs(float(x))
+    if kind == "ramp":
+        return 1.0
+    if kind == "shepp":
+        return 1.0 if x == 0.0 else math.sin(0.5 * math.pi * x) / (0.5 * math.pi * x)
+    if kind == "parzen":
+        if x <= 0.5:
+            return 1.0 - 6.0 * x * x + 6.0 * x ** 3
+        return 2.0 * (1.0 - x) ** 3 if x <= 1.0 else 0.0
+    raise ValueError(f"unknown filter {kind!r}")
+
+
+_WINDOW_KNOTS = {"ramp": (), "shepp": (), "parzen": (0.5,)}
+_kernel_cache: dict = {}
+
+
+def filter_kernel(L: int, kind: str = "ramp") -> np.ndarray:
+    """Windowed band-limited ramp h_W[m] = integral over |w| <= 1/2 of
+    |w| W(2|w|) exp(2 pi i w m) dw, for m in [-L/2, L/2), FFT order.
+
+    ramp: the closed form of ``ramp_kernel``.  Windowed kinds:
+    h_W[m] = 2 * integral_0^{1/2} w W(2w) cos(2 pi m w) dw by QUADPACK's
+    rule for cosine-weighted integrands (scipy.integrate.quad, weight='cos'),
+    once per smooth piece of the window.
+    """
+    if kind == "ramp":
+        return ramp_kernel(L)
+    if kind not in FILTERS:
+        raise ValueError(f"unknown filter {kind!r}")
+    key = (int(L), kind)
+    if key not in _kernel_cache:
+        import warnings
+
+        from scipy import integrate
+
+        edges = [0.0] + [0.5 * k for k in _WINDOW_KNOTS[kind]] + [0.5]
+        f = lambda w: w * filter_window(2.0 * w, kind)  # noqa: E731
+        half = np.empty(L // 2 + 1, dtype=np.float64)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", integrate.IntegrationWarning)
+            for m in range(L // 2 + 1):
+                tot = 0.0
+                for a, b in zip(edges[:-1], edges[1:]):
+                    if m == 0:
+                        v, _ = integrate.quad(f, a, b, epsabs=1e-17, epsrel=1e-13, limit=200)
+                    else:
+                        v, _ = integrate.quad(f, a, b, weight="cos", wvar=2.0 * math.pi * m, epsabs=1e-17,
+                                              epsrel=1e-13, limit=200)
+                    tot += v
+                half[m] = 2.0 * tot
+        m = np.arange(L, dtype=np.int64)
+        m = np.where(m < L // 2, m, m - L)
+        _kernel_cache[key] = half[np.abs(m)]
+    return _kernel_cache[key].copy()
+
+
+def filter_response(L: int, kind: str = "ramp") -> np.ndarray:
+    """H_W[k] = sum_m h_W[m] exp(-2 pi i k m / L) (FFT of ``filter_kernel``), real."""
+    return np.fft.fft(filter_kernel(L, kind)).real
+
+
 def pad_rows(p: np.ndarray, L: int):
     """Edge-replicating pad of the last axis from n to L, data at offset floor((L-n)/2).
 
@@ -149,17 +226,17 @@ def pad_rows(p: np.ndarray, L: int):
     return u, off
 
 
-def filter_rows(p: np.ndarray, L: int | None = None) -> np.ndarray:
-    """q = crop( IFFT( H * FFT( pad(p) ) ) ) along the last axis, FP64."""
+def filter_rows(p: np.ndarray, L: int | None = None, kind: str = "ramp") -> np.ndarray:
+    """q = crop( IFFT( H_W * FFT( pad(p) ) ) ) along the last axis, FP64."""
     n = p.shape[-1]
     L = pad_len(n) if L is None else L
     u, off = pad_rows(np.asarray(p, dtype=np.float64), L)
-    H = ramp_response(L)
+    H = filter_response(L, kind)
     y = np.fft.ifft(np.fft.fft(u, axis=-1) * H, axis=-1).real
     return np.ascontiguousarray(y[..., off:off + n])
 
 
-def filter_rows_direct(p: np.ndarray, L: int | None = None) -> np.ndarray:
+def filter_rows_direct(p: np.ndarray, L: int | None = None, kind: str = "ramp") -> np.ndarray:
     """Same result as ``filter_rows`` by direct circular convolution with h.
 
     y[off + j] = sum_k u[k] h[(off + j - k) mod L]; O(n L) per row, for small
@@ -168,7 +245,7 @@ def filter_rows_direct(p: np.ndarray, L: int | None = None) -> np.ndarray:
     n = p.shape[-1]
     L = pad_len(n) if L is None else L
     u, off = pad_rows(np.asarray(p, dtype=np.float64), L)
-    h = ramp_kernel(L)
+    h = filter_kernel(L, kind)
     k = np.arange(L)
     out = np.empty(p.shape[:-1] + (n,), dtype=np.float64)
     for j in range(n):
@@ -268,22 +345,24 @@ def _round_storage(x, storage):
     raise ValueError(storage)
 
 
-def fbp(proj, dark, flat, angles, center: float, N: int | None = None, storage: str | None = None):
+def fbp(proj, dark, flat, angles, center: float, N: int | None = None, storage: str | None = None,
+        kind: str = "ramp"):
     """FBP = backproject(filter(normalize(raw))), FP64, scale pi / n_angles.
 
     ``storage`` in {None/'f32', 'f16', 'bf16'} rounds the filtered rows to that
     type before backprojection (emulates reduced-precision storage with
     arithmetic kept in higher precision).  'f32' applies no rounding: the FP32
-    GPU path is compared against the unrounded FP64 result.
+    GPU path is compared against the unrounded FP64 result.  ``kind`` picks the
+    filter window (``FILTERS``).
     """
     p = normalize(proj, dark, flat)
     n = p.shape[-1]
-    q = filter_rows(p)
+    q = filter_rows(p, kind=kind)
     q = _round_storage(q, storage)
     return backproject(q, angles, center, n if N is None else N)
 
 
-def fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, storage=None):
+def fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, storage=None, kind="ramp"):
     """FBP of one slice at listed voxels.
 
     proj_slice: [n_angles][n] raw counts of one detector row;
@@ -291,7 +370,7 @@ def fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, st
     """
     p = normalize(np.asarray(proj_slice)[:, None, :], np.asarray(dark_slice)[:, None, :],
                   np.asarray(flat_slice)[:, None, :])[0]
-    q = _round_storage(filter_rows(p), storage)
+    q = _round_storage(filter_rows(p, kind=kind), storage)
     return backproject_points(q, angles, center, N, ix, iy)
 
 
