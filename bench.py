@@ -40,6 +40,10 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
 
 
+FILTER_NAMES = {"ramp": "ramp filter", "shepp": "Shepp-Logan-windowed ramp filter",
+                "parzen": "Parzen-windowed ramp filter"}
+
+
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -54,6 +58,8 @@ def parse():
     ap.add_argument("--rows", type=int, default=2048)
     ap.add_argument("--chunk", type=int, default=256, help="rows per tp_fbp_chunk call")
     ap.add_argument("--storage", default="f16,f32", help="storage precisions to time (first is reported)")
+    ap.add_argument("--filter", default="ramp", choices=("ramp", "shepp", "parzen"),
+                    help="filter window (the paper's tool defaults to parzen; the headline workload is ramp)")
     ap.add_argument("--tuning", default="", help="backprojection tuning K,A (default: plan default)")
     ap.add_argument("--parity-rows", type=int, default=2, help="full slices checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -158,7 +164,7 @@ def main():
         def step(record):
             for ci, (z0, z1) in enumerate(chunks):
                 tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st,
-                             out=vol[z0:z1], workspace=ws, events=evs[ci] if record else None)
+                             out=vol[z0:z1], workspace=ws, events=evs[ci] if record else None, kind=args.filter)
 
         for _ in range(args.warmup):
             step(False)
@@ -197,7 +203,7 @@ def main():
         d = scan.dark[:, z, :].cpu().numpy().view(np.uint16)[:, None, :]
         f = scan.flat[:, z, :].cpu().numpy().view(np.uint16)[:, None, :]
         t1 = time.perf_counter()
-        v = oracle.fbp(p, d, f, scan.angles, center)[0]
+        v = oracle.fbp(p, d, f, scan.angles, center, kind=args.filter)[0]
         return v, time.perf_counter() - t1
 
     rel = {st: None for st in storages}
@@ -255,7 +261,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"fbp {n}x{n}x{rows} volume from {na} angles x {rows} rows x {n} cols "
-                               f"12-bit ellipsoid scan, ramp filter, linear-interpolation backprojection",
+                               f"12-bit ellipsoid scan, {FILTER_NAMES[args.filter]}, linear-interpolation "
+                               f"backprojection",
                    "storage": head, "chunk_rows": chunk, "bp_tuning": tuning},
         "s_per_volume": {st: round(results[st]["s_per_volume"], 4) for st in storages},
         "gups": {st: round(results[st]["gups"], 2) for st in storages},
@@ -352,7 +359,7 @@ def main_single_launch(args):
     vol = torch.empty((rows, n, n), dtype=torch.float32, device="cuda")
     ws = torch.empty(plan.fbp_workspace_bytes(rows, st), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    tp.fbp_chunk(plan, scan.proj, scan.dark, scan.flat, st, out=vol, workspace=ws)
+    tp.fbp_chunk(plan, scan.proj, scan.dark, scan.flat, st, out=vol, workspace=ws, kind=args.filter)
     torch.cuda.synchronize()
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
@@ -400,12 +407,12 @@ def main_pipeline(args):
     ws = torch.empty(plan.fbp_workspace_bytes(max(pattern), st), dtype=torch.uint8, device=dev)
     for z0, z1 in chunks[:3]:
         tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st,
-                     out=vol_c[: z1 - z0], workspace=ws)
+                     out=vol_c[: z1 - z0], workspace=ws, kind=args.filter)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for z0, z1 in chunks:
         tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st,
-                     out=vol_c[: z1 - z0], workspace=ws)
+                     out=vol_c[: z1 - z0], workspace=ws, kind=args.filter)
     torch.cuda.synchronize()
     t_compute = time.perf_counter() - t0
     log(f"compute only: {t_compute:.2f} s")
@@ -440,7 +447,7 @@ def main_pipeline(args):
                 kept[z] = v[z - z0].copy()
 
     pl = pipeline.ChunkPipeline(plan, max_rows=max(pattern), n_dark=dark_h.shape[0], n_flat=flat_h.shape[0],
-                                storage=st, use_graphs=True)
+                                storage=st, use_graphs=True, kind=args.filter)
     pl.prepare(chunks)
     log(f"pipeline: {len(chunks)} chunks, {pl.stats.graphs_captured} graphs; running")
     stats = pl.run(chunks, source, sink)
@@ -450,7 +457,8 @@ def main_pipeline(args):
     for z in sample_z:
         ix, iy = rng.integers(0, n, 1024), rng.integers(0, n, 1024)
         want = oracle.fbp_points(proj_h[:, z].view(np.uint16), dark_h[:, z].view(np.uint16),
-                                 flat_h[:, z].view(np.uint16), plan.angles, center, n, ix, iy)
+                                 flat_h[:, z].view(np.uint16), plan.angles, center, n, ix, iy,
+                                 kind=args.filter)
         got = kept[z][iy, ix].astype(np.float64)
         rel.append(float(np.linalg.norm(got - want) / np.linalg.norm(want)))
     h2d = (proj_h.nbytes + dark_h.nbytes + flat_h.nbytes) / 1e9
@@ -463,7 +471,8 @@ def main_pipeline(args):
         "higher_is_better": True,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"fbp {n}x{n}x{rows} from {na} angles x {rows} rows x {n} cols 12-bit ellipsoid scan",
+        "config": {"workload": f"fbp {n}x{n}x{rows} from {na} angles x {rows} rows x {n} cols 12-bit ellipsoid scan, "
+                               f"{FILTER_NAMES[args.filter]}",
                    "storage": st, "chunks": list(pattern), "n_chunks": len(chunks), "graphs": stats.graphs_captured,
                    "bp_tuning": [k, a]},
         "s_host_to_host": round(stats.seconds, 3),

@@ -53,9 +53,13 @@ typedef enum {
 /* Storage type of sinograms and filtered rows.  Arithmetic is FP32 for all. */
 typedef enum { TP_F32 = 0, TP_F16 = 1, TP_BF16 = 2 } tp_dtype;
 
-/* Row filter.  Only the band-limited ramp |w| (cycles/pixel) is implemented;
- * the paper's Shepp-Logan and Parzen windows (Section 2.4 options) return
- * TP_EUNSUPPORTED. */
+/* Row filter: the band-limited ramp |w| (w in cycles/pixel, |w| <= 1/2) times
+ * a window W(x), x = 2|w| (the paper's filter choices, Section 2.4; Parzen is
+ * its default and is used for every result of Section 3).  The paper gives no
+ * formulas; the textbook windows are:
+ *   TP_RAMP:   W = 1;
+ *   TP_SHEPP:  W = sinc(x/2) = sin(pi x/2)/(pi x/2)  (taps 2/(pi^2 (1 - 4m^2)));
+ *   TP_PARZEN: W = 1 - 6x^2 + 6x^3 for x <= 1/2, 2(1 - x)^3 for 1/2 < x <= 1. */
 typedef enum { TP_RAMP = 0, TP_SHEPP = 1, TP_PARZEN = 2 } tp_filter_kind;
 
 /* Scan geometry (paper Section 2.4: angles, rotation axis, detector width). */
@@ -92,10 +96,19 @@ tp_status tp_plan_set_tuning(tp_plan* plan, tp_dtype storage, int32_t slices_per
 tp_status tp_plan_get_tuning(const tp_plan* plan, tp_dtype storage, int32_t* slices_per_block,
                              int32_t* angles_per_block);
 
-/* Build and cache the ramp-filter tables of one pad length on the current
- * device (for tp_filter calls that will be graph-captured).  pad_len: power of
- * two in [2, 16384]. */
+/* Build and cache the filter tables of one pad length and window on the
+ * current device (for tp_filter / tp_fbp_chunk calls that will be
+ * graph-captured; a plan prepares the ramp of its own pad length).  pad_len:
+ * power of two in [2, 16384]. */
 tp_status tp_filter_prepare(int32_t pad_len, tp_filter_kind kind);
+
+/* Host only, no device needed: the FP64 filter response the device tables are
+ * rounded from, H[k] = sum_{m=-L/2}^{L/2-1} h[m] exp(-2 pi i k m / L), where
+ * h[m] = integral over |w| <= 1/2 of |w| W(2|w|) exp(2 pi i w m) dw.
+ * H: HOST array of pad_len doubles, written.  pad_len: power of two in
+ * [2, 16384].  Errors: TP_EINVAL (null H, bad pad_len), TP_EUNSUPPORTED
+ * (unknown kind). */
+tp_status tp_filter_response(int32_t pad_len, tp_filter_kind kind, double* H);
 
 /* --------------------------------------------------------------------------
  * Dark/flat correction and negative logarithm (paper Section 2.2):
@@ -118,10 +131,10 @@ tp_status tp_normalize(const uint16_t* proj, int64_t proj_stride,
                        void* workspace, size_t workspace_bytes, void* stream);
 
 /* --------------------------------------------------------------------------
- * Ramp filter of detector rows by FFT (paper Section 2.2, padding per Section 3):
+ * Filter of detector rows by FFT (paper Section 2.2, padding per Section 3):
  * each row p[0..n) is padded to L by replicating its end values, with the data
- * at offset floor((L - n)/2); y = IFFT(H . FFT(u)), H[k] = DFT of the
- * band-limited ramp h[0] = 1/4, h[odd m] = -1/(pi^2 m^2); q[j] = y[off + j].
+ * at offset floor((L - n)/2); y = IFFT(H . FFT(u)), H = tp_filter_response of
+ * (L, kind) (ramp: h[0] = 1/4, h[odd m] = -1/(pi^2 m^2)); q[j] = y[off + j].
  * sino: dev [n_lines][n_det] of in_dtype;  filt: dev [n_lines][n_det] of
  * out_dtype; filt may equal sino only when in_dtype == out_dtype (in place),
  * otherwise the ranges must not overlap.  pad_len 0 => 2^ceil(log2(2 n_det));
@@ -164,6 +177,9 @@ tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float*
  * counts in registers, filters in FP32 and stores only the filtered rows, in
  * `storage` precision, into the workspace.  Inputs as for tp_normalize
  * (n_angles, n_det from the plan); vol: dev float [n_rows][N][N] (overwritten).
+ * kind: filter window at the plan's pad length 2^ceil(log2(2 n_det)); windows
+ * other than TP_RAMP build their tables on first use (tp_filter_prepare first
+ * when the call will be graph-captured; else TP_EUNSUPPORTED during capture).
  * workspace: dev, 256-byte aligned, >= tp_fbp_workspace_bytes(plan, n_rows, storage).
  * ------------------------------------------------------------------------ */
 size_t tp_fbp_workspace_bytes(const tp_plan* plan, int32_t n_rows, tp_dtype storage);

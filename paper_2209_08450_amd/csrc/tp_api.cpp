@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -65,37 +66,112 @@ size_t dtype_size(tp_dtype d) { return d == TP_F32 ? 4 : 2; }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t{255}; }
 
-// ---- ramp filter tables, cached per (device, L) ----
+// ---- filter tables, cached per (device, L, window) ----
 struct FilterEntry {
     float2* tw = nullptr;
     float* H = nullptr;
 };
 std::mutex g_filter_mu;
-std::map<std::pair<int, int>, FilterEntry> g_filter_cache;
+std::map<std::tuple<int, int, int>, FilterEntry> g_filter_cache;
 
-// H[k] = sum_{m=-L/2}^{L/2-1} h[m] exp(-2 pi i k m / L) with h[0] = 1/4,
-// h[odd m] = -1/(pi^2 m^2), h[even m != 0] = 0: the DFT of the band-limited
-// ramp, real and even.  FP64 direct sum over the odd lags with an exact
-// integer phase index.
-void ramp_response_fp64(int L, std::vector<double>& H) {
+// Exact integral of p(x) cos(pi m x) over [x0, x1] for a polynomial p with
+// coefficients c[0..deg] (p = sum c[i] x^i), using the antiderivative
+//   F(x) = sum_k (-1)^k [ p^(2k)(x) sin(a x) / a^(2k+1) + p^(2k+1)(x) cos(a x) / a^(2k+2) ],  a = pi m.
+// The end points are multiples of 1/2, so sin and cos of a x are taken
+// exactly from the quarter-turn count (m x in half-integers).
+double poly_cos_integral(std::vector<double> c, int m, double x0, double x1) {
+    auto eval = [](const std::vector<double>& q, double x) {
+        double v = 0.0;
+        for (size_t i = q.size(); i-- > 0;) v = v * x + q[i];
+        return v;
+    };
+    auto deriv = [](const std::vector<double>& q) {
+        std::vector<double> d;
+        for (size_t i = 1; i < q.size(); ++i) d.push_back(q[i] * static_cast<double>(i));
+        return d;
+    };
+    if (m == 0) {
+        double v = 0.0;
+        for (size_t i = 0; i < c.size(); ++i)
+            v += c[i] * (std::pow(x1, static_cast<double>(i + 1)) - std::pow(x0, static_cast<double>(i + 1))) /
+                 static_cast<double>(i + 1);
+        return v;
+    }
+    auto sin_cos = [m](double x, double* sv, double* cv) {
+        // a x = (pi/2) * q with q = 2 m x an integer for x in {0, 1/2, 1}
+        const int64_t q = static_cast<int64_t>(std::llround(2.0 * m * x));
+        static const double S[4] = {0.0, 1.0, 0.0, -1.0}, C[4] = {1.0, 0.0, -1.0, 0.0};
+        *sv = S[q & 3];
+        *cv = C[q & 3];
+    };
+    const double a = M_PI * m;
+    auto F = [&](double x) {
+        double sv, cv;
+        sin_cos(x, &sv, &cv);
+        double total = 0.0, apow = a, sign = 1.0;
+        std::vector<double> q = c;
+        while (!q.empty()) {
+            total += sign * eval(q, x) * sv / apow;
+            q = deriv(q);
+            if (q.empty()) break;
+            total += sign * eval(q, x) * cv / (apow * a);
+            q = deriv(q);
+            apow *= a * a;
+            sign = -sign;
+        }
+        return total;
+    };
+    return F(x1) - F(x0);
+}
+
+// Taps h[m], m = 0..L/2, of the windowed band-limited ramp
+//   h[m] = integral over |w| <= 1/2 of |w| W(2|w|) exp(2 pi i w m) dw   (h is even),
+// with the window W on x = 2|w| in [0, 1]:
+//   ramp:   W = 1                      -> h[0] = 1/4, h[odd m] = -1/(pi^2 m^2), h[even m] = 0;
+//   Shepp-Logan: W = sinc(x/2)         -> h[m] = 2 / (pi^2 (1 - 4 m^2));
+//   Parzen: W = 1 - 6x^2 + 6x^3 (x <= 1/2), 2 (1 - x)^3 (x > 1/2)
+//           -> h[m] = (1/2) integral_0^1 x W(x) cos(pi m x) dx, exact per polynomial piece.
+void window_taps_fp64(int L, tp_filter_kind kind, std::vector<double>& h) {
+    h.assign(L / 2 + 1, 0.0);
+    const double inv_pi2 = 1.0 / (M_PI * M_PI);
+    for (int m = 0; m <= L / 2; ++m) {
+        const double dm = static_cast<double>(m);
+        if (kind == TP_RAMP) {
+            h[m] = m == 0 ? 0.25 : ((m & 1) ? -inv_pi2 / (dm * dm) : 0.0);
+        } else if (kind == TP_SHEPP) {
+            h[m] = 2.0 * inv_pi2 / (1.0 - 4.0 * dm * dm);
+        } else {
+            // x W(x) on each piece, as polynomial coefficients in x
+            h[m] = 0.5 * (poly_cos_integral({0.0, 1.0, 0.0, -6.0, 6.0}, m, 0.0, 0.5) +
+                          poly_cos_integral({0.0, 2.0, -6.0, 6.0, -2.0}, m, 0.5, 1.0));
+        }
+    }
+}
+
+// H[k] = sum_{m=-L/2}^{L/2-1} h[m] exp(-2 pi i k m / L), real and even: FP64
+// direct sum over the non-zero lags with an exact integer phase index.
+void filter_response_fp64(int L, tp_filter_kind kind, std::vector<double>& H) {
+    std::vector<double> h;
+    window_taps_fp64(L, kind, h);
     std::vector<double> c(L);
     for (int k = 0; k < L; ++k) c[k] = std::cos(2.0 * M_PI * static_cast<double>(k) / L);
-    H.assign(L, 0.25);
-    const double inv_pi2 = 1.0 / (M_PI * M_PI);
+    H.assign(L, h[0]);
     for (int m = -L / 2; m < L / 2; ++m) {
-        if ((m & 1) == 0) continue;
-        const double hm = -inv_pi2 / (static_cast<double>(m) * m);
+        const double hm = h[m < 0 ? -m : m];
+        if (m == 0 || hm == 0.0) continue;
         const int64_t mm = ((m % L) + L) % L;
         for (int k = 0; k < L; ++k) H[k] += hm * c[(static_cast<int64_t>(k) * mm) % L];
     }
 }
 
-tp_status filter_tables(int L, tp::FilterTables* out, hipStream_t st_for_capture_check) {
+bool valid_kind(tp_filter_kind k) { return k == TP_RAMP || k == TP_SHEPP || k == TP_PARZEN; }
+
+tp_status filter_tables(int L, tp_filter_kind kind, tp::FilterTables* out, hipStream_t st_for_capture_check) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_filter_mu);
-    auto key = std::make_pair(dev, L);
+    auto key = std::make_tuple(dev, L, static_cast<int>(kind));
     auto it = g_filter_cache.find(key);
     if (it == g_filter_cache.end()) {
         if (st_for_capture_check != nullptr) {
@@ -103,10 +179,11 @@ tp_status filter_tables(int L, tp::FilterTables* out, hipStream_t st_for_capture
             if (hipStreamIsCapturing(st_for_capture_check, &cs) == hipSuccess &&
                 cs != hipStreamCaptureStatusNone)
                 return fail(TP_EUNSUPPORTED,
-                            "filter tables for pad length %d not built; call tp_filter_prepare before capture", L);
+                            "filter tables for pad length %d, window %d not built; call tp_filter_prepare before "
+                            "capture", L, static_cast<int>(kind));
         }
         std::vector<double> H;
-        ramp_response_fp64(L, H);
+        filter_response_fp64(L, kind, H);
         std::vector<float2> tw(L);
         std::vector<float> hf(L);
         for (int k = 0; k < L; ++k) {
@@ -268,7 +345,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     p->geo.center_f = static_cast<float>(g->center);
     p->geo.order = reinterpret_cast<const int*>(d_order);
     p->geo.n_rows_major = n_rows_major;
-    tp_status st = filter_tables(default_pad_len(g->n_det), &p->filt, nullptr);
+    tp_status st = filter_tables(default_pad_len(g->n_det), TP_RAMP, &p->filt, nullptr);
     if (st != TP_OK) {
         (void)hipFree(p->dev_block);
         delete p;
@@ -316,11 +393,22 @@ tp_status tp_plan_get_tuning(const tp_plan* plan, tp_dtype storage, int32_t* sli
 }
 
 tp_status tp_filter_prepare(int32_t pad_len, tp_filter_kind kind) {
-    if (kind != TP_RAMP) return fail(TP_EUNSUPPORTED, "only the ramp filter is implemented");
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
     if (!is_pow2(pad_len) || pad_len < 2 || pad_len > kMaxPadLen)
         return fail(TP_EINVAL, "pad_len=%d must be a power of two in [2, %d]", pad_len, kMaxPadLen);
     tp::FilterTables ft;
-    return filter_tables(pad_len, &ft, nullptr);
+    return filter_tables(pad_len, kind, &ft, nullptr);
+}
+
+tp_status tp_filter_response(int32_t pad_len, tp_filter_kind kind, double* H) {
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
+    if (!H) return fail(TP_EINVAL, "H is null");
+    if (!is_pow2(pad_len) || pad_len < 2 || pad_len > kMaxPadLen)
+        return fail(TP_EINVAL, "pad_len=%d must be a power of two in [2, %d]", pad_len, kMaxPadLen);
+    std::vector<double> r;
+    filter_response_fp64(pad_len, kind, r);
+    std::copy(r.begin(), r.end(), H);
+    return TP_OK;
 }
 
 size_t tp_normalize_workspace_bytes(int32_t n_rows, int32_t n_det) {
@@ -354,7 +442,7 @@ tp_status tp_normalize(const uint16_t* proj, int64_t proj_stride, const uint16_t
 
 tp_status tp_filter(const void* sino, tp_dtype in_dtype, void* filt, tp_dtype out_dtype, int64_t n_lines,
                     int32_t n_det, int32_t pad_len, tp_filter_kind kind, void* stream) {
-    if (kind != TP_RAMP) return fail(TP_EUNSUPPORTED, "only the ramp filter is implemented");
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
     if (!sino || !filt) return fail(TP_EINVAL, "null buffer");
     if (!valid_dtype(in_dtype) || !valid_dtype(out_dtype)) return fail(TP_EINVAL, "bad dtype");
     if (n_lines <= 0 || n_det <= 0) return fail(TP_EINVAL, "n_lines and n_det must be positive");
@@ -372,7 +460,7 @@ tp_status tp_filter(const void* sino, tp_dtype in_dtype, void* filt, tp_dtype ou
         return fail(TP_EINVAL, "filt overlaps sino (in place only with identical pointers and dtypes)");
     auto st = static_cast<hipStream_t>(stream);
     tp::FilterTables ft;
-    tp_status s = filter_tables(L, &ft, st);
+    tp_status s = filter_tables(L, kind, &ft, st);
     if (s != TP_OK) return s;
     hipError_t e = tp::launch_filter(sino, in_dtype, filt, out_dtype, n_lines, n_det, ft, st);
     if (e != hipSuccess) return hip_fail(e, "filter launch");
@@ -427,7 +515,7 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
     tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, plan->na, n_rows,
                             plan->n);
     if (s != TP_OK) return s;
-    if (kind != TP_RAMP) return fail(TP_EUNSUPPORTED, "only the ramp filter is implemented");
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
     if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
     if (!vol) return fail(TP_EINVAL, "vol is null");
     if (!workspace) return fail(TP_EINVAL, "workspace is null");
@@ -440,6 +528,8 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
     if (static_cast<int64_t>(n_rows) * ((plan->na + 1) / 2) > 0x7fffffffLL)
         return fail(TP_EINVAL, "n_rows=%d x n_angles=%d too large for one call", n_rows, plan->na);
     auto st = static_cast<hipStream_t>(stream);
+    tp::FilterTables ft = plan->filt;
+    if (kind != TP_RAMP && (s = filter_tables(plan->filt.L, kind, &ft, st)) != TP_OK) return s;
     const size_t dfb = tp_normalize_workspace_bytes(n_rows, plan->n);
     float* dmean = static_cast<float*>(workspace);
     float* den = reinterpret_cast<float*>(static_cast<char*>(workspace) + dfb / 2);
@@ -454,7 +544,7 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
     e = tp::launch_darkflat(in, n_rows, plan->n, dmean, den, st);
     if (e != hipSuccess) return hip_fail(e, "darkflat launch");
     if ((e = mark(1)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = tp::launch_norm_filter(in, dmean, den, plan->na, n_rows, plan->n, plan->filt, storage, filt, st);
+    e = tp::launch_norm_filter(in, dmean, den, plan->na, n_rows, plan->n, ft, storage, filt, st);
     if (e != hipSuccess) return hip_fail(e, "norm_filter launch");
     if ((e = mark(2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     e = tp::launch_backproject(plan->geo, filt, storage, n_rows, static_cast<float>(M_PI / plan->na), vol, 0, K, A,

@@ -59,14 +59,16 @@ class ChunkPipeline:
 
     plan: tp.Plan of the scan geometry; max_rows: largest chunk; n_dark/n_flat:
     frames per chunk; storage: 'f16' / 'f32' / 'bf16' for the filtered rows;
-    use_graphs: capture each (size, buffer) once and replay it; poison: fill
+    kind: filter window ('ramp', 'shepp', 'parzen'); use_graphs: capture each (size, buffer) once and replay it; poison: fill
     device and pinned buffers with NaN before each use (a missing dependency
     then shows as NaN in the result).
     """
 
     def __init__(self, plan: "tp.Plan", max_rows: int, n_dark: int, n_flat: int, storage="f16",
-                 use_graphs: bool = True, poison: bool = False, device=None):
+                 use_graphs: bool = True, poison: bool = False, device=None, kind="ramp"):
         self.plan = plan
+        self.kind = kind
+        tp.filter_code(kind)  # reject unknown names early
         self.device = torch.device(device or f"cuda:{torch.cuda.current_device()}")
         self.max_rows = int(max_rows)
         self.n_dark, self.n_flat = int(n_dark), int(n_flat)
@@ -115,7 +117,7 @@ class ChunkPipeline:
 
     def _compute(self, v):
         tp.fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], self.storage, out=v["dev_out"],
-                     workspace=self.ws)
+                     workspace=self.ws, kind=self.kind)
 
     def prepare(self, chunks):
         """Capture the graphs of every (chunk size, buffer) the run will use.

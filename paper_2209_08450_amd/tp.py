@@ -27,6 +27,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 TP_OK, TP_EINVAL, TP_EUNSUPPORTED, TP_EHIP, TP_ENOMEM = 0, -1, -2, -3, -4
 TP_F32, TP_F16, TP_BF16 = 0, 1, 2
 TP_RAMP, TP_SHEPP, TP_PARZEN = 0, 1, 2
+FILTERS = {"ramp": TP_RAMP, "shepp": TP_SHEPP, "parzen": TP_PARZEN}
 
 _c_i32, _c_i64, _c_sz, _c_vp, _c_f, _c_d = (ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
                                             ctypes.c_void_p, ctypes.c_float, ctypes.c_double)
@@ -50,6 +51,7 @@ _plan_set_tuning = _proto("tp_plan_set_tuning", _c_i32, _c_vp, _c_i32, _c_i32, _
 _plan_get_tuning = _proto("tp_plan_get_tuning", _c_i32, _c_vp, _c_i32, ctypes.POINTER(_c_i32),
                           ctypes.POINTER(_c_i32))
 _filter_prepare = _proto("tp_filter_prepare", _c_i32, _c_i32, _c_i32)
+_filter_response = _proto("tp_filter_response", _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_d))
 _normalize_ws = _proto("tp_normalize_workspace_bytes", _c_sz, _c_i32, _c_i32)
 _normalize = _proto("tp_normalize", _c_i32, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32,
                     _c_i32, _c_i32, _c_vp, _c_vp, _c_sz, _c_vp)
@@ -188,8 +190,24 @@ class Plan:
         return int(_fbp_ws(self._h, int(n_rows), dtype_code(storage)))
 
 
-def filter_prepare(pad_len: int, kind: int = TP_RAMP):
-    _check(_filter_prepare(int(pad_len), int(kind)))
+def filter_code(kind) -> int:
+    """Filter window code from a name ('ramp', 'shepp', 'parzen') or a code."""
+    if isinstance(kind, str):
+        if kind not in FILTERS:
+            raise ValueError(f"unknown filter {kind!r}; choose from {sorted(FILTERS)}")
+        return FILTERS[kind]
+    return int(kind)
+
+
+def filter_prepare(pad_len: int, kind="ramp"):
+    _check(_filter_prepare(int(pad_len), filter_code(kind)))
+
+
+def filter_response(pad_len: int, kind="ramp") -> np.ndarray:
+    """The library's FP64 filter response H[0..pad_len) (host only, no device)."""
+    out = np.empty(int(pad_len), dtype=np.float64)
+    _check(_filter_response(int(pad_len), filter_code(kind), out.ctypes.data_as(ctypes.POINTER(_c_d))))
+    return out
 
 
 def pad_len(n_det: int) -> int:
@@ -222,8 +240,9 @@ def normalize(proj, dark, flat, out_dtype="f32", out=None, workspace=None, strea
     return out
 
 
-def filter(sino, out_dtype=None, out=None, pad_len: int = 0, kind: int = TP_RAMP, stream=None):
-    """Ramp-filter every row of ``sino`` [..., n_det]; returns the filtered rows."""
+def filter(sino, out_dtype=None, out=None, pad_len: int = 0, kind="ramp", stream=None):
+    """Filter every row of ``sino`` [..., n_det] (ramp, or ramp with the Shepp-Logan
+    or Parzen window); returns the filtered rows."""
     torch = _torch()
     if not sino.is_contiguous():
         raise ValueError("sino must be contiguous")
@@ -233,8 +252,8 @@ def filter(sino, out_dtype=None, out=None, pad_len: int = 0, kind: int = TP_RAMP
     n_lines = int(sino.numel() // n_det)
     if out is None:
         out = torch.empty(sino.shape, dtype=torch_dtype(out_code), device=sino.device)
-    _check(_filter(_dev(sino, "sino"), in_code, _dev(out, "out"), out_code, n_lines, n_det, int(pad_len), int(kind),
-                   _stream_ptr(stream)))
+    _check(_filter(_dev(sino, "sino"), in_code, _dev(out, "out"), out_code, n_lines, n_det, int(pad_len),
+                   filter_code(kind), _stream_ptr(stream)))
     return out
 
 
@@ -270,8 +289,11 @@ def radon(plan: Plan, vol, out=None, stream=None):
     return out
 
 
-def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=None, stream=None, events=None):
+def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=None, stream=None, events=None,
+              kind="ramp"):
     """Raw counts of a row chunk -> reconstructed slices [rows][N][N] (float32).
+
+    ``kind``: filter window, 'ramp', 'shepp' or 'parzen' (or its code).
 
     ``events``: optional list of four recorded-once ``torch.cuda.Event`` objects
     (or None entries) marked before the dark/flat means, the fused
@@ -289,13 +311,14 @@ def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=N
     if dark.shape[1] != n_rows or flat.shape[1] != n_rows:
         raise ValueError("dark/flat rows must match proj rows")
     code = dtype_code(storage)
+    kcode = filter_code(kind)
     need = plan.fbp_workspace_bytes(n_rows, code)
     if workspace is None:
         workspace = _workspace(need, proj.device)
     if out is None:
         out = torch.empty((n_rows, plan.n_vox, plan.n_vox), dtype=torch.float32, device=proj.device)
     if events is None:
-        _check(_fbp_chunk(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, TP_RAMP,
+        _check(_fbp_chunk(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode,
                           code, _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
                           _dev(out, "out"), _stream_ptr(stream)))
     else:
@@ -305,7 +328,7 @@ def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=N
         if any(e is not None and not e.cuda_event for e in events):
             raise ValueError("record each event once before passing it (torch creates it lazily)")
         _check(_fbp_chunk_events(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows,
-                                 TP_RAMP, code, _dev(workspace, "workspace"),
+                                 kcode, code, _dev(workspace, "workspace"),
                                  workspace.numel() * workspace.element_size(), _dev(out, "out"),
                                  _stream_ptr(stream), arr))
     return out

@@ -51,8 +51,8 @@ def test_null_and_size_errors(tp):
     assert st == tp.TP_EINVAL and "power of two" in tp.last_error()
     st = tp._filter(dummy, tp.TP_F32, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 8, tp.TP_RAMP, nul)
     assert st == tp.TP_EINVAL  # pad shorter than the row
-    st = tp._filter(dummy, tp.TP_F32, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 0, tp.TP_PARZEN, nul)
-    assert st == tp.TP_EUNSUPPORTED
+    st = tp._filter(dummy, tp.TP_F32, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 0, 7, nul)
+    assert st == tp.TP_EUNSUPPORTED and "kind" in tp.last_error()
     st = tp._filter(dummy, 7, ctypes.c_void_p(0x900000), tp.TP_F32, 4, 16, 0, tp.TP_RAMP, nul)
     assert st == tp.TP_EINVAL and "dtype" in tp.last_error()
 
@@ -95,7 +95,30 @@ def test_plan_null_handles(tp):
 def test_filter_prepare_validation(tp):
     assert tp._filter_prepare(3, tp.TP_RAMP) == tp.TP_EINVAL
     assert tp._filter_prepare(32768, tp.TP_RAMP) == tp.TP_EINVAL
-    assert tp._filter_prepare(64, tp.TP_SHEPP) == tp.TP_EUNSUPPORTED
+    assert tp._filter_prepare(64, 7) == tp.TP_EUNSUPPORTED
+
+
+def test_filter_response_validation(tp):
+    buf = np.zeros(64)
+    ptr = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert tp._filter_response(24, tp.TP_RAMP, ptr) == tp.TP_EINVAL
+    assert tp._filter_response(32768, tp.TP_RAMP, ptr) == tp.TP_EINVAL
+    assert tp._filter_response(64, 7, ptr) == tp.TP_EUNSUPPORTED
+    assert tp._filter_response(64, tp.TP_RAMP, None) == tp.TP_EINVAL
+    with pytest.raises(ValueError):
+        tp.filter_code("hann")
+
+
+@pytest.mark.parametrize("kind", ["ramp", "shepp", "parzen"])
+def test_filter_response_matches_oracle(tp, kind):
+    """The library's FP64 response (closed-form / exact piecewise taps, direct
+    DFT sum on the host) against the oracle's (quadrature taps, numpy FFT)."""
+    import oracle
+    for L in (2, 8, 64, 1024, 8192):
+        got = tp.filter_response(L, kind)
+        want = oracle.filter_response(L, kind)
+        # both FP64; summation order differs, so rounding grows ~ L (largest at Nyquist)
+        assert np.max(np.abs(got - want)) < 1e-15 + 1e-16 * L, (kind, L)
 
 
 def test_normalize_validation(tp):

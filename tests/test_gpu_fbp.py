@@ -111,3 +111,49 @@ def test_fbp_paper_scale_sampled(tp):
     note(f"paper-scale rel-L2 f32 {e32} f16 {e16}")
     assert max(e32) < 1e-5
     assert max(e16) < 3e-3
+
+
+@pytest.mark.parametrize("kind", ["shepp", "parzen"])
+def test_fbp_windowed_filters(tp, scan16, kind):
+    # the paper's filter choices; Parzen is its default
+    s = scan16
+    note(f"fbp {kind} 180x16x256")
+    want = oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center, kind=kind)
+    want16 = oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center, storage="f16", kind=kind)
+    plan = tp.Plan(s.angles, 256, s.center)
+    run = lambda st: to_host(tp.fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), st,  # noqa: E731
+                                          kind=kind)).astype(np.float64)
+    assert rel_l2(run("f32"), want) < 1e-5
+    e = rel_l2(run("f16"), want)
+    assert e < 3e-3
+    assert rel_l2(run("f16"), want16) < 0.25 * e + 1e-5
+    assert rel_l2(run("bf16"), want) < 2e-2
+    # the window changes the reconstruction
+    assert rel_l2(want, oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center)) > 1e-2
+
+
+def test_fbp_windowed_graph_capture_needs_prepared_tables(tp):
+    import torch
+    s = synth.ellipsoid_scan_np(seed=9, n_angles=24, n_rows=3, n_det=40, center=19.5, n_dark=1, n_flat=1)
+    plan = tp.Plan(s.angles, 40, s.center)
+    P, D, F = to_dev(s.proj), to_dev(s.dark), to_dev(s.flat)
+    out = torch.empty((3, 40, 40), device="cuda")
+    ws = torch.empty(plan.fbp_workspace_bytes(3, "f32"), dtype=torch.uint8, device="cuda")
+    st = torch.cuda.Stream()
+    note("fbp shepp capture without prepared tables")
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(tp.TpError, match="tp_filter_prepare"):
+        with torch.cuda.graph(g, stream=st, capture_error_mode="thread_local"):
+            tp.fbp_chunk(plan, P, D, F, "f32", out=out, workspace=ws, kind="shepp")
+    torch.cuda.synchronize()
+    note("fbp shepp capture with prepared tables, replays")
+    tp.filter_prepare(tp.pad_len(40), "shepp")
+    want = oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center, kind="shepp")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st, capture_error_mode="thread_local"):
+        tp.fbp_chunk(plan, P, D, F, "f32", out=out, workspace=ws, kind="shepp")
+    for rep in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert rel_l2(to_host(out).astype(np.float64), want) < 1e-5, rep

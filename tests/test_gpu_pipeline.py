@@ -58,6 +58,17 @@ def test_pipeline_bitwise_equals_monolithic(env, graphs, poison, storage):
     assert np.array_equal(got, want)
 
 
+def test_pipeline_parzen_bitwise_equals_monolithic(env):
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    want = to_host(tp.fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), "f16", kind="parzen"))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, storage="f16", kind="parzen")
+    got = np.full((100, 128, 128), np.nan, np.float32)
+    note("pipeline parzen f16 graphs")
+    pl.run(pipeline.uneven_chunks(100, (32, 9)), _source(s), _sink(got))
+    assert np.array_equal(got, want)
+
+
 def test_graph_replays_repeat_with_eager_work_between(env):
     import torch
     tp, pipeline, _, s = env

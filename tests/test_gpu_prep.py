@@ -134,3 +134,41 @@ def test_filter_odd_line_count_and_large_l(tp):
     note("filter L=16384, odd lines")
     got = to_host(tp.filter(to_dev(p)))
     assert rel_l2(got, oracle.filter_rows(p.astype(np.float64))) < 3e-6
+
+
+@pytest.mark.parametrize("kind", ["shepp", "parzen"])
+@pytest.mark.parametrize("n", [1, 13, 256, 1000, 2048, 4096, 6000])
+def test_windowed_filter_matches_oracle(tp, kind, n):
+    # n spans the LDS FFT (L < 1024 and L = 16384) and the register FFT
+    # (1024 <= L <= 8192)
+    rng = np.random.default_rng(1000 + n)
+    p = rng.standard_normal((5, n)) + 1.5
+    note(f"filter {kind} f32 n={n}")
+    got = to_host(tp.filter(to_dev(p.astype(np.float32)), kind=kind))
+    want = oracle.filter_rows(p.astype(np.float32).astype(np.float64), kind=kind)
+    assert rel_l2(got, want) < 3e-6
+
+
+@pytest.mark.parametrize("kind", ["shepp", "parzen"])
+def test_windowed_filter_f16_out_and_in_place(tp, kind):
+    import torch
+    rng = np.random.default_rng(77)
+    p = rng.standard_normal((4, 700)).astype(np.float32)
+    note(f"filter {kind} f32->f16, in place")
+    want = oracle.filter_rows(p.astype(np.float64), kind=kind)
+    got16 = to_host(tp.filter(to_dev(p), out_dtype="f16", kind=kind)).astype(np.float64)
+    assert rel_l2(got16, want) < 1e-3
+    t = to_dev(p)
+    tp.filter(t, out=t, kind=kind)
+    torch.cuda.synchronize()
+    assert rel_l2(to_host(t), want) < 3e-6
+
+
+def test_windows_differ_from_ramp(tp):
+    rng = np.random.default_rng(5)
+    p = to_dev(rng.standard_normal((3, 128)).astype(np.float32))
+    note("filter windows differ")
+    r = to_host(tp.filter(p))
+    s = to_host(tp.filter(p, kind="shepp"))
+    z = to_host(tp.filter(p, kind="parzen"))
+    assert rel_l2(s, r) > 1e-2 and rel_l2(z, r) > 1e-2 and rel_l2(z, s) > 1e-2
