@@ -103,10 +103,12 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
     const int z0 = blockIdx.y * K;
     const int kz = min(K, n_rows - z0);
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: angle loads go scalar
     const float dy = static_cast<float>((lane >> 3) + 8 * wv);
     const float dx0 = static_cast<float>(lane & 7);
     const T* rows0 = filt + static_cast<int64_t>(z0) * na * n;
+    const int64_t slice_bytes = static_cast<int64_t>(na) * n * static_cast<int64_t>(sizeof(T));
 
     float acc[4][K];
 #pragma unroll
@@ -126,17 +128,35 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
             const int fmin = coord_floor(smin);
             if (lane == 0) sGeo[a] = make_float4(bf, cs, sn, __int_as_float((a * kWin - fmin) * BIN));
             if (lane < kWin) {
+                // Each slice's row base is wave-uniform (scalar arithmetic) and
+                // every slice uses the same 32-bit lane offset, of the bin
+                // clamped onto the detector; bins off the detector are then
+                // zeroed with one AND per 32-bit word.  Slices past the last
+                // row re-read the last one; their sums are never stored.
                 const int j = bi + fmin + lane;
-                const bool on = j >= 0 && j < n;
+                const uint32_t keep = (j >= 0 && j < n) ? 0xffffffffu : 0u;
+                const uint32_t voff = static_cast<uint32_t>(min(max(j, 0), n - 1)) *
+                                      static_cast<uint32_t>(sizeof(T));
+                const unsigned char* rowb = reinterpret_cast<const unsigned char*>(rows0) +
+                                            static_cast<int64_t>(ag) * n * static_cast<int64_t>(sizeof(T));
                 U q[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const T* row = rows0 + (static_cast<int64_t>(k) * na + ag) * n;
+                    const T* src = reinterpret_cast<const T*>(rowb + min(k, kz - 1) * slice_bytes + voff);
                     if constexpr (std::is_same<T, U>::value) {
-                        q[k] = (on && k < kz) ? row[j] : static_cast<U>(0.0f);  // raw copy
+                        q[k] = *src;  // raw copy
                     } else {
-                        q[k] = (on && k < kz) ? ld(row, j) : 0.0f;  // bf16 widened
+                        q[k] = ld(src, 0);  // bf16 widened
                     }
+                }
+                if constexpr (BIN % 4 == 0) {
+                    uint32_t* qw = reinterpret_cast<uint32_t*>(q);
+#pragma unroll
+                    for (int i = 0; i < BIN / 4; ++i) qw[i] &= keep;
+                } else {  // one FP16 slice
+                    uint16_t* qh = reinterpret_cast<uint16_t*>(q);
+#pragma unroll
+                    for (int i = 0; i < BIN / 2; ++i) qh[i] &= static_cast<uint16_t>(keep);
                 }
                 copy_group<BIN, (BIN < 16 ? BIN : 16)>(smem + (a * kWin + lane) * BIN, q);
             }

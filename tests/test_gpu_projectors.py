@@ -204,3 +204,30 @@ def test_unsorted_nonuniform_angles(tp):
     assert rel_l2(to_host(tp.radon(plan, to_dev(x))), oracle.radon(x.astype(np.float64), ang, c, n)) < 1e-5
     assert rel_l2(to_host(tp.backproject(plan, to_dev(q), scale=1.0)),
                   oracle.backproject(q.astype(np.float64), ang, c, N, scale=1.0)) < 1e-5
+
+
+def test_backproject_more_than_4gb_of_rows(tp):
+    # 16 slices of 17477 angles x 8192 columns in f16: one slice group spans
+    # 4.6 GB of filtered rows, past 32-bit byte offsets.  Checked against the
+    # oracle at sampled voxels of the first and the last slice.
+    import torch
+    na, n, rows = 17477, 8192, 16
+    ang = synth.uniform_angles(na)
+    plan = tp.Plan(ang, n, n / 2.0)
+    assert plan.get_tuning("f16")[0] == 16
+    g = torch.Generator(device="cuda").manual_seed(31)
+    q = torch.randn((rows, na, n), generator=g, device="cuda").half()
+    note("backproject 16 x 17477 x 8192 f16")
+    vol = tp.backproject(plan, q)
+    rng = np.random.default_rng(31)
+    ix = rng.integers(0, n, 48)
+    iy = rng.integers(0, n, 48)
+    for z in (0, rows - 1):
+        qz = q[z].cpu().numpy().astype(np.float64)
+        want = oracle.backproject_points(qz, ang, n / 2.0, n, ix, iy)
+        got = vol[z].cpu().numpy()[iy, ix].astype(np.float64)
+        # FP32 sums of 17477 random terms: rounding ~ sqrt(n_angles) eps
+        # relative; an addressing mistake would be O(1)
+        assert rel_l2(got, want) < 3e-5, z
+    del q, vol
+    torch.cuda.empty_cache()
