@@ -89,8 +89,9 @@ tp_status tp_plan_destroy(tp_plan* plan);
  * sums its angles in order).
  *   slices_per_block in {1, 2, 4, 8, 16}: slices sharing one coordinate evaluation;
  *   angles_per_block in {8, 16, 32, 64}: angles staged in LDS per step;
- *   the staged block, angles x 48 bins x slices x 4 bytes (2 for F16), must
- *   fit in 160 KiB.  Defaults: F16 (16, 16); F32 and BF16 (8, 16). */
+ *   the staged block, angles x 48 bins x pitch (slices x 4 bytes, 2 for F16,
+ *   plus 16 when that is 64 or more), must fit in 160 KiB.  Defaults: F16
+ *   (16, 16); F32 and BF16 (16, 8). */
 tp_status tp_plan_set_tuning(tp_plan* plan, tp_dtype storage, int32_t slices_per_block,
                              int32_t angles_per_block);
 tp_status tp_plan_get_tuning(const tp_plan* plan, tp_dtype storage, int32_t* slices_per_block,

@@ -17,12 +17,13 @@
 // wave step covers an 8x8 block whose taps fall in a window of about 13
 // detector bins.  For a block of A angles, each wave stages whole angles: lane
 // b loads bin ws + b of the K slices' filtered rows and writes them as one
-// contiguous group, so LDS holds [angle][bin][slice] (bf16 widened to FP32).
+// contiguous group, so LDS holds [angle][bin][slice] (bf16 widened to FP32;
+// groups padded to an odd number of 16-byte bank groups).
 // The window starts at ws = bi + floor(min over the tile corners of the
 // FP32 offset); fma is monotone in each argument, so every voxel's floor
 // lies in [0, 45) of the 48-bin window and both taps are staged.  The inner
 // loop per voxel and angle: offset (1 FMA), fraction, floor, address, 1 - w,
-// one read of the two bins' K-slice groups (16-byte LDS reads), then two
+// reads of the two bins' K-slice groups (16-byte LDS reads), then two
 // FMAs per slice (v_fma_mix_f32 reads FP16 operands directly).  Every slice
 // sums its angles in order, so results do not depend on K or A.
 #include <type_traits>
@@ -36,6 +37,16 @@ template <typename T> struct Lds { using U = T; };          // LDS element per s
 template <> struct Lds<uint16_t> { using U = float; };     // bf16 widened
 
 template <typename T> __device__ __forceinline__ float ld(const T* p, int j) { return load_as_float(p, j); }
+
+// One staged element: raw copy, or bf16 widened to FP32.
+template <typename T, typename U>
+__device__ __forceinline__ U stage_load(const unsigned char* p) {
+    if constexpr (std::is_same<T, U>::value) {
+        return *reinterpret_cast<const T*>(p);
+    } else {
+        return ld(reinterpret_cast<const T*>(p), 0);
+    }
+}
 
 __device__ __forceinline__ float lds_val(const float* v, int i) { return v[i]; }
 __device__ __forceinline__ float lds_val(const __half* v, int i) { return __half2float(v[i]); }
@@ -87,15 +98,23 @@ __device__ __forceinline__ void tile_of(int wg, int nb, int& bx, int& by) {
     }
 }
 
+// LDS pitch of one (angle, bin) group of BIN bytes.  With a pitch of four or
+// more (an even number of) 16-byte bank groups, bins 4 apart share banks and
+// a wave's 16-byte reads of its ~10 neighbouring bins conflict; one more
+// group makes the pitch odd and spreads them.  (Two groups measured no
+// better padded.)
+constexpr int bin_pitch(int bin) { return (bin >= 64 && (bin / 16) % 2 == 0) ? bin + 16 : bin; }
+
 template <typename T, int K, int A>
 __global__ void __launch_bounds__(kBpThreads)
 k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, float* __restrict__ vol,
               int accumulate) {
     using U = typename Lds<T>::U;
     constexpr int BIN = K * static_cast<int>(sizeof(U));  // bytes of one (angle, bin) group
+    constexpr int P = bin_pitch(BIN);                       // LDS bytes between bins
     extern __shared__ __align__(16) unsigned char smem[];
     // smem: [A][kWin][K] values of U, then sGeo
-    float4* sGeo = reinterpret_cast<float4*>(smem + A * kWin * BIN);          // [A] {bf, cos, sin, byte base}
+    float4* sGeo = reinterpret_cast<float4*>(smem + A * kWin * P);          // [A] {bf, cos, sin, byte base}
 
     const int na = g.na, n = g.n, nb = g.nb;
     int bx, by;
@@ -126,15 +145,17 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
             const float bf = g.xf[bx * na + ag] + g.yf[by * na + ag];
             const float smin = tile_offset(cs >= 0.0f ? 0.0f : 31.0f, sn >= 0.0f ? 0.0f : 31.0f, cs, sn, bf);
             const int fmin = coord_floor(smin);
-            if (lane == 0) sGeo[a] = make_float4(bf, cs, sn, __int_as_float((a * kWin - fmin) * BIN));
+            if (lane == 0) sGeo[a] = make_float4(bf, cs, sn, __int_as_float((a * kWin - fmin) * P));
             if (lane < kWin) {
-                // Each slice's row base is wave-uniform (scalar arithmetic) and
-                // every slice uses the same 32-bit lane offset, of the bin
-                // clamped onto the detector; bins off the detector are then
-                // zeroed with one AND per 32-bit word.  Slices past the last
-                // row re-read the last one; their sums are never stored.
+                // Every slice uses the same 32-bit lane offset, of the bin
+                // clamped onto the detector; slice k's row base is
+                // wave-uniform: rowb + kk * slice_bytes with kk = min(k, kz - 1)
+                // made opaque, so each base is a few scalar instructions at its
+                // load instead of K hoisted 64-bit constants.  Slices past the
+                // last row re-read it; their sums are never stored.  Lanes
+                // whose bin is off the detector overwrite their group with
+                // zeros afterwards (only edge waves take that branch).
                 const int j = bi + fmin + lane;
-                const uint32_t keep = (j >= 0 && j < n) ? 0xffffffffu : 0u;
                 const uint32_t voff = static_cast<uint32_t>(min(max(j, 0), n - 1)) *
                                       static_cast<uint32_t>(sizeof(T));
                 const unsigned char* rowb = reinterpret_cast<const unsigned char*>(rows0) +
@@ -142,23 +163,18 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
                 U q[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const T* src = reinterpret_cast<const T*>(rowb + min(k, kz - 1) * slice_bytes + voff);
-                    if constexpr (std::is_same<T, U>::value) {
-                        q[k] = *src;  // raw copy
-                    } else {
-                        q[k] = ld(src, 0);  // bf16 widened
-                    }
+                    int kk = min(k, kz - 1);
+                    asm volatile("" : "+s"(kk));
+                    q[k] = stage_load<T, U>(rowb + kk * slice_bytes + voff);
                 }
-                if constexpr (BIN % 4 == 0) {
-                    uint32_t* qw = reinterpret_cast<uint32_t*>(q);
+                unsigned char* dst = smem + (a * kWin + lane) * P;
+                copy_group<BIN, (BIN < 16 ? BIN : 16)>(dst, q);
+                if (j < 0 || j >= n) {
+                    U zero[K];
 #pragma unroll
-                    for (int i = 0; i < BIN / 4; ++i) qw[i] &= keep;
-                } else {  // one FP16 slice
-                    uint16_t* qh = reinterpret_cast<uint16_t*>(q);
-#pragma unroll
-                    for (int i = 0; i < BIN / 2; ++i) qh[i] &= static_cast<uint16_t>(keep);
+                    for (int k = 0; k < K; ++k) zero[k] = static_cast<U>(0.0f);
+                    copy_group<BIN, (BIN < 16 ? BIN : 16)>(dst, zero);
                 }
-                copy_group<BIN, (BIN < 16 ? BIN : 16)>(smem + (a * kWin + lane) * BIN, q);
             }
         }
         __syncthreads();
@@ -172,7 +188,13 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
                 const float s = tile_offset(dx0 + 8.0f * i, dy, ge.y, ge.z, ge.x);
                 w[i] = coord_frac(s);
                 omw[i] = 1.0f - w[i];
-                copy_group<2 * BIN, (BIN < 16 ? BIN : 16)>(r[i], smem + base + coord_floor(s) * BIN);
+                const unsigned char* tap = smem + base + coord_floor(s) * P;
+                if constexpr (P == BIN) {
+                    copy_group<2 * BIN, (BIN < 16 ? BIN : 16)>(r[i], tap);
+                } else {
+                    copy_group<BIN, 16>(r[i], tap);
+                    copy_group<BIN, 16>(r[i] + K, tap + P);
+                }
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -355,8 +377,8 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
 }
 
 size_t bp_lds_bytes(tp_dtype dt, int K, int A) {
-    const size_t elem = (dt == TP_F16) ? 2 : 4;  // bf16 is widened to FP32 in LDS
-    return elem * K * A * kWin + static_cast<size_t>(A) * sizeof(float4);
+    const int elem = (dt == TP_F16) ? 2 : 4;  // bf16 is widened to FP32 in LDS
+    return static_cast<size_t>(bin_pitch(elem * K)) * A * kWin + static_cast<size_t>(A) * sizeof(float4);
 }
 
 template <typename T, int K, int A>

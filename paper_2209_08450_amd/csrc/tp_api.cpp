@@ -24,8 +24,8 @@ struct tp_plan {
     tp::GeoTables geo{};
     tp::FilterTables filt{};
     // backprojection tuning per storage type (F32, F16, BF16)
-    int bp_k[3] = {8, 16, 8};
-    int bp_a[3] = {16, 16, 16};
+    int bp_k[3] = {16, 16, 16};
+    int bp_a[3] = {8, 16, 8};
 };
 
 namespace {

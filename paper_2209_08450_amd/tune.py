@@ -19,9 +19,15 @@ LDS_BYTES = 160 * 1024
 WINDOW = 48
 
 
+def bin_pitch(group_bytes: int) -> int:
+    """LDS bytes between staged bins (padded by 16 when the group is an even
+    number, at least 4, of 16-byte bank groups, as the kernel does)."""
+    return group_bytes + 16 if group_bytes >= 64 and (group_bytes // 16) % 2 == 0 else group_bytes
+
+
 def legal(storage: str, k: int, a: int) -> bool:
     elem = 2 if storage == "f16" else 4
-    return k * a * WINDOW * elem + a * 16 <= LDS_BYTES
+    return bin_pitch(k * elem) * a * WINDOW + a * 16 <= LDS_BYTES
 
 
 def candidates(storage: str, slices=SLICES, angles=ANGLES):

@@ -91,6 +91,8 @@ def test_backproject_accumulate_and_scale(tp):
 
 def test_tuning_variants_are_bitwise_identical(tp):
     import torch
+
+    from paper_2209_08450_amd import tune
     na, n, N, c, rows = 70, 120, 110, 61.2, 11
     rng = np.random.default_rng(8)
     ang = synth.uniform_angles(na) + 0.2
@@ -104,7 +106,7 @@ def test_tuning_variants_are_bitwise_identical(tp):
                     plan.set_tuning(st, k, a)
                 except tp.TpError:
                     # rejected only when the staged block exceeds the LDS
-                    assert k * a * 48 * (2 if st == "f16" else 4) + a * 16 > 160 * 1024
+                    assert not tune.legal(st, k, a)
                     continue
                 assert plan.get_tuning(st) == (k, a)
                 note(f"backproject {st} tuning K={k} A={a}")

@@ -25,9 +25,12 @@ def test_uneven_chunks_cover_rows_once():
 def test_tuner_legal_candidates():
     c16 = tune.candidates("f16")
     c32 = tune.candidates("f32")
-    assert (8, 64) in c16 and (8, 64) in c32  # 8*64*48*4 + 1 KiB = 99 KiB fits 160 KiB
+    assert (8, 64) in c16 and (8, 64) in c32  # f32: 32 B x 48 bins x 64 + 1 KiB = 97 KiB fits 160 KiB
+    # groups of 64 bytes or more get one 16-byte bank group of padding
+    assert tune.bin_pitch(16) == 16 and tune.bin_pitch(32) == 32 and tune.bin_pitch(64) == 80
     assert all(tune.legal("f32", k, a) for k, a in c32)
     assert len(c16) == 20 and (16, 64) in c16 and (16, 64) not in c32
+    assert (16, 32) in c32  # f32: 80 B x 48 x 32 + 512 = 120.5 KiB
 
 
 class FakePlan:
