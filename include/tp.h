@@ -165,11 +165,19 @@ tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtyp
  *   sino[r][a][j] = sum over voxels of vol[r][iy][ix] * ( (1-w)[j0 == j] + w[j0+1 == j] )
  * with (j0, w) computed by the same FP32 formula as tp_backproject, so
  * <R x, y> = <x, R^T y> holds up to FP32 summation rounding.  Gather form
- * (each output summed by one thread in a fixed order): deterministic.
- * vol: dev float [n_rows][N][N];  sino: dev float [n_rows][n_angles][n_det], overwritten.
+ * (each output summed by one thread in a fixed order): deterministic.  Inputs
+ * are finite.
+ * vol: dev float [n_rows][N][N];  sino: dev float [n_rows][n_angles][n_det],
+ * overwritten; 1 <= n_rows <= 65535.
+ * workspace: dev, 256-byte aligned, not overlapping vol or sino, at least
+ * tp_radon_workspace_bytes(plan, n_rows) bytes (a transposed copy of vol, so
+ * that angles whose rays run closer to the y axis also read contiguous
+ * memory; 0 bytes, and workspace may be NULL, when every angle has
+ * |cos| >= |sin|).  Its contents are scratch.
  * ------------------------------------------------------------------------ */
+size_t tp_radon_workspace_bytes(const tp_plan* plan, int32_t n_rows);
 tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float* sino,
-                   void* stream);
+                   void* workspace, size_t workspace_bytes, void* stream);
 
 /* --------------------------------------------------------------------------
  * One chunk of rows through the whole path: normalise -> filter -> backproject.

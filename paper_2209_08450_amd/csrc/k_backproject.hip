@@ -136,7 +136,7 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
         for (int k = 0; k < K; ++k) acc[i][k] = 0.0f;
 
     for (int a0 = 0; a0 < na; a0 += A) {
-        const int nA = min(A, na - a0);
+        const int nA = __builtin_amdgcn_readfirstlane(min(A, na - a0));  // keeps the angle loop scalar
         // stage: wave wv takes angles wv, wv+4, ...; lane b holds bin ws + b
         for (int a = wv; a < nA; a += kBpThreads / 64) {
             const int ag = a0 + a;
@@ -240,19 +240,23 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
 // wider than kRadonStrip (sparse angle sets) is read from global memory
 // instead, with the same arithmetic and order.  No atomics: every output is
 // summed by one lane, lines ascending, candidates ascending.
-constexpr int kCand = 5;
-constexpr int kRadonSlices = 8;
+constexpr int kCand = 3;
 constexpr int kRadonLines = 4;
 constexpr int kRadonStrip = 128;
+// floats between strip positions: an odd number of 16-byte bank groups, so
+// neighbouring bins (candidates 1 to 1.41 voxels apart) read distinct banks
+template <int K> constexpr int radon_pitch() { return K + 4; }
 
 template <int K>
 __global__ void __launch_bounds__(256)
-k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restrict__ sino) {
+k_radon(GeoTables g, const float* __restrict__ vol, const float* __restrict__ volT, int n_rows,
+        float* __restrict__ sino) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_lo[4][4];
     const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
-    float* strip = reinterpret_cast<float*>(smem);                        // [lines][kRadonStrip][K]
-    int* tabs = reinterpret_cast<int*>(strip + kRadonLines * kRadonStrip * K);  // [4 waves][4][nb]
+    constexpr int SP = radon_pitch<K>();
+    float* strip = reinterpret_cast<float*>(smem);                        // [lines][kRadonStrip][SP]
+    int* tabs = reinterpret_cast<int*>(strip + kRadonLines * kRadonStrip * SP);  // [4 waves][4][nb]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int jgroups = (g.n + 63) >> 6;
     const int jb = (blockIdx.x % jgroups) * 64;
@@ -281,9 +285,12 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
     const float cmaj = rows_major ? cs : sn;   // coefficient of the swept (minor) coordinate
     const float cmin = rows_major ? sn : cs;   // coefficient of the line (major) coordinate
     const float inv = 1.0f / cmaj;
+    // left end of the window of voxels whose coordinate can fall in [j-1, j+1)
     const float start = static_cast<float>(half) - 1.0f / fabsf(cmaj) - 0.01f;
     const int64_t slab = static_cast<int64_t>(N) * N;
-    const float* vz = vol + static_cast<int64_t>(z0) * slab;
+    // a line is a row of vol (rows-major angles) or of its transpose: both
+    // contiguous in memory
+    const float* vz = (rows_major ? vol : volT) + static_cast<int64_t>(z0) * slab;
     float acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0f;
@@ -295,7 +302,7 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
             const int jj = min((lane & 1) ? jb + 63 : jb, g.n - 1);
             const int mm = (lane & 2) ? m0 + mr - 1 : m0;
             const float um = static_cast<float>(mm - half) * cmin + g.center_f;
-            s_lo[wv][lane] = coord_floor(__builtin_fmaf(static_cast<float>(jj) - um, inv, start));
+            s_lo[wv][lane] = -coord_floor(-__builtin_fmaf(static_cast<float>(jj) - um, inv, start));
         }
         __syncthreads();
         int xmin = 1 << 30, xmax = -(1 << 30);
@@ -313,13 +320,11 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
         if (staged) {
             for (int idx = threadIdx.x; idx < mr * width; idx += 256) {
                 const int r = idx / width, x = idx - r * width;
-                const int ix = rows_major ? xmin + x : m0 + r;
-                const int iy = rows_major ? m0 + r : xmin + x;
-                const float* p = vz + static_cast<int64_t>(iy) * N + ix;
+                const float* p = vz + static_cast<int64_t>(m0 + r) * N + xmin + x;
                 float v[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) v[k] = (k < nz) ? p[k * slab] : 0.0f;
-                float4* dst = reinterpret_cast<float4*>(strip + (r * kRadonStrip + x) * K);
+                float4* dst = reinterpret_cast<float4*>(strip + (r * kRadonStrip + x) * SP);
 #pragma unroll
                 for (int q = 0; q < K / 4; ++q) dst[q] = reinterpret_cast<const float4*>(v)[q];
             }
@@ -329,7 +334,9 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
             for (int r = 0; r < mr; ++r) {
                 const int m = m0 + r;
                 const float um = static_cast<float>(m - half) * cmin + g.center_f;
-                const int lo = coord_floor(__builtin_fmaf(static_cast<float>(j) - um, inv, start));
+                // first candidate: ceil of the window's left end (the window
+                // is 2/|c| + 0.02 <= 2.85 voxels long, so 3 candidates cover it)
+                const int lo = -coord_floor(-__builtin_fmaf(static_cast<float>(j) - um, inv, start));
                 const int bm = m >> 5;
                 const float dm = static_cast<float>(m & 31);
 #pragma unroll
@@ -348,16 +355,18 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
                     const float w = coord_frac(s);
                     float wt = (j0 == j) ? 1.0f - w : ((j0 + 1 == j) ? w : 0.0f);
                     wt = inside ? wt : 0.0f;
-                    if (wt != 0.0f) {
+                    if (staged) {  // zero weights add exact zeros: no branch
                         float val[K];
-                        if (staged) {
-                            const int xo = min(max(vc - xmin, 0), kRadonStrip - 1);
-                            const float4* src = reinterpret_cast<const float4*>(strip + (r * kRadonStrip + xo) * K);
+                        const int xo = min(max(vc - xmin, 0), kRadonStrip - 1);
+                        const float4* src = reinterpret_cast<const float4*>(strip + (r * kRadonStrip + xo) * SP);
 #pragma unroll
-                            for (int q = 0; q < K / 4; ++q) reinterpret_cast<float4*>(val)[q] = src[q];
-                        } else {
-                            const int ix = rows_major ? vc : m, iy = rows_major ? m : vc;
-                            const float* p = vz + static_cast<int64_t>(iy) * N + ix;
+                        for (int q = 0; q < K / 4; ++q) reinterpret_cast<float4*>(val)[q] = src[q];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) acc[k] = __builtin_fmaf(wt, val[k], acc[k]);
+                    } else if (wt != 0.0f) {
+                        float val[K];
+                        {
+                            const float* p = vz + static_cast<int64_t>(m) * N + vc;
 #pragma unroll
                             for (int k = 0; k < K; ++k) val[k] = (k < nz) ? p[k * slab] : 0.0f;
                         }
@@ -444,19 +453,69 @@ hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st) {
-    constexpr int K = kRadonSlices;
+namespace {
+
+// out[z][x][y] = in[z][y][x] for N x N slices: 64 x 64 tiles through LDS
+// (65-float rows, so the transposed reads do not share banks), coalesced
+// reads and writes.
+__global__ void __launch_bounds__(256) k_transpose(const float* __restrict__ in, float* __restrict__ out, int N) {
+    __shared__ float t[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 64;
+    const int64_t slab = static_cast<int64_t>(N) * N;
+    const float* src = in + blockIdx.z * slab;
+    float* dst = out + blockIdx.z * slab;
+    for (int r = ty; r < 64; r += 4) {
+        const int y = y0 + r, x = x0 + tx;
+        if (y < N && x < N) t[r][tx] = src[static_cast<int64_t>(y) * N + x];
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int x = x0 + r, y = y0 + tx;
+        if (y < N && x < N) dst[static_cast<int64_t>(x) * N + y] = t[tx][r];
+    }
+}
+
+template <int K>
+hipError_t launch_radon_k(const GeoTables& g, const float* vol, const float* volT, int n_rows, float* sino,
+                          hipStream_t st) {
     const int jgroups = (g.n + 63) / 64;
     const int groups = (g.n_rows_major + 3) / 4 + (g.na - g.n_rows_major + 3) / 4;
-    const size_t lds = sizeof(float) * kRadonLines * kRadonStrip * K + sizeof(int) * 16 * static_cast<size_t>(g.nb);
+    const size_t lds = sizeof(float) * kRadonLines * kRadonStrip * radon_pitch<K>() +
+                       sizeof(int) * 16 * static_cast<size_t>(g.nb);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     const dim3 grid(static_cast<unsigned>(jgroups * groups), static_cast<unsigned>((n_rows + K - 1) / K));
-    hipLaunchKernelGGL((k_radon<K>), grid, dim3(256), lds, st, g, vol, n_rows, sino);
+    hipLaunchKernelGGL((k_radon<K>), grid, dim3(256), lds, st, g, vol, volT, n_rows, sino);
     return hipGetLastError();
+}
+
+}  // namespace
+
+size_t radon_workspace_bytes(const GeoTables& g, int n_rows) {
+    return g.n_rows_major < g.na ? sizeof(float) * static_cast<size_t>(n_rows) * g.N * g.N : 0;
+}
+
+// Angles that sweep columns (|sin| > |cos|) read a transposed copy of the
+// volume, so their lines are contiguous too.  16 slices per work-group
+// amortise each candidate's coordinate over twice the slices; chunks of 8 rows
+// or fewer use 8.
+hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
+                        hipStream_t st) {
+    const float* volT = vol;
+    if (g.n_rows_major < g.na) {
+        const dim3 tg(static_cast<unsigned>((g.N + 63) / 64), static_cast<unsigned>((g.N + 63) / 64),
+                      static_cast<unsigned>(n_rows));
+        hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, vol, workspace, g.N);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        volT = workspace;
+    }
+    return n_rows > 8 ? launch_radon_k<16>(g, vol, volT, n_rows, sino, st)
+                      : launch_radon_k<8>(g, vol, volT, n_rows, sino, st);
 }
 
 }  // namespace tp

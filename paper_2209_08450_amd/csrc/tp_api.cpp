@@ -484,11 +484,30 @@ tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtyp
     return TP_OK;
 }
 
-tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float* sino, void* stream) {
+size_t tp_radon_workspace_bytes(const tp_plan* plan, int32_t n_rows) {
+    if (!plan || n_rows <= 0) return 0;
+    return tp::radon_workspace_bytes(plan->geo, n_rows);
+}
+
+tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float* sino, void* workspace,
+                   size_t workspace_bytes, void* stream) {
     if (!plan) return fail(TP_EINVAL, "plan is null");
     if (!vol || !sino) return fail(TP_EINVAL, "null buffer");
-    if (n_rows <= 0 || (n_rows + 7) / 8 > 65535) return fail(TP_EINVAL, "n_rows=%d out of range", n_rows);
-    hipError_t e = tp::launch_radon(plan->geo, vol, n_rows, sino, static_cast<hipStream_t>(stream));
+    if (n_rows <= 0 || n_rows > 65535) return fail(TP_EINVAL, "n_rows=%d out of range [1, 65535]", n_rows);
+    const size_t need = tp::radon_workspace_bytes(plan->geo, n_rows);
+    if (need > 0) {
+        if (!workspace) return fail(TP_EINVAL, "workspace is null (%zu bytes needed)", need);
+        if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(TP_EINVAL, "workspace not 256-byte aligned");
+        if (workspace_bytes < need) return fail(TP_EINVAL, "workspace %zu < %zu bytes", workspace_bytes, need);
+        const char* w0 = static_cast<const char*>(workspace);
+        const char* v0 = reinterpret_cast<const char*>(vol);
+        const char* s0 = reinterpret_cast<const char*>(sino);
+        const size_t vb = need, sb = sizeof(float) * static_cast<size_t>(n_rows) * plan->na * plan->n;
+        if ((w0 < v0 + vb && v0 < w0 + need) || (w0 < s0 + sb && s0 < w0 + need))
+            return fail(TP_EINVAL, "workspace overlaps vol or sino");
+    }
+    hipError_t e = tp::launch_radon(plan->geo, vol, n_rows, sino, static_cast<float*>(workspace),
+                                    static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "radon launch");
     return TP_OK;
 }

@@ -65,7 +65,9 @@ hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt,
                               float* vol, int accumulate, int slices_per_block, int angles_per_block,
                               hipStream_t st);
 size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_block);
-hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st);
+size_t radon_workspace_bytes(const GeoTables& g, int n_rows);
+hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
+                        hipStream_t st);
 
 // ---- detector coordinate decisions shared by backprojection and radon ----
 // Offset of voxel (dx, dy) within its 32x32 tile at one angle; bf is the

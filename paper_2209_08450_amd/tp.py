@@ -57,7 +57,8 @@ _normalize = _proto("tp_normalize", _c_i32, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
                     _c_i32, _c_i32, _c_vp, _c_vp, _c_sz, _c_vp)
 _filter = _proto("tp_filter", _c_i32, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp)
 _backproject = _proto("tp_backproject", _c_i32, _c_vp, _c_vp, _c_i32, _c_i32, _c_f, _c_vp, _c_i32, _c_vp)
-_radon = _proto("tp_radon", _c_i32, _c_vp, _c_vp, _c_i32, _c_vp, _c_vp)
+_radon = _proto("tp_radon", _c_i32, _c_vp, _c_vp, _c_i32, _c_vp, _c_vp, _c_sz, _c_vp)
+_radon_ws = _proto("tp_radon_workspace_bytes", _c_sz, _c_vp, _c_i32)
 _fbp_ws = _proto("tp_fbp_workspace_bytes", _c_sz, _c_vp, _c_i32, _c_i32)
 _fbp_chunk = _proto("tp_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32,
                     _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp)
@@ -189,6 +190,9 @@ class Plan:
     def fbp_workspace_bytes(self, n_rows: int, storage) -> int:
         return int(_fbp_ws(self._h, int(n_rows), dtype_code(storage)))
 
+    def radon_workspace_bytes(self, n_rows: int) -> int:
+        return int(_radon_ws(self._h, int(n_rows)))
+
 
 def filter_code(kind) -> int:
     """Filter window code from a name ('ramp', 'shepp', 'parzen') or a code."""
@@ -276,8 +280,12 @@ def backproject(plan: Plan, filt, scale=None, out=None, accumulate: bool = False
     return out
 
 
-def radon(plan: Plan, vol, out=None, stream=None):
-    """Volume [rows][N][N] float32 -> projections [rows][n_angles][n_det] float32."""
+def radon(plan: Plan, vol, out=None, workspace=None, stream=None):
+    """Volume [rows][N][N] float32 -> projections [rows][n_angles][n_det] float32.
+
+    ``workspace``: optional device buffer of at least
+    ``plan.radon_workspace_bytes(rows)`` bytes (allocated when omitted).
+    """
     torch = _torch()
     if vol.dtype != torch.float32 or vol.dim() != 3 or tuple(vol.shape[1:]) != (plan.n_vox, plan.n_vox) \
             or not vol.is_contiguous():
@@ -285,7 +293,12 @@ def radon(plan: Plan, vol, out=None, stream=None):
     n_rows = int(vol.shape[0])
     if out is None:
         out = torch.empty((n_rows, plan.n_angles, plan.n_det), dtype=torch.float32, device=vol.device)
-    _check(_radon(plan.handle, _dev(vol, "vol"), n_rows, _dev(out, "out"), _stream_ptr(stream)))
+    need = plan.radon_workspace_bytes(n_rows)
+    if workspace is None and need > 0:
+        workspace = _workspace(need, vol.device)
+    ws_ptr = _dev(workspace, "workspace") if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(_radon(plan.handle, _dev(vol, "vol"), n_rows, _dev(out, "out"), ws_ptr, ws_bytes, _stream_ptr(stream)))
     return out
 
 

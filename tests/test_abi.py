@@ -88,7 +88,8 @@ def test_plan_null_handles(tp):
     nul = ctypes.c_void_p()
     assert tp._plan_set_tuning(nul, tp.TP_F32, 4, 32) == tp.TP_EINVAL
     assert tp._backproject(nul, nul, 0, 1, 1.0, nul, 0, nul) == tp.TP_EINVAL
-    assert tp._radon(nul, nul, 1, nul, nul) == tp.TP_EINVAL
+    assert tp._radon(nul, nul, 1, nul, nul, 0, nul) == tp.TP_EINVAL
+    assert tp._radon_ws(nul, 4) == 0
     assert tp._plan_destroy(nul) == tp.TP_OK
 
 

@@ -233,3 +233,31 @@ def test_backproject_more_than_4gb_of_rows(tp):
         assert rel_l2(got, want) < 3e-5, z
     del q, vol
     torch.cuda.empty_cache()
+
+
+def test_radon_workspace_contract(tp):
+    import torch
+    na, n, rows = 30, 64, 3
+    rng = np.random.default_rng(41)
+    ang = synth.uniform_angles(na)
+    plan = tp.Plan(ang, n, 31.5)
+    x = to_dev(rng.standard_normal((rows, n, n)).astype(np.float32))
+    need = plan.radon_workspace_bytes(rows)
+    assert need == rows * n * n * 4  # a transposed copy: some angles sweep columns
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    note("radon explicit workspace")
+    ref = tp.radon(plan, x)
+    assert torch.equal(tp.radon(plan, x, workspace=ws), ref)
+    with pytest.raises(tp.TpError, match="workspace"):
+        tp.radon(plan, x, workspace=ws[: need // 2])
+    with pytest.raises(tp.TpError, match="overlaps"):
+        tp.radon(plan, x, workspace=x.view(torch.uint8).reshape(-1))
+    # every angle within 45 degrees of the x axis: no transpose, no workspace
+    ang2 = np.linspace(-0.7, 0.7, 25)
+    plan2 = tp.Plan(ang2, n, 31.5)
+    assert plan2.radon_workspace_bytes(rows) == 0
+    note("radon without workspace")
+    got = to_host(tp.radon(plan2, x)).astype(np.float64)
+    want = oracle.radon(to_host(x).astype(np.float64), ang2, 31.5, n)
+    assert rel_l2(got, want) < 1e-5
+    torch.cuda.synchronize()
