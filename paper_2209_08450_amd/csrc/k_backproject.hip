@@ -247,50 +247,88 @@ constexpr int kRadonStrip = 128;
 // neighbouring bins (candidates 1 to 1.41 voxels apart) read distinct banks
 template <int K> constexpr int radon_pitch() { return K + 4; }
 
-template <int K>
+// One line of the sweep for bin j: first candidate and the line's tile entries.
+struct RadonLine {
+    int lo, li;
+    float lf, dm;
+};
+
+__device__ __forceinline__ RadonLine radon_line(int m, int j, int half, float cmin, float inv, float start,
+                                                float center_f, const int2* tl) {
+    RadonLine ln;
+    const float um = static_cast<float>(m - half) * cmin + center_f;
+    // first candidate: ceil of the window's left end (the window is
+    // 2/|c| + 0.02 <= 2.85 voxels long, so 3 candidates cover it)
+    ln.lo = -coord_floor(-__builtin_fmaf(static_cast<float>(j) - um, inv, start));
+    const int2 e = tl[m >> 5];
+    ln.li = e.x;
+    ln.lf = __int_as_float(e.y);
+    ln.dm = static_cast<float>(m & 31);
+    return ln;
+}
+
+// Weight of candidate t of a line in bin j, from the backprojector's exact
+// expression (bi = xi + yi, bf = xf + yf, then tile_offset): (1 - w) when
+// floor lands on j, w when on j - 1, else 0.  vc: the clamped voxel index.
+template <bool ROWS>
+__device__ __forceinline__ float radon_weight(const RadonLine& ln, int t, int j, int N, float cs, float sn,
+                                              const int2* tc, int& vc) {
+    const int v = ln.lo + t;
+    vc = min(max(v, 0), N - 1);
+    const int bv = vc >> 5;
+    const float dv = static_cast<float>(vc & 31);
+    const int2 e = tc[bv];
+    const int bi = e.x + ln.li;
+    const float bf = __int_as_float(e.y) + ln.lf;
+    const float s = ROWS ? tile_offset(dv, ln.dm, cs, sn, bf) : tile_offset(ln.dm, dv, cs, sn, bf);
+    const int j0 = bi + coord_floor(s);
+    const float w = coord_frac(s);
+    const float wt = (j0 == j) ? 1.0f - w : ((j0 + 1 == j) ? w : 0.0f);
+    return (v >= 0 && v < N) ? wt : 0.0f;
+}
+
+template <int K, bool ROWS>
 __global__ void __launch_bounds__(256)
-k_radon(GeoTables g, const float* __restrict__ vol, const float* __restrict__ volT, int n_rows,
-        float* __restrict__ sino) {
+k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restrict__ sino) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_lo[4][4];
     const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
     constexpr int SP = radon_pitch<K>();
     float* strip = reinterpret_cast<float*>(smem);                        // [lines][kRadonStrip][SP]
-    int* tabs = reinterpret_cast<int*>(strip + kRadonLines * kRadonStrip * SP);  // [4 waves][4][nb]
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int2* tabs = reinterpret_cast<int2*>(strip + kRadonLines * kRadonStrip * SP);  // [4 waves][2][nb]
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jgroups = (g.n + 63) >> 6;
     const int jb = (blockIdx.x % jgroups) * 64;
     const int grp = blockIdx.x / jgroups;
-    const int groups_rows = (g.n_rows_major + 3) / 4;
-    const bool rows_major = grp < groups_rows;
-    const int e0 = rows_major ? grp * 4 : g.n_rows_major + (grp - groups_rows) * 4;
-    const int e_end = rows_major ? min(g.n_rows_major, e0 + 4) : min(na, e0 + 4);
+    // this launch covers the angles that sweep rows (ROWS) or columns
+    const int e0 = ROWS ? grp * 4 : g.n_rows_major + grp * 4;
+    const int e_end = ROWS ? min(g.n_rows_major, e0 + 4) : min(na, e0 + 4);
     const int e = e0 + wv;
     const bool active = e < e_end;
     const int a = active ? g.order[e] : g.order[e0];
     const int j = jb + lane;
     const int z0 = blockIdx.y * K;
     const int nz = min(K, n_rows - z0);
-    int* sxi = tabs + wv * 4 * nb;
-    float* sxf = reinterpret_cast<float*>(sxi + nb);
-    int* syi = reinterpret_cast<int*>(sxf + nb);
-    float* syf = reinterpret_cast<float*>(syi + nb);
+    // tables of this wave's angle: the candidate's tile (along the line) and
+    // the line's tile, integer and fraction parts
+    int2* tc = tabs + wv * 2 * nb;  // (integer, fraction bits) per tile
+    int2* tl = tc + nb;
     for (int b = lane; b < nb; b += 64) {
-        sxi[b] = g.xi[b * na + a];
-        sxf[b] = g.xf[b * na + a];
-        syi[b] = g.yi[b * na + a];
-        syf[b] = g.yf[b * na + a];
+        const int xi = g.xi[b * na + a], yi = g.yi[b * na + a];
+        const int xf = __float_as_int(g.xf[b * na + a]), yf = __float_as_int(g.yf[b * na + a]);
+        tc[b] = ROWS ? make_int2(xi, xf) : make_int2(yi, yf);
+        tl[b] = ROWS ? make_int2(yi, yf) : make_int2(xi, xf);
     }
     const float cs = g.cs[a], sn = g.sn[a];
-    const float cmaj = rows_major ? cs : sn;   // coefficient of the swept (minor) coordinate
-    const float cmin = rows_major ? sn : cs;   // coefficient of the line (major) coordinate
+    const float cmaj = ROWS ? cs : sn;   // coefficient of the swept coordinate
+    const float cmin = ROWS ? sn : cs;   // coefficient of the line coordinate
     const float inv = 1.0f / cmaj;
     // left end of the window of voxels whose coordinate can fall in [j-1, j+1)
     const float start = static_cast<float>(half) - 1.0f / fabsf(cmaj) - 0.01f;
     const int64_t slab = static_cast<int64_t>(N) * N;
-    // a line is a row of vol (rows-major angles) or of its transpose: both
-    // contiguous in memory
-    const float* vz = (rows_major ? vol : volT) + static_cast<int64_t>(z0) * slab;
+    // a line is a row of the volume (ROWS) or of its transpose: contiguous
+    const float* vz = vol + static_cast<int64_t>(z0) * slab;
     float acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0f;
@@ -317,61 +355,66 @@ k_radon(GeoTables g, const float* __restrict__ vol, const float* __restrict__ vo
         xmax = min(xmax + 1, N - 1);
         const int width = xmax - xmin + 1;
         const bool staged = width > 0 && width <= kRadonStrip;
-        if (staged) {
-            for (int idx = threadIdx.x; idx < mr * width; idx += 256) {
-                const int r = idx / width, x = idx - r * width;
-                const float* p = vz + static_cast<int64_t>(m0 + r) * N + xmin + x;
-                float v[K];
+        if (staged && wv < mr) {  // wave r stages line m0 + r, positions lane and lane + 64
+            const float* row = vz + static_cast<int64_t>(m0 + wv) * N + xmin;
 #pragma unroll
-                for (int k = 0; k < K; ++k) v[k] = (k < nz) ? p[k * slab] : 0.0f;
-                float4* dst = reinterpret_cast<float4*>(strip + (r * kRadonStrip + x) * SP);
+            for (int h = 0; h < kRadonStrip; h += 64) {
+                const int x = lane + h;
+                if (x < width) {
+                    float v[K];
 #pragma unroll
-                for (int q = 0; q < K / 4; ++q) dst[q] = reinterpret_cast<const float4*>(v)[q];
+                    for (int k = 0; k < K; ++k) {
+                        // slices past the last row re-read it (their sums are never
+                        // stored); the opaque index keeps the offsets scalar, not hoisted
+                        int kk = min(k, nz - 1);
+                        asm volatile("" : "+s"(kk));
+                        v[k] = row[x + kk * slab];
+                    }
+                    float4* dst = reinterpret_cast<float4*>(strip + __umul24(wv * kRadonStrip + x, SP));
+#pragma unroll
+                    for (int q = 0; q < K / 4; ++q) dst[q] = reinterpret_cast<const float4*>(v)[q];
+                }
             }
         }
         __syncthreads();
         if (active && j < g.n) {
-            for (int r = 0; r < mr; ++r) {
-                const int m = m0 + r;
-                const float um = static_cast<float>(m - half) * cmin + g.center_f;
-                // first candidate: ceil of the window's left end (the window
-                // is 2/|c| + 0.02 <= 2.85 voxels long, so 3 candidates cover it)
-                const int lo = -coord_floor(-__builtin_fmaf(static_cast<float>(j) - um, inv, start));
-                const int bm = m >> 5;
-                const float dm = static_cast<float>(m & 31);
+            // the staged and the global variant are separate loops, so the
+            // uniform choice is not re-tested (and the sums not copied) per candidate
+            if (staged) {
+                for (int r = 0; r < mr; ++r) {
+                    RadonLine ln = radon_line(m0 + r, j, half, cmin, inv, start, g.center_f, tl);
 #pragma unroll
-                for (int t = 0; t < kCand; ++t) {
-                    const int v = lo + t;
-                    const bool inside = v >= 0 && v < N;
-                    const int vc = min(max(v, 0), N - 1);
-                    const int bv = vc >> 5;
-                    const float dv = static_cast<float>(vc & 31);
-                    const int bx = rows_major ? bv : bm, by = rows_major ? bm : bv;
-                    const float dx = rows_major ? dv : dm, dy = rows_major ? dm : dv;
-                    const int bi = sxi[bx] + syi[by];
-                    const float bf = sxf[bx] + syf[by];
-                    const float s = tile_offset(dx, dy, cs, sn, bf);
-                    const int j0 = bi + coord_floor(s);
-                    const float w = coord_frac(s);
-                    float wt = (j0 == j) ? 1.0f - w : ((j0 + 1 == j) ? w : 0.0f);
-                    wt = inside ? wt : 0.0f;
-                    if (staged) {  // zero weights add exact zeros: no branch
-                        float val[K];
+                    for (int t = 0; t < kCand; ++t) {
+                        int vc;
+                        const float wt = radon_weight<ROWS>(ln, t, j, N, cs, sn, tc, vc);
                         const int xo = min(max(vc - xmin, 0), kRadonStrip - 1);
-                        const float4* src = reinterpret_cast<const float4*>(strip + (r * kRadonStrip + xo) * SP);
+                        const float4* src =
+                            reinterpret_cast<const float4*>(strip + __umul24(r * kRadonStrip + xo, SP));
+                        float val[K];
 #pragma unroll
                         for (int q = 0; q < K / 4; ++q) reinterpret_cast<float4*>(val)[q] = src[q];
+                        // zero weights add exact zeros: no branch
 #pragma unroll
                         for (int k = 0; k < K; ++k) acc[k] = __builtin_fmaf(wt, val[k], acc[k]);
-                    } else if (wt != 0.0f) {
-                        float val[K];
-                        {
+                    }
+                }
+            } else {
+                for (int r = 0; r < mr; ++r) {
+                    const int m = m0 + r;
+                    RadonLine ln = radon_line(m, j, half, cmin, inv, start, g.center_f, tl);
+#pragma unroll
+                    for (int t = 0; t < kCand; ++t) {
+                        int vc;
+                        const float wt = radon_weight<ROWS>(ln, t, j, N, cs, sn, tc, vc);
+                        if (wt != 0.0f) {
                             const float* p = vz + static_cast<int64_t>(m) * N + vc;
 #pragma unroll
-                            for (int k = 0; k < K; ++k) val[k] = (k < nz) ? p[k * slab] : 0.0f;
+                            for (int k = 0; k < K; ++k) {
+                                int kk = min(k, nz - 1);
+                                asm volatile("" : "+s"(kk));
+                                acc[k] = __builtin_fmaf(wt, p[kk * slab], acc[k]);
+                            }
                         }
-#pragma unroll
-                        for (int k = 0; k < K; ++k) acc[k] = __builtin_fmaf(wt, val[k], acc[k]);
                     }
                 }
             }
@@ -476,21 +519,29 @@ __global__ void __launch_bounds__(256) k_transpose(const float* __restrict__ in,
     }
 }
 
-template <int K>
-hipError_t launch_radon_k(const GeoTables& g, const float* vol, const float* volT, int n_rows, float* sino,
-                          hipStream_t st) {
+template <int K, bool ROWS>
+hipError_t launch_radon_k(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st) {
     const int jgroups = (g.n + 63) / 64;
-    const int groups = (g.n_rows_major + 3) / 4 + (g.na - g.n_rows_major + 3) / 4;
+    const int groups = ROWS ? (g.n_rows_major + 3) / 4 : (g.na - g.n_rows_major + 3) / 4;
+    if (groups == 0) return hipSuccess;
     const size_t lds = sizeof(float) * kRadonLines * kRadonStrip * radon_pitch<K>() +
-                       sizeof(int) * 16 * static_cast<size_t>(g.nb);
+                       sizeof(int2) * 8 * static_cast<size_t>(g.nb);
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K, ROWS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     const dim3 grid(static_cast<unsigned>(jgroups * groups), static_cast<unsigned>((n_rows + K - 1) / K));
-    hipLaunchKernelGGL((k_radon<K>), grid, dim3(256), lds, st, g, vol, volT, n_rows, sino);
+    hipLaunchKernelGGL((k_radon<K, ROWS>), grid, dim3(256), lds, st, g, vol, n_rows, sino);
     return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_radon_both(const GeoTables& g, const float* vol, const float* volT, int n_rows, float* sino,
+                             hipStream_t st) {
+    hipError_t e = launch_radon_k<K, true>(g, vol, n_rows, sino, st);
+    if (e != hipSuccess) return e;
+    return launch_radon_k<K, false>(g, volT, n_rows, sino, st);
 }
 
 }  // namespace
@@ -500,9 +551,8 @@ size_t radon_workspace_bytes(const GeoTables& g, int n_rows) {
 }
 
 // Angles that sweep columns (|sin| > |cos|) read a transposed copy of the
-// volume, so their lines are contiguous too.  16 slices per work-group
-// amortise each candidate's coordinate over twice the slices; chunks of 8 rows
-// or fewer use 8.
+// volume, so their lines are contiguous too.  32 slices per work-group
+// amortise each candidate's coordinate; smaller chunks use 16 or 8.
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
                         hipStream_t st) {
     const float* volT = vol;
@@ -514,8 +564,9 @@ hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float*
         if (e != hipSuccess) return e;
         volT = workspace;
     }
-    return n_rows > 8 ? launch_radon_k<16>(g, vol, volT, n_rows, sino, st)
-                      : launch_radon_k<8>(g, vol, volT, n_rows, sino, st);
+    if (n_rows > 16) return launch_radon_both<32>(g, vol, volT, n_rows, sino, st);
+    return n_rows > 8 ? launch_radon_both<16>(g, vol, volT, n_rows, sino, st)
+                      : launch_radon_both<8>(g, vol, volT, n_rows, sino, st);
 }
 
 }  // namespace tp

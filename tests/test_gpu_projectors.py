@@ -261,3 +261,22 @@ def test_radon_workspace_contract(tp):
     want = oracle.radon(to_host(x).astype(np.float64), ang2, 31.5, n)
     assert rel_l2(got, want) < 1e-5
     torch.cuda.synchronize()
+
+
+def test_radon_32_slice_groups(tp):
+    # more than 16 rows take 32 slices per work-group: one full group and a
+    # partial one (40 = 32 + 8), angles sweeping both rows and columns
+    na, n, rows = 50, 96, 40
+    rng = np.random.default_rng(43)
+    ang = synth.uniform_angles(na) + 0.05
+    plan = tp.Plan(ang, n, 47.3)
+    x = rng.standard_normal((rows, n, n)).astype(np.float32)
+    note("radon 40 rows (32-slice groups)")
+    got = to_host(tp.radon(plan, to_dev(x))).astype(np.float64)
+    want = oracle.radon(x.astype(np.float64), ang, 47.3, n)
+    assert rel_l2(got, want) < 1e-5
+    for z in (0, 31, 32, 39):
+        assert rel_l2(got[z], want[z]) < 1e-5, z
+    # each slice alone gives the same bits as inside the group
+    one = to_host(tp.radon(plan, to_dev(np.ascontiguousarray(x[33:34])))).astype(np.float64)
+    assert np.array_equal(one[0], got[33])
