@@ -233,7 +233,7 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
 // the same unrolled loop.  Each candidate's exact (j0, w) comes from the
 // backprojector's expression with the angle's tile tables staged in LDS;
 // weights are (1-w) for j0 == j, w for j0+1 == j, else 0.
-// Lines are processed in blocks of kRadonLines: the work-group stages the
+// Lines are processed in blocks of radon_lines: the work-group stages the
 // strip its 4 angles x 64 bins can touch on those lines (all K slices,
 // [line][position][slice]) into LDS with coalesced loads, so each voxel is
 // fetched once per work-group instead of once per bin and angle.  A strip
@@ -241,7 +241,9 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
 // instead, with the same arithmetic and order.  No atomics: every output is
 // summed by one lane, lines ascending, candidates ascending.
 constexpr int kCand = 3;
-constexpr int kRadonLines = 4;
+// lines staged per block: 4, or 2 for 32 slices (keeps the strip at 37 KB,
+// four work-groups per CU)
+template <int K> constexpr int radon_lines() { return K >= 32 ? 2 : 4; }
 constexpr int kRadonStrip = 128;
 // floats between strip positions: an odd number of 16-byte bank groups, so
 // neighbouring bins (candidates 1 to 1.41 voxels apart) read distinct banks
@@ -295,7 +297,8 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
     const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
     constexpr int SP = radon_pitch<K>();
     float* strip = reinterpret_cast<float*>(smem);                        // [lines][kRadonStrip][SP]
-    int2* tabs = reinterpret_cast<int2*>(strip + kRadonLines * kRadonStrip * SP);  // [4 waves][2][nb]
+    constexpr int LINES = radon_lines<K>();
+    int2* tabs = reinterpret_cast<int2*>(strip + LINES * kRadonStrip * SP);  // [4 waves][2][nb]
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jgroups = (g.n + 63) >> 6;
@@ -333,8 +336,8 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0f;
 
-    for (int m0 = 0; m0 < N; m0 += kRadonLines) {
-        const int mr = min(kRadonLines, N - m0);
+    for (int m0 = 0; m0 < N; m0 += LINES) {
+        const int mr = min(LINES, N - m0);
         // candidate starts at the block's corners (first/last bin, first/last line)
         if (lane < 4) {
             const int jj = min((lane & 1) ? jb + 63 : jb, g.n - 1);
@@ -524,7 +527,7 @@ hipError_t launch_radon_k(const GeoTables& g, const float* vol, int n_rows, floa
     const int jgroups = (g.n + 63) / 64;
     const int groups = ROWS ? (g.n_rows_major + 3) / 4 : (g.na - g.n_rows_major + 3) / 4;
     if (groups == 0) return hipSuccess;
-    const size_t lds = sizeof(float) * kRadonLines * kRadonStrip * radon_pitch<K>() +
+    const size_t lds = sizeof(float) * radon_lines<K>() * kRadonStrip * radon_pitch<K>() +
                        sizeof(int2) * 8 * static_cast<size_t>(g.nb);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K, ROWS>),
