@@ -235,19 +235,18 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
 // weights are (1-w) for j0 == j, w for j0+1 == j, else 0.
 // Lines are processed in blocks of radon_lines: the work-group stages the
 // strip its 4 angles x 64 bins can touch on those lines (all K slices,
-// [line][position][slice]) into LDS with coalesced loads, so each voxel is
+// [line][slice / 4][position] of float4, so a wave's read of one 4-slice
+// chunk at its ~1.2-voxel-spaced positions touches near-consecutive 16-byte
+// words) into LDS with coalesced loads, so each voxel is
 // fetched once per work-group instead of once per bin and angle.  A strip
 // wider than kRadonStrip (sparse angle sets) is read from global memory
 // instead, with the same arithmetic and order.  No atomics: every output is
 // summed by one lane, lines ascending, candidates ascending.
 constexpr int kCand = 3;
-// lines staged per block: 4, or 2 for 32 slices (keeps the strip at 37 KB,
+// lines staged per block: 4, or 2 for 32 slices (keeps the strip at 32 KB,
 // four work-groups per CU)
 template <int K> constexpr int radon_lines() { return K >= 32 ? 2 : 4; }
 constexpr int kRadonStrip = 128;
-// floats between strip positions: an odd number of 16-byte bank groups, so
-// neighbouring bins (candidates 1 to 1.41 voxels apart) read distinct banks
-template <int K> constexpr int radon_pitch() { return K + 4; }
 
 // One line of the sweep for bin j: first candidate and the line's tile entries.
 struct RadonLine {
@@ -295,10 +294,9 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_lo[4][4];
     const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
-    constexpr int SP = radon_pitch<K>();
-    float* strip = reinterpret_cast<float*>(smem);                        // [lines][kRadonStrip][SP]
+    float4* strip = reinterpret_cast<float4*>(smem);                      // [lines][K / 4][kRadonStrip]
     constexpr int LINES = radon_lines<K>();
-    int2* tabs = reinterpret_cast<int2*>(strip + LINES * kRadonStrip * SP);  // [4 waves][2][nb]
+    int2* tabs = reinterpret_cast<int2*>(strip + LINES * (K / 4) * kRadonStrip);  // [4 waves][2][nb]
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jgroups = (g.n + 63) >> 6;
@@ -373,9 +371,9 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
                         asm volatile("" : "+s"(kk));
                         v[k] = row[x + kk * slab];
                     }
-                    float4* dst = reinterpret_cast<float4*>(strip + __umul24(wv * kRadonStrip + x, SP));
+                    float4* dst = strip + wv * (K / 4) * kRadonStrip + x;
 #pragma unroll
-                    for (int q = 0; q < K / 4; ++q) dst[q] = reinterpret_cast<const float4*>(v)[q];
+                    for (int q = 0; q < K / 4; ++q) dst[q * kRadonStrip] = reinterpret_cast<const float4*>(v)[q];
                 }
             }
         }
@@ -391,11 +389,10 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
                         int vc;
                         const float wt = radon_weight<ROWS>(ln, t, j, N, cs, sn, tc, vc);
                         const int xo = min(max(vc - xmin, 0), kRadonStrip - 1);
-                        const float4* src =
-                            reinterpret_cast<const float4*>(strip + __umul24(r * kRadonStrip + xo, SP));
+                        const float4* src = strip + r * (K / 4) * kRadonStrip + xo;
                         float val[K];
 #pragma unroll
-                        for (int q = 0; q < K / 4; ++q) reinterpret_cast<float4*>(val)[q] = src[q];
+                        for (int q = 0; q < K / 4; ++q) reinterpret_cast<float4*>(val)[q] = src[q * kRadonStrip];
                         // zero weights add exact zeros: no branch
 #pragma unroll
                         for (int k = 0; k < K; ++k) acc[k] = __builtin_fmaf(wt, val[k], acc[k]);
@@ -527,7 +524,7 @@ hipError_t launch_radon_k(const GeoTables& g, const float* vol, int n_rows, floa
     const int jgroups = (g.n + 63) / 64;
     const int groups = ROWS ? (g.n_rows_major + 3) / 4 : (g.na - g.n_rows_major + 3) / 4;
     if (groups == 0) return hipSuccess;
-    const size_t lds = sizeof(float) * radon_lines<K>() * kRadonStrip * radon_pitch<K>() +
+    const size_t lds = sizeof(float) * radon_lines<K>() * K * kRadonStrip +
                        sizeof(int2) * 8 * static_cast<size_t>(g.nb);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K, ROWS>),
