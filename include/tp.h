@@ -121,7 +121,8 @@ tp_status tp_filter_response(int32_t pad_len, tp_filter_kind kind, double* H);
  *        0 => n_rows*n_det.  n_dark, n_flat >= 1, each <= 256 (exact sums).
  * sino:  dev [n_rows][n_angles][n_det] of out_dtype (RNE rounding for F16/BF16).
  * workspace: dev, >= tp_normalize_workspace_bytes(n_rows, n_det) bytes,
- *        256-byte aligned; holds D and max(F - D, 1) between two kernels.
+ *        256-byte aligned; holds D and 1 / max(F - D, 1) between two kernels
+ *        (the normaliser multiplies by the stored reciprocal).
  * ------------------------------------------------------------------------ */
 size_t tp_normalize_workspace_bytes(int32_t n_rows, int32_t n_det);
 tp_status tp_normalize(const uint16_t* proj, int64_t proj_stride,

@@ -23,7 +23,6 @@
 namespace tp {
 namespace {
 
-constexpr float kMinTransmission = 1e-6f;
 constexpr int kMaxPerThread4 = 4;  // radix-4 butterflies per thread (L / (4 B) with B = L / 16)
 constexpr int kMaxPerThread2 = 8;  // radix-2 butterflies per thread
 
@@ -162,10 +161,9 @@ k_norm_filter(RawInput in, const float* __restrict__ dmean, const float* __restr
     const float* dn = den + static_cast<int64_t>(r) * n;
     for (int j = tid; j < n; j += B) {
         const float d = dm[j], e = dn[j];
-        const float t0 = fmaxf((static_cast<float>(p0[j]) - d) / e, kMinTransmission);
-        float v1 = 0.0f;
-        if (has1) v1 = 0.0f - logf(fmaxf((static_cast<float>(p1[j]) - d) / e, kMinTransmission));
-        buf[off + j] = make_float2(0.0f - logf(t0), v1);
+        const float v0 = neglog_counts(static_cast<float>(p0[j]), d, e);
+        const float v1 = has1 ? neglog_counts(static_cast<float>(p1[j]), d, e) : 0.0f;
+        buf[off + j] = make_float2(v0, v1);
     }
     __syncthreads();
     filter_in_lds(buf, n, off, ft);
@@ -260,10 +258,10 @@ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 // the previous radices.  If LAST, outputs stay in the slots; otherwise they
 // are written to LDS at their Stockham destinations.
 template <int L, int R, bool LAST>
-__device__ __forceinline__ void reg_pass(float2 (&x)[kRegPts], float2* lds, int Ns, const float2* __restrict__ tw) {
+__device__ __forceinline__ void reg_pass(float2 (&x)[kRegPts], float2* lds, int Ns, const float2* __restrict__ tw,
+                                         int t) {
     constexpr int B = L / kRegPts;
     constexpr int NBF = kRegPts / R;
-    const int t = threadIdx.x;
 #pragma unroll
     for (int c = 0; c < NBF; ++c) {
         float2 v[R];
@@ -289,59 +287,59 @@ __device__ __forceinline__ void reg_pass(float2 (&x)[kRegPts], float2* lds, int 
 }
 
 template <int L>
-__device__ __forceinline__ void reg_exchange(float2 (&x)[kRegPts], float2* lds) {
+__device__ __forceinline__ void reg_exchange(float2 (&x)[kRegPts], float2* lds, int t) {
     constexpr int B = L / kRegPts;
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kRegPts; ++s) x[s] = lds[lds_pad(threadIdx.x + B * s)];
+    for (int s = 0; s < kRegPts; ++s) x[s] = lds[lds_pad(t + B * s)];
     __syncthreads();
 }
 
 // Forward DFT of the register-held sequence (slots: element t + B*s in, X[t + B*s] out).
 template <int L>
-__device__ __forceinline__ void reg_fft(float2 (&x)[kRegPts], float2* lds, const float2* __restrict__ tw) {
+__device__ __forceinline__ void reg_fft(float2 (&x)[kRegPts], float2* lds, const float2* __restrict__ tw, int t) {
     static_assert(L >= 1024 && L <= 16384, "register FFT covers 1024..16384");
     constexpr int log2L = (L == 1024) ? 10 : (L == 2048) ? 11 : (L == 4096) ? 12 : (L == 8192) ? 13 : 14;
     constexpr int rem = 1 << (log2L - 8 - ((log2L >= 12) ? 4 : 0));  // radix of the pass after the 16s
     if constexpr (log2L < 12) {
         // 16 x 16 x rem, rem in {4, 8}
-        reg_pass<L, 16, false>(x, lds, 1, tw);
-        reg_exchange<L>(x, lds);
-        reg_pass<L, 16, false>(x, lds, 16, tw);
-        reg_exchange<L>(x, lds);
-        reg_pass<L, rem, true>(x, lds, 256, tw);
+        reg_pass<L, 16, false>(x, lds, 1, tw, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass<L, 16, false>(x, lds, 16, tw, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass<L, rem, true>(x, lds, 256, tw, t);
     } else if constexpr (log2L == 12) {
-        reg_pass<L, 16, false>(x, lds, 1, tw);
-        reg_exchange<L>(x, lds);
-        reg_pass<L, 16, false>(x, lds, 16, tw);
-        reg_exchange<L>(x, lds);
-        reg_pass<L, 16, true>(x, lds, 256, tw);
+        reg_pass<L, 16, false>(x, lds, 1, tw, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass<L, 16, false>(x, lds, 16, tw, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass<L, 16, true>(x, lds, 256, tw, t);
     } else {
         // 16 x 16 x 16 x rem, rem in {2, 4}
-        reg_pass<L, 16, false>(x, lds, 1, tw);
-        reg_exchange<L>(x, lds);
-        reg_pass<L, 16, false>(x, lds, 16, tw);
-        reg_exchange<L>(x, lds);
-        reg_pass<L, 16, false>(x, lds, 256, tw);
-        reg_exchange<L>(x, lds);
-        reg_pass<L, (L >> 12), true>(x, lds, 4096, tw);
+        reg_pass<L, 16, false>(x, lds, 1, tw, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass<L, 16, false>(x, lds, 16, tw, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass<L, 16, false>(x, lds, 256, tw, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass<L, (L >> 12), true>(x, lds, 4096, tw, t);
     }
 }
 
 // Multiply the spectrum by H/L and conjugate, transform again: slots then hold
 // y = conj of (IFFT(H . FFT(u)) * L) / L, i.e. (row0, -row1).
 template <int L>
-__device__ __forceinline__ void reg_filter(float2 (&x)[kRegPts], float2* lds, const FilterTables& ft) {
+__device__ __forceinline__ void reg_filter(float2 (&x)[kRegPts], float2* lds, const FilterTables& ft, int t) {
     constexpr int B = L / kRegPts;
-    reg_fft<L>(x, lds, ft.tw);
+    reg_fft<L>(x, lds, ft.tw, t);
 #pragma unroll
     for (int s = 0; s < kRegPts; ++s) {
-        const float h = ft.H[threadIdx.x + B * s];
+        const float h = ft.H[t + B * s];
         x[s] = make_float2(x[s].x * h, 0.0f - x[s].y * h);
     }
     // no barrier needed: the forward transform's last LDS reads were followed
     // by one, and its last pass ran in registers
-    reg_fft<L>(x, lds, ft.tw);
+    reg_fft<L>(x, lds, ft.tw, t);
 }
 
 template <int L, typename TI, typename TO>
@@ -364,7 +362,7 @@ k_filter_reg(const TI* in, TO* out, int64_t n_lines, int n, int off, FilterTable
         else if (j >= n) x[s] = make_float2(e01, e11);
         else x[s] = make_float2(load_as_float(r0, j), has1 ? load_as_float(r1, j) : 0.0f);
     }
-    reg_filter<L>(x, lds, ft);
+    reg_filter<L>(x, lds, ft, t);
     TO* o0 = out + l0 * n;
     TO* o1 = o0 + n;
 #pragma unroll
@@ -377,54 +375,72 @@ k_filter_reg(const TI* in, TO* out, int64_t n_lines, int n, int off, FilterTable
     }
 }
 
-__device__ __forceinline__ float neglog(float P, float d, float e) {
-    return 0.0f - logf(fmaxf((P - d) / e, kMinTransmission));
-}
+
+// Angle pairs per work-group of the fused kernel: each pair's raw counts are
+// prefetched into registers while the previous pair is transformed.
+constexpr int kPairsPerGroup = 8;
 
 template <int L, typename TO>
 __global__ void __launch_bounds__(L / kRegPts)
-k_norm_filter_reg(RawInput in, const float* __restrict__ dmean, const float* __restrict__ den, int n_angles, int n,
+k_norm_filter_reg(RawInput in, const float* __restrict__ dmean, const float* __restrict__ rden, int n_angles, int n,
                   int off, FilterTables ft, TO* out) {
     extern __shared__ float2 lds[];
     constexpr int B = L / kRegPts;
-    const int t = threadIdx.x;
     const int pairs = (n_angles + 1) >> 1;
-    const int r = blockIdx.x / pairs;
-    const int a0 = 2 * (blockIdx.x - r * pairs);
-    const bool has1 = a0 + 1 < n_angles;
-    const uint16_t* p0 = in.proj + a0 * in.proj_stride + static_cast<int64_t>(r) * n;
-    const uint16_t* p1 = p0 + in.proj_stride;
+    const int groups = (pairs + kPairsPerGroup - 1) / kPairsPerGroup;
+    const int r = blockIdx.x / groups;
+    const int g0 = (blockIdx.x - r * groups) * kPairsPerGroup;
+    const int g1 = min(pairs, g0 + kPairsPerGroup);
     const float* dm = dmean + static_cast<int64_t>(r) * n;
-    const float* dn = den + static_cast<int64_t>(r) * n;
-    // edge values for the padding
-    const float e00 = neglog(static_cast<float>(p0[0]), dm[0], dn[0]);
-    const float e01 = neglog(static_cast<float>(p0[n - 1]), dm[n - 1], dn[n - 1]);
-    const float e10 = has1 ? neglog(static_cast<float>(p1[0]), dm[0], dn[0]) : 0.0f;
-    const float e11 = has1 ? neglog(static_cast<float>(p1[n - 1]), dm[n - 1], dn[n - 1]) : 0.0f;
-    float2 x[kRegPts];
+    const float* dn = rden + static_cast<int64_t>(r) * n;
+    // slot s holds padded position t + B s; loading at the column clamped onto
+    // the detector gives the edge-replicated padding directly.  Raw counts of a
+    // pair: row 2g in the low half, row 2g + 1 (or 0) in the high half.
+    auto load_pair = [&](int g, int t, uint32_t (&raw)[kRegPts]) {
+        const int a0 = 2 * g;
+        const uint16_t* p0 = in.proj + a0 * in.proj_stride + static_cast<int64_t>(r) * n;
+        const bool has1 = a0 + 1 < n_angles;
+        const uint16_t* p1 = has1 ? p0 + in.proj_stride : p0;
 #pragma unroll
-    for (int s = 0; s < kRegPts; ++s) {
-        const int j = t + B * s - off;
-        if (j < 0) {
-            x[s] = make_float2(e00, e10);
-        } else if (j >= n) {
-            x[s] = make_float2(e01, e11);
-        } else {
-            const float d = dm[j], e = dn[j];
-            x[s] = make_float2(neglog(static_cast<float>(p0[j]), d, e),
-                               has1 ? neglog(static_cast<float>(p1[j]), d, e) : 0.0f);
+        for (int s = 0; s < kRegPts; ++s) {
+            const int c = min(max(t + B * s - off, 0), n - 1);
+            const uint32_t hi = p1[c];
+            raw[s] = p0[c] | (has1 ? hi << 16 : 0u);
         }
-    }
-    reg_filter<L>(x, lds, ft);
-    TO* o0 = out + (static_cast<int64_t>(r) * n_angles + a0) * n;
-    TO* o1 = o0 + n;
+    };
+    uint32_t cur[kRegPts], nxt[kRegPts];
+    load_pair(g0, threadIdx.x, cur);
+#pragma unroll 1
+    for (int g = g0; g < g1; ++g) {
+        // an opaque thread index per pair: per-thread offsets (columns, FFT
+        // twiddles, LDS and output positions) are recomputed in the loop
+        // instead of being hoisted into registers held across it
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        if (g + 1 < g1) load_pair(g + 1, t, nxt);
+        const int a0 = 2 * g;
+        const bool has1 = a0 + 1 < n_angles;
+        float2 x[kRegPts];
 #pragma unroll
-    for (int s = 0; s < kRegPts; ++s) {
-        const int j = t + B * s - off;
-        if (j >= 0 && j < n) {
-            store_from_float(o0, j, x[s].x);
-            if (has1) store_from_float(o1, j, 0.0f - x[s].y);
+        for (int s = 0; s < kRegPts; ++s) {
+            const int c = min(max(t + B * s - off, 0), n - 1);
+            const float d = dm[c], e = dn[c];
+            x[s] = make_float2(neglog_counts(static_cast<float>(cur[s] & 0xffffu), d, e),
+                               has1 ? neglog_counts(static_cast<float>(cur[s] >> 16), d, e) : 0.0f);
         }
+        reg_filter<L>(x, lds, ft, t);
+        TO* o0 = out + (static_cast<int64_t>(r) * n_angles + a0) * n;
+        TO* o1 = o0 + n;
+#pragma unroll
+        for (int s = 0; s < kRegPts; ++s) {
+            const int j = t + B * s - off;
+            if (j >= 0 && j < n) {
+                store_from_float(o0, j, x[s].x);
+                if (has1) store_from_float(o1, j, 0.0f - x[s].y);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kRegPts; ++s) cur[s] = nxt[s];
     }
 }
 
@@ -499,14 +515,17 @@ hipError_t launch_norm_filter_t(const RawInput& in, const float* dmean, const fl
     const int off = (ft.L - n) / 2;
     const int64_t blocks = static_cast<int64_t>(n_rows) * ((n_angles + 1) / 2);
     const dim3 grid(static_cast<unsigned>(blocks));
+    const int64_t reg_blocks =
+        static_cast<int64_t>(n_rows) * ((((n_angles + 1) / 2) + kPairsPerGroup - 1) / kPairsPerGroup);
+    const dim3 reg_grid(static_cast<unsigned>(reg_blocks));
     TO* pout = static_cast<TO*>(out);
     size_t lds = 0;
     hipError_t e = hipSuccess;
 #define TP_REG_CASE(LL)                                                                                    \
     case LL:                                                                                              \
-        e = launch_reg<LL>(k_norm_filter_reg<LL, TO>, grid, st, lds);                                     \
+        e = launch_reg<LL>(k_norm_filter_reg<LL, TO>, reg_grid, st, lds);                                 \
         if (e != hipSuccess) return e;                                                                    \
-        hipLaunchKernelGGL((k_norm_filter_reg<LL, TO>), grid, dim3(LL / kRegPts), lds, st, in, dmean, den, \
+        hipLaunchKernelGGL((k_norm_filter_reg<LL, TO>), reg_grid, dim3(LL / kRegPts), lds, st, in, dmean, den, \
                            n_angles, n, off, ft, pout);                                                   \
         return hipGetLastError();
     switch (ft.L) {

@@ -3,8 +3,8 @@
 // k_darkflat: per detector pixel (row r, column j), the arithmetic means of the
 //   dark and flat frames.  Frame values are summed as integers (<= 256 frames
 //   of 16-bit counts stay below 2^24, exact in FP32), then divided once.
-//   Stores D and den = max(F - D, 1).
-// k_normalize: sino[r][a][j] = -ln(max((P[a][r][j] - D) / den, 1e-6)).
+//   Stores D and rden = 1 / max(F - D, 1).
+// k_normalize: sino[r][a][j] = -ln(max((P[a][r][j] - D) * rden, 1e-6)).
 //   One work-group per (projection a, row r): it moves a whole detector row,
 //   so both the projection-major read and the sinogram-major write are
 //   contiguous; 8 counts per thread per 16-byte load where the row allows.
@@ -13,10 +13,8 @@
 namespace tp {
 namespace {
 
-constexpr float kMinTransmission = 1e-6f;
-
 __global__ void __launch_bounds__(256)
-k_darkflat(RawInput in, int n_rows, int n_det, float* __restrict__ dmean, float* __restrict__ den) {
+k_darkflat(RawInput in, int n_rows, int n_det, float* __restrict__ dmean, float* __restrict__ rden) {
     const int64_t npix = static_cast<int64_t>(n_rows) * n_det;
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= npix) return;
@@ -28,12 +26,7 @@ k_darkflat(RawInput in, int n_rows, int n_det, float* __restrict__ dmean, float*
     const float d = static_cast<float>(sd) / static_cast<float>(in.n_dark);
     const float fl = static_cast<float>(sf) / static_cast<float>(in.n_flat);
     dmean[p] = d;
-    den[p] = fmaxf(fl - d, 1.0f);
-}
-
-__device__ __forceinline__ float neglog_transmission(float P, float d, float den) {
-    const float t = fmaxf((P - d) / den, kMinTransmission);
-    return 0.0f - logf(t);  // subtraction, not negation: avoids a packed sign-flip pattern
+    rden[p] = 1.0f / fmaxf(fl - d, 1.0f);
 }
 
 template <typename T>
@@ -57,12 +50,12 @@ k_normalize(RawInput in, const float* __restrict__ dmean, const float* __restric
             for (int k = 0; k < 8; ++k) {
                 const int j = v * 8 + k;
                 const float P = static_cast<float>((w[k >> 1] >> ((k & 1) * 16)) & 0xffffu);
-                store_from_float(dst, j, neglog_transmission(P, dm[j], dn[j]));
+                store_from_float(dst, j, neglog_counts(P, dm[j], dn[j]));
             }
         }
     } else {
         for (int j = threadIdx.x; j < n_det; j += blockDim.x) {
-            store_from_float(dst, j, neglog_transmission(static_cast<float>(src[j]), dm[j], dn[j]));
+            store_from_float(dst, j, neglog_counts(static_cast<float>(src[j]), dm[j], dn[j]));
         }
     }
 }

@@ -87,6 +87,15 @@ __device__ __forceinline__ int coord_floor(float s) {
 __device__ __forceinline__ float coord_frac(float s) { return __builtin_amdgcn_fractf(s); }
 
 // ---- storage conversions (round to nearest even) ----
+// Negative log of the flat/dark-corrected transmission (paper, Section 2.2):
+// -ln(max((P - D) * rden, 1e-6)) with rden = 1 / max(F - D, 1) stored per
+// pixel by the dark/flat pass (a multiply per sample instead of a divide).
+// Written as a subtraction from zero, not a negation.
+constexpr float kMinTransmission = 1e-6f;
+__device__ __forceinline__ float neglog_counts(float P, float d, float rden) {
+    return 0.0f - logf(fmaxf((P - d) * rden, kMinTransmission));
+}
+
 __device__ __forceinline__ float load_as_float(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float load_as_float(const __half* p, int64_t i) { return __half2float(p[i]); }
 __device__ __forceinline__ float load_as_float(const uint16_t* p, int64_t i) {  // bfloat16 bits
