@@ -57,7 +57,10 @@ def parse():
     ap.add_argument("--angles", type=int, default=2048)
     ap.add_argument("--rows", type=int, default=2048)
     ap.add_argument("--chunk", type=int, default=256, help="rows per tp_fbp_chunk call")
-    ap.add_argument("--storage", default="f16,f32", help="storage precisions to time (first is reported)")
+    ap.add_argument("--storage", default="f16,f32,bf16", help="storage precisions to time (first is reported)")
+    ap.add_argument("--precision-slices", type=int, default=32,
+                    help="slices sampled for the precision report (rel-L2 and max error vs FP64 per storage)")
+    ap.add_argument("--precision-points", type=int, default=2048, help="sampled voxels per precision slice")
     ap.add_argument("--filter", default="ramp", choices=("ramp", "shepp", "parzen"),
                     help="filter window (the paper's tool defaults to parzen; the headline workload is ramp)")
     ap.add_argument("--tuning", default="", help="backprojection tuning K,A (default: plan default)")
@@ -153,6 +156,12 @@ def main():
 
     parity_z = [int(z) for z in np.linspace(rows // 8, rows - rows // 8, args.parity_rows).round()] \
         if args.parity_rows > 0 else []
+    # precision report: evenly spaced slices (32 + 64k for 2048 rows), seeded voxel samples
+    nps = min(args.precision_slices, rows)
+    prec_z = [int((k + 0.5) * rows / nps) for k in range(nps)] if nps > 0 else []
+    prng = np.random.default_rng(2048)
+    prec_ix = {z: prng.integers(0, n, args.precision_points) for z in prec_z}
+    prec_iy = {z: prng.integers(0, n, args.precision_points) for z in prec_z}
     results = {}
     for st in storages:
         # events per chunk: before darkflat, before norm+filter, before BP, after BP
@@ -184,6 +193,8 @@ def main():
         t_total = time.perf_counter() - t_start
         sec = t_total / args.steps
         samples = {z: vol[z].detach().cpu().numpy().astype(np.float64) for z in parity_z}
+        points = {z: vol[z][torch.from_numpy(prec_iy[z]).to(dev), torch.from_numpy(prec_ix[z]).to(dev)]
+                  .cpu().numpy().astype(np.float64) for z in prec_z}
         results[st] = {
             "s_per_volume": sec,
             "gups": updates / sec / 1e9,
@@ -191,6 +202,7 @@ def main():
                                   "backproject": stage[2] / args.steps},
             "bp_launch_ms": float(np.mean(bp_times)),
             "samples": samples,
+            "points": points,
         }
         log(f"[{st}] {sec:.3f} s per volume, {updates / sec / 1e9:.1f} Gupd/s, "
             f"BP launch {np.mean(bp_times):.2f} ms")
@@ -220,6 +232,25 @@ def main():
             den = sum(np.sum(ref[z] ** 2) for z in parity_z)
             rel[st] = float(math.sqrt(num / den))
             log(f"[{st}] rel-L2 vs FP64 oracle on slices {parity_z}: {rel[st]:.3e}")
+    precision = None
+    if prec_z:
+        log(f"oracle FBP at {args.precision_points} voxels of each of {len(prec_z)} slices")
+        want = {}
+        for z in prec_z:
+            p = scan.proj[:, z, :].cpu().numpy().view(np.uint16)
+            d = scan.dark[:, z, :].cpu().numpy().view(np.uint16)
+            f = scan.flat[:, z, :].cpu().numpy().view(np.uint16)
+            want[z] = oracle.fbp_points(p, d, f, scan.angles, center, n, prec_ix[z], prec_iy[z], kind=args.filter)
+        w_all = np.concatenate([want[z] for z in prec_z])
+        precision = {"slices": prec_z if len(prec_z) <= 8 else f"{len(prec_z)} evenly spaced, {prec_z[0]} + "
+                     f"{prec_z[1] - prec_z[0]}k", "points_per_slice": args.precision_points}
+        for st in storages:
+            g_all = np.concatenate([results[st]["points"][z] for z in prec_z])
+            err = g_all - w_all
+            precision[st] = {"rel_l2": float(np.linalg.norm(err) / np.linalg.norm(w_all)),
+                             "max_abs_over_max_ref": float(np.max(np.abs(err)) / np.max(np.abs(w_all)))}
+            log(f"[{st}] sampled precision: rel-L2 {precision[st]['rel_l2']:.3e}, "
+                f"max|err|/max|ref| {precision[st]['max_abs_over_max_ref']:.3e}")
     cpu = None
     if args.cpu_seconds > 0:
         extra = [z for z in range(0, rows, max(1, rows // 16)) if z not in parity_z]
@@ -267,6 +298,7 @@ def main():
         "s_per_volume": {st: round(results[st]["s_per_volume"], 4) for st in storages},
         "gups": {st: round(results[st]["gups"], 2) for st in storages},
         "rel_l2_vs_fp64_oracle": rel,
+        "precision_sampled_vs_fp64_oracle": precision,
         "stage_ms_per_step": {st: {k: round(v, 2) for k, v in results[st]["stage_ms_per_step"].items()}
                               for st in storages},
         "roofline": {"bound": "alu", "kernel": "k_backproject", "achieved": round(achieved, 2),
