@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--pattern", default="32,64,128", help="chunk sizes of the pipeline mode")
     ap.add_argument("--no-ls", action="store_true",
                     help="skip the differentiation section (forward projector, adjoint, 30 LS steps)")
+    ap.add_argument("--single-radon", action="store_true",
+                    help="instead: one tp_radon of the differentiation workload (128 x 1024^2 x 900), then a 1 GiB "
+                         "device copy (a short program for hardware-counter passes)")
     ap.add_argument("--single-launch", action="store_true",
                     help="instead: one tp_fbp_chunk of the timed launch shape, then a 1 GiB device copy "
                          "(a short program for hardware-counter runs; the copy calibrates the byte counters)")
@@ -113,6 +116,8 @@ def main():
         return main_pipeline(args)
     if args.single_launch:
         return main_single_launch(args)
+    if args.single_radon:
+        return main_single_radon(args)
 
     import numpy as np
     import torch
@@ -400,6 +405,30 @@ def main_single_launch(args):
     torch.cuda.synchronize()
     print(json.dumps({"single_launch": {"storage": st, "rows": rows, "n": n, "angles": na,
                                         "tuning": list(plan.get_tuning(st)), "copy_bytes": 1 << 30}}), flush=True)
+    plan.close()
+
+
+def main_single_radon(args):
+    import torch
+
+    from paper_2209_08450_amd import synth, tp
+
+    y, ang, c = synth.ls_problem_torch(seed=4, n_slices=128, n_vox=1024, n_angles=900, device="cuda")
+    plan = tp.Plan(ang, 1024, c)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn((128, 1024, 1024), generator=g, device="cuda")
+    ws = torch.empty(max(256, plan.radon_workspace_bytes(128)), dtype=torch.uint8, device="cuda")
+    out = torch.empty((128, 900, 1024), device="cuda")
+    torch.cuda.synchronize()
+    tp.radon(plan, x, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)  # 1 GiB read + 1 GiB written
+    torch.cuda.synchronize()
+    print(json.dumps({"single_radon": {"slices": 128, "n": 1024, "angles": 900, "copy_bytes": 1 << 30}}),
+          flush=True)
     plan.close()
 
 
