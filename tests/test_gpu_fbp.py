@@ -157,3 +157,37 @@ def test_fbp_windowed_graph_capture_needs_prepared_tables(tp):
         g.replay()
         torch.cuda.synchronize()
         assert rel_l2(to_host(out).astype(np.float64), want) < 1e-5, rep
+
+
+def test_zero_rows_rejected_before_launch(tp):
+    import ctypes
+
+    import torch
+    s = synth.ellipsoid_scan_np(seed=3, n_angles=8, n_rows=2, n_det=32, center=15.5, n_dark=1, n_flat=1)
+    plan = tp.Plan(s.angles, 32, s.center)
+    buf = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
+    p = ctypes.c_void_p(buf.data_ptr())
+    nul = ctypes.c_void_p()
+    note("zero-row calls")
+    assert tp._backproject(plan.handle, p, tp.TP_F32, 0, 1.0, p, 0, nul) == tp.TP_EINVAL
+    assert "n_rows" in tp.last_error()
+    assert tp._radon(plan.handle, p, 0, p, p, 1 << 20, nul) == tp.TP_EINVAL
+    assert tp._fbp_chunk(plan.handle, p, 0, p, 1, p, 1, 0, 0, tp.TP_RAMP, tp.TP_F32, p, 1 << 20, p,
+                         nul) == tp.TP_EINVAL
+    assert tp._normalize(p, 0, p, 1, p, 1, 0, 8, 0, 32, tp.TP_F32, p, p, 1 << 20, nul) == tp.TP_EINVAL
+    torch.cuda.synchronize()
+
+
+def test_fbp_widest_detector(tp):
+    # n_det = 8192, the widest a plan takes: pad length 16384 (the LDS FFT path
+    # of the fused kernel), 8192^2 slices; sampled voxels against the oracle
+    s = synth.ellipsoid_scan_np(seed=6, n_angles=24, n_rows=2, n_det=8192, center=4095.5, n_dark=2, n_flat=2)
+    plan = tp.Plan(s.angles, 8192, s.center)
+    note("fbp 24 x 2 x 8192 f32")
+    out = tp.fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), "f32")
+    rng = np.random.default_rng(7)
+    ix, iy = rng.integers(0, 8192, 256), rng.integers(0, 8192, 256)
+    for z in range(2):
+        want = oracle.fbp_points(s.proj[:, z], s.dark[:, z], s.flat[:, z], s.angles, s.center, 8192, ix, iy)
+        got = to_host(out[z])[iy, ix].astype(np.float64)
+        assert rel_l2(got, want) < 1e-5, z

@@ -172,3 +172,14 @@ def test_windows_differ_from_ramp(tp):
     s = to_host(tp.filter(p, kind="shepp"))
     z = to_host(tp.filter(p, kind="parzen"))
     assert rel_l2(s, r) > 1e-2 and rel_l2(z, r) > 1e-2 and rel_l2(z, s) > 1e-2
+
+
+@pytest.mark.parametrize("kind", ["ramp", "parzen"])
+def test_filter_widest_rows(tp, kind):
+    # n = 8192: pad length 16384, the largest the filter takes
+    rng = np.random.default_rng(81)
+    p = rng.standard_normal((3, 8192)) + 1.0
+    note(f"filter {kind} n=8192")
+    got = to_host(tp.filter(to_dev(p.astype(np.float32)), kind=kind))
+    want = oracle.filter_rows(p.astype(np.float32).astype(np.float64), kind=kind)
+    assert rel_l2(got, want) < 3e-6
