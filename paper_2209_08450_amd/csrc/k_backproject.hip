@@ -247,6 +247,7 @@ constexpr int kCand = 3;
 // four work-groups per CU)
 template <int K> constexpr int radon_lines() { return K >= 32 ? 2 : 4; }
 constexpr int kRadonStrip = 128;
+constexpr int W = 4;  // angles (waves) per work-group
 
 // One line of the sweep for bin j: first candidate and the line's tile entries.
 struct RadonLine {
@@ -289,24 +290,26 @@ __device__ __forceinline__ float radon_weight(const RadonLine& ln, int t, int j,
 }
 
 template <int K, bool ROWS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * W)
 k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restrict__ sino) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_lo[4][4];
+    __shared__ int s_lo[W][4];
     const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
     float4* strip = reinterpret_cast<float4*>(smem);                      // [lines][K / 4][kRadonStrip]
     constexpr int LINES = radon_lines<K>();
-    int2* tabs = reinterpret_cast<int2*>(strip + LINES * (K / 4) * kRadonStrip);  // [4 waves][2][nb]
+    int2* tabs = reinterpret_cast<int2*>(strip + LINES * (K / 4) * kRadonStrip);  // [W waves][2][nb]
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int jgroups = (g.n + 63) >> 6;
     const int jb = (blockIdx.x % jgroups) * 64;
     const int grp = blockIdx.x / jgroups;
     // this launch covers the angles that sweep rows (ROWS) or columns
-    const int e0 = ROWS ? grp * 4 : g.n_rows_major + grp * 4;
-    const int e_end = ROWS ? min(g.n_rows_major, e0 + 4) : min(na, e0 + 4);
+    const int e0 = ROWS ? grp * W : g.n_rows_major + grp * W;
+    const int e_end = ROWS ? min(g.n_rows_major, e0 + W) : min(g.n_order, e0 + W);
+    if (g.order[e0] < 0) return;  // a group of padding only (whole work-group, before any barrier)
     const int e = e0 + wv;
-    const bool active = e < e_end;
+    // padding entries (-1) and entries past the class are inactive waves
+    const bool active = e < e_end && g.order[e] >= 0;
     const int a = active ? g.order[e] : g.order[e0];
     const int j = jb + lane;
     const int z0 = blockIdx.y * K;
@@ -345,8 +348,8 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
         }
         __syncthreads();
         int xmin = 1 << 30, xmax = -(1 << 30);
-        for (int w = 0; w < 4; ++w) {
-            if (e0 + w >= e_end) continue;
+        for (int w = 0; w < W; ++w) {
+            if (e0 + w >= e_end || g.order[e0 + w] < 0) continue;
             for (int c = 0; c < 4; ++c) {
                 xmin = min(xmin, s_lo[w][c]);
                 xmax = max(xmax, s_lo[w][c] + kCand - 1);
@@ -356,12 +359,14 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
         xmax = min(xmax + 1, N - 1);
         const int width = xmax - xmin + 1;
         const bool staged = width > 0 && width <= kRadonStrip;
-        if (staged && wv < mr) {  // wave r stages line m0 + r, positions lane and lane + 64
-            const float* row = vz + static_cast<int64_t>(m0 + wv) * N + xmin;
-#pragma unroll
-            for (int h = 0; h < kRadonStrip; h += 64) {
-                const int x = lane + h;
+        if (staged) {
+            // jobs of 64 positions of one line, spread over the waves
+            constexpr int kChunks = kRadonStrip / 64;
+            for (int job = wv; job < mr * kChunks; job += W) {
+                const int r = job / kChunks;
+                const int x = lane + 64 * (job - r * kChunks);
                 if (x < width) {
+                    const float* row = vz + static_cast<int64_t>(m0 + r) * N + xmin;
                     float v[K];
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
@@ -371,7 +376,7 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
                         asm volatile("" : "+s"(kk));
                         v[k] = row[x + kk * slab];
                     }
-                    float4* dst = strip + wv * (K / 4) * kRadonStrip + x;
+                    float4* dst = strip + r * (K / 4) * kRadonStrip + x;
 #pragma unroll
                     for (int q = 0; q < K / 4; ++q) dst[q * kRadonStrip] = reinterpret_cast<const float4*>(v)[q];
                 }
@@ -522,17 +527,17 @@ __global__ void __launch_bounds__(256) k_transpose(const float* __restrict__ in,
 template <int K, bool ROWS>
 hipError_t launch_radon_k(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st) {
     const int jgroups = (g.n + 63) / 64;
-    const int groups = ROWS ? (g.n_rows_major + 3) / 4 : (g.na - g.n_rows_major + 3) / 4;
+    const int groups = ROWS ? (g.n_rows_major + W - 1) / W : (g.n_order - g.n_rows_major + W - 1) / W;
     if (groups == 0) return hipSuccess;
     const size_t lds = sizeof(float) * radon_lines<K>() * K * kRadonStrip +
-                       sizeof(int2) * 8 * static_cast<size_t>(g.nb);
+                       sizeof(int2) * 2 * W * static_cast<size_t>(g.nb);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K, ROWS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     const dim3 grid(static_cast<unsigned>(jgroups * groups), static_cast<unsigned>((n_rows + K - 1) / K));
-    hipLaunchKernelGGL((k_radon<K, ROWS>), grid, dim3(256), lds, st, g, vol, n_rows, sino);
+    hipLaunchKernelGGL((k_radon<K, ROWS>), grid, dim3(64 * W), lds, st, g, vol, n_rows, sino);
     return hipGetLastError();
 }
 
@@ -547,7 +552,7 @@ hipError_t launch_radon_both(const GeoTables& g, const float* vol, const float* 
 }  // namespace
 
 size_t radon_workspace_bytes(const GeoTables& g, int n_rows) {
-    return g.n_rows_major < g.na ? sizeof(float) * static_cast<size_t>(n_rows) * g.N * g.N : 0;
+    return g.n_rows_major < g.n_order ? sizeof(float) * static_cast<size_t>(n_rows) * g.N * g.N : 0;
 }
 
 // Angles that sweep columns (|sin| > |cos|) read a transposed copy of the
@@ -556,7 +561,7 @@ size_t radon_workspace_bytes(const GeoTables& g, int n_rows) {
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
                         hipStream_t st) {
     const float* volT = vol;
-    if (g.n_rows_major < g.na) {
+    if (g.n_rows_major < g.n_order) {
         const dim3 tg(static_cast<unsigned>((g.N + 63) / 64), static_cast<unsigned>((g.N + 63) / 64),
                       static_cast<unsigned>(n_rows));
         hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, vol, workspace, g.N);

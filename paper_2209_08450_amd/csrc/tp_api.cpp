@@ -279,20 +279,39 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
             yf[static_cast<size_t>(b) * na + a] = static_cast<float>(Y - fy);
         }
     }
-    // forward-projector grouping: angles sweeping rows first, then columns, each sorted by angle
+    // Forward-projector grouping.  Angles sweep rows (|cos| >= |sin|) or
+    // columns; within each class the sign of the swept coefficient decides on
+    // which side of the image a bin's strip lies (angles near 0 and near pi
+    // are mirror images), so each class is split by that sign.  Each of the 4
+    // segments is sorted by the angle reduced modulo pi into [-pi/4, 3pi/4)
+    // (neighbours share a work-group) and padded with -1 to a multiple of 4
+    // entries, so no work-group of 4 angles straddles two segments.
+    auto key = [&](int a) {
+        double t = std::fmod(g->angles[a] + M_PI / 4, M_PI);
+        if (t < 0) t += M_PI;
+        return t - M_PI / 4;
+    };
+    auto by_angle = [&](int p, int q) { return key(p) < key(q) || (key(p) == key(q) && p < q); };
+    std::vector<int> seg[4];
+    for (int a = 0; a < na; ++a) {
+        const bool rows = std::fabs(cs[a]) >= std::fabs(sn[a]);
+        const bool neg = rows ? cs[a] < 0.0f : sn[a] < 0.0f;
+        seg[(rows ? 0 : 2) + (neg ? 1 : 0)].push_back(a);
+    }
     std::vector<int> order;
-    order.reserve(na);
-    for (int a = 0; a < na; ++a)
-        if (std::fabs(cs[a]) >= std::fabs(sn[a])) order.push_back(a);
-    const int n_rows_major = static_cast<int>(order.size());
-    for (int a = 0; a < na; ++a)
-        if (!(std::fabs(cs[a]) >= std::fabs(sn[a]))) order.push_back(a);
-    auto by_angle = [&](int p, int q) { return g->angles[p] < g->angles[q] || (g->angles[p] == g->angles[q] && p < q); };
-    std::sort(order.begin(), order.begin() + n_rows_major, by_angle);
-    std::sort(order.begin() + n_rows_major, order.end(), by_angle);
+    order.reserve(na + 16);
+    int n_rows_major = 0;
+    for (int q = 0; q < 4; ++q) {
+        std::sort(seg[q].begin(), seg[q].end(), by_angle);
+        order.insert(order.end(), seg[q].begin(), seg[q].end());
+        while (order.size() % 4) order.push_back(-1);
+        if (q == 1) n_rows_major = static_cast<int>(order.size());
+    }
+    const int n_order = static_cast<int>(order.size());
     const size_t s_ang = align256(sizeof(float) * na);
     const size_t s_tab = align256(sizeof(float) * static_cast<size_t>(nb) * na);
-    const size_t total = 3 * s_ang + 4 * s_tab;
+    const size_t s_ord = align256(sizeof(int) * static_cast<size_t>(n_order));
+    const size_t total = 2 * s_ang + 4 * s_tab + s_ord;
 
     tp_plan* p = new (std::nothrow) tp_plan();
     if (!p) return fail(TP_ENOMEM, "host allocation failed");
@@ -321,7 +340,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     if (e == hipSuccess) e = hipMemcpy(d_xf, xf.data(), tb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_yi, yi.data(), tb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_yf, yf.data(), tb, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_order, order.data(), sizeof(int) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_order, order.data(), sizeof(int) * n_order, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p->dev_block);
         delete p;
@@ -345,6 +364,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     p->geo.center_f = static_cast<float>(g->center);
     p->geo.order = reinterpret_cast<const int*>(d_order);
     p->geo.n_rows_major = n_rows_major;
+    p->geo.n_order = n_order;
     tp_status st = filter_tables(default_pad_len(g->n_det), TP_RAMP, &p->filt, nullptr);
     if (st != TP_OK) {
         (void)hipFree(p->dev_block);

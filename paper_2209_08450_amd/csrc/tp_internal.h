@@ -30,9 +30,10 @@ struct GeoTables {
     const float* yf;   // [nb][na]
     int na, n, N, nb;
     float center_f;    // FP32 rotation axis (only for candidate search in the forward projector)
-    const int* order;  // [na] angle indices: first the n_rows_major angles with |cos| >= |sin|,
-                       // then the rest, each group sorted by angle (forward projector grouping)
+    const int* order;  // [n_order] forward-projector grouping: angle indices (-1 = padding), first
+                       // n_rows_major entries for angles with |cos| >= |sin|, then the rest
     int n_rows_major;
+    int n_order;
 };
 
 struct FilterTables {
