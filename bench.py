@@ -110,7 +110,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(slices are independent, see DESIGN.md for how the path shards)", file=sys.stderr)
+              "(slices are independent; the path would shard by slice)", file=sys.stderr)
         sys.exit(2)
     if args.pipeline:
         return main_pipeline(args)

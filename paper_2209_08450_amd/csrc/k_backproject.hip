@@ -1,6 +1,6 @@
 // Pixel-driven backprojection with linear interpolation (paper, Sections 2.2
-// and 3, "LineRec": direct discretisation of the backprojection line integral),
-// and its exact transpose, the forward projector.
+// and 3, "LineRec": direct discretisation of the backprojection line integral).
+// Its exact transpose, the forward projector, is in k_radon.hip.
 //
 // Detector coordinate of voxel (ix, iy) at angle a, for tile (bx, by) =
 // (ix / 32, iy / 32) and in-tile offset (dx, dy) = (ix % 32, iy % 32):
@@ -9,8 +9,9 @@
 //   split into integers xi + yi and FP32 fractions xf + yf).
 // Keeping the FP32 part below 64 columns holds the coordinate error near
 // 1e-6 column where a plain FP32 evaluation of |s| ~ 1000 loses ~1e-4.
-// Both kernels evaluate exactly this expression (explicit fma, no
-// reassociation), so they take identical floor and weight decisions.
+// The backprojector and the forward projector evaluate exactly this
+// expression (shared helpers, explicit fma, no reassociation), so they take
+// identical floor and weight decisions.
 //
 // Backprojection work-group: one 32x32 voxel tile x K slices, 256 threads.
 // Thread (wave w, lane l) owns voxels (l%8 + 8i, l/8 + 8w), i = 0..3, so each
@@ -222,217 +223,6 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
     }
 }
 
-// Forward projection, gather form.  Work-group: 4 waves = 4 neighbouring
-// angles that sweep the same axis (the plan lists angles grouped by sweep
-// axis and sorted), lanes = 64 consecutive detector bins, K slices.  Each bin
-// sweeps the image along the axis the ray is closer to (rows when |cos| >=
-// |sin|).  On each line the voxels whose coordinate can fall in [j-1, j+1)
-// lie within 1/|c| <= sqrt(2) of the line's crossing point; a fixed window of
-// kCand candidates starting just below it covers them with margin (the
-// crossing point is an FP32 estimate good to ~1e-3 voxel), so every lane runs
-// the same unrolled loop.  Each candidate's exact (j0, w) comes from the
-// backprojector's expression with the angle's tile tables staged in LDS;
-// weights are (1-w) for j0 == j, w for j0+1 == j, else 0.
-// Lines are processed in blocks of radon_lines: the work-group stages the
-// strip its 4 angles x 64 bins can touch on those lines (all K slices,
-// [line][slice / 4][position] of float4, so a wave's read of one 4-slice
-// chunk at its ~1.2-voxel-spaced positions touches near-consecutive 16-byte
-// words) into LDS with coalesced loads, so each voxel is
-// fetched once per work-group instead of once per bin and angle.  A strip
-// wider than kRadonStrip (sparse angle sets) is read from global memory
-// instead, with the same arithmetic and order.  No atomics: every output is
-// summed by one lane, lines ascending, candidates ascending.
-constexpr int kCand = 3;
-// lines staged per block: 4, or 2 for 32 slices (keeps the strip at 32 KB,
-// four work-groups per CU)
-template <int K> constexpr int radon_lines() { return K >= 32 ? 2 : 4; }
-constexpr int kRadonStrip = 128;
-constexpr int W = 4;  // angles (waves) per work-group
-
-// One line of the sweep for bin j: first candidate and the line's tile entries.
-struct RadonLine {
-    int lo, li;
-    float lf, dm;
-};
-
-__device__ __forceinline__ RadonLine radon_line(int m, int j, int half, float cmin, float inv, float start,
-                                                float center_f, const int2* tl) {
-    RadonLine ln;
-    const float um = static_cast<float>(m - half) * cmin + center_f;
-    // first candidate: ceil of the window's left end (the window is
-    // 2/|c| + 0.02 <= 2.85 voxels long, so 3 candidates cover it)
-    ln.lo = -coord_floor(-__builtin_fmaf(static_cast<float>(j) - um, inv, start));
-    const int2 e = tl[m >> 5];
-    ln.li = e.x;
-    ln.lf = __int_as_float(e.y);
-    ln.dm = static_cast<float>(m & 31);
-    return ln;
-}
-
-// Weight of candidate t of a line in bin j, from the backprojector's exact
-// expression (bi = xi + yi, bf = xf + yf, then tile_offset): (1 - w) when
-// floor lands on j, w when on j - 1, else 0.  vc: the clamped voxel index.
-template <bool ROWS>
-__device__ __forceinline__ float radon_weight(const RadonLine& ln, int t, int j, int N, float cs, float sn,
-                                              const int2* tc, int& vc) {
-    const int v = ln.lo + t;
-    vc = min(max(v, 0), N - 1);
-    const int bv = vc >> 5;
-    const float dv = static_cast<float>(vc & 31);
-    const int2 e = tc[bv];
-    const int bi = e.x + ln.li;
-    const float bf = __int_as_float(e.y) + ln.lf;
-    const float s = ROWS ? tile_offset(dv, ln.dm, cs, sn, bf) : tile_offset(ln.dm, dv, cs, sn, bf);
-    const int j0 = bi + coord_floor(s);
-    const float w = coord_frac(s);
-    const float wt = (j0 == j) ? 1.0f - w : ((j0 + 1 == j) ? w : 0.0f);
-    return (v >= 0 && v < N) ? wt : 0.0f;
-}
-
-template <int K, bool ROWS>
-__global__ void __launch_bounds__(64 * W)
-k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restrict__ sino) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int s_lo[W][4];
-    const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
-    float4* strip = reinterpret_cast<float4*>(smem);                      // [lines][K / 4][kRadonStrip]
-    constexpr int LINES = radon_lines<K>();
-    int2* tabs = reinterpret_cast<int2*>(strip + LINES * (K / 4) * kRadonStrip);  // [W waves][2][nb]
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int jgroups = (g.n + 63) >> 6;
-    const int jb = (blockIdx.x % jgroups) * 64;
-    const int grp = blockIdx.x / jgroups;
-    // this launch covers the angles that sweep rows (ROWS) or columns
-    const int e0 = ROWS ? grp * W : g.n_rows_major + grp * W;
-    const int e_end = ROWS ? min(g.n_rows_major, e0 + W) : min(g.n_order, e0 + W);
-    if (g.order[e0] < 0) return;  // a group of padding only (whole work-group, before any barrier)
-    const int e = e0 + wv;
-    // padding entries (-1) and entries past the class are inactive waves
-    const bool active = e < e_end && g.order[e] >= 0;
-    const int a = active ? g.order[e] : g.order[e0];
-    const int j = jb + lane;
-    const int z0 = blockIdx.y * K;
-    const int nz = min(K, n_rows - z0);
-    // tables of this wave's angle: the candidate's tile (along the line) and
-    // the line's tile, integer and fraction parts
-    int2* tc = tabs + wv * 2 * nb;  // (integer, fraction bits) per tile
-    int2* tl = tc + nb;
-    for (int b = lane; b < nb; b += 64) {
-        const int xi = g.xi[b * na + a], yi = g.yi[b * na + a];
-        const int xf = __float_as_int(g.xf[b * na + a]), yf = __float_as_int(g.yf[b * na + a]);
-        tc[b] = ROWS ? make_int2(xi, xf) : make_int2(yi, yf);
-        tl[b] = ROWS ? make_int2(yi, yf) : make_int2(xi, xf);
-    }
-    const float cs = g.cs[a], sn = g.sn[a];
-    const float cmaj = ROWS ? cs : sn;   // coefficient of the swept coordinate
-    const float cmin = ROWS ? sn : cs;   // coefficient of the line coordinate
-    const float inv = 1.0f / cmaj;
-    // left end of the window of voxels whose coordinate can fall in [j-1, j+1)
-    const float start = static_cast<float>(half) - 1.0f / fabsf(cmaj) - 0.01f;
-    const int64_t slab = static_cast<int64_t>(N) * N;
-    // a line is a row of the volume (ROWS) or of its transpose: contiguous
-    const float* vz = vol + static_cast<int64_t>(z0) * slab;
-    float acc[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0f;
-
-    for (int m0 = 0; m0 < N; m0 += LINES) {
-        const int mr = min(LINES, N - m0);
-        // candidate starts at the block's corners (first/last bin, first/last line)
-        if (lane < 4) {
-            const int jj = min((lane & 1) ? jb + 63 : jb, g.n - 1);
-            const int mm = (lane & 2) ? m0 + mr - 1 : m0;
-            const float um = static_cast<float>(mm - half) * cmin + g.center_f;
-            s_lo[wv][lane] = -coord_floor(-__builtin_fmaf(static_cast<float>(jj) - um, inv, start));
-        }
-        __syncthreads();
-        int xmin = 1 << 30, xmax = -(1 << 30);
-        for (int w = 0; w < W; ++w) {
-            if (e0 + w >= e_end || g.order[e0 + w] < 0) continue;
-            for (int c = 0; c < 4; ++c) {
-                xmin = min(xmin, s_lo[w][c]);
-                xmax = max(xmax, s_lo[w][c] + kCand - 1);
-            }
-        }
-        xmin = max(xmin - 1, 0);  // one voxel of margin for the FP32 corner estimates
-        xmax = min(xmax + 1, N - 1);
-        const int width = xmax - xmin + 1;
-        const bool staged = width > 0 && width <= kRadonStrip;
-        if (staged) {
-            // jobs of 64 positions of one line, spread over the waves
-            constexpr int kChunks = kRadonStrip / 64;
-            for (int job = wv; job < mr * kChunks; job += W) {
-                const int r = job / kChunks;
-                const int x = lane + 64 * (job - r * kChunks);
-                if (x < width) {
-                    const float* row = vz + static_cast<int64_t>(m0 + r) * N + xmin;
-                    float v[K];
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        // slices past the last row re-read it (their sums are never
-                        // stored); the opaque index keeps the offsets scalar, not hoisted
-                        int kk = min(k, nz - 1);
-                        asm volatile("" : "+s"(kk));
-                        v[k] = row[x + kk * slab];
-                    }
-                    float4* dst = strip + r * (K / 4) * kRadonStrip + x;
-#pragma unroll
-                    for (int q = 0; q < K / 4; ++q) dst[q * kRadonStrip] = reinterpret_cast<const float4*>(v)[q];
-                }
-            }
-        }
-        __syncthreads();
-        if (active && j < g.n) {
-            // the staged and the global variant are separate loops, so the
-            // uniform choice is not re-tested (and the sums not copied) per candidate
-            if (staged) {
-                for (int r = 0; r < mr; ++r) {
-                    RadonLine ln = radon_line(m0 + r, j, half, cmin, inv, start, g.center_f, tl);
-#pragma unroll
-                    for (int t = 0; t < kCand; ++t) {
-                        int vc;
-                        const float wt = radon_weight<ROWS>(ln, t, j, N, cs, sn, tc, vc);
-                        const int xo = min(max(vc - xmin, 0), kRadonStrip - 1);
-                        const float4* src = strip + r * (K / 4) * kRadonStrip + xo;
-                        float val[K];
-#pragma unroll
-                        for (int q = 0; q < K / 4; ++q) reinterpret_cast<float4*>(val)[q] = src[q * kRadonStrip];
-                        // zero weights add exact zeros: no branch
-#pragma unroll
-                        for (int k = 0; k < K; ++k) acc[k] = __builtin_fmaf(wt, val[k], acc[k]);
-                    }
-                }
-            } else {
-                for (int r = 0; r < mr; ++r) {
-                    const int m = m0 + r;
-                    RadonLine ln = radon_line(m, j, half, cmin, inv, start, g.center_f, tl);
-#pragma unroll
-                    for (int t = 0; t < kCand; ++t) {
-                        int vc;
-                        const float wt = radon_weight<ROWS>(ln, t, j, N, cs, sn, tc, vc);
-                        if (wt != 0.0f) {
-                            const float* p = vz + static_cast<int64_t>(m) * N + vc;
-#pragma unroll
-                            for (int k = 0; k < K; ++k) {
-                                int kk = min(k, nz - 1);
-                                asm volatile("" : "+s"(kk));
-                                acc[k] = __builtin_fmaf(wt, p[kk * slab], acc[k]);
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (active && j < g.n) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (k < nz) sino[(static_cast<int64_t>(z0 + k) * na + a) * g.n + j] = acc[k];
-    }
-}
-
 size_t bp_lds_bytes(tp_dtype dt, int K, int A) {
     const int elem = (dt == TP_F16) ? 2 : 4;  // bf16 is widened to FP32 in LDS
     return static_cast<size_t>(bin_pitch(elem * K)) * A * kWin + static_cast<size_t>(A) * sizeof(float4);
@@ -499,79 +289,6 @@ hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt,
                                          angles_per_block, lds, st);
     }
     return hipErrorInvalidValue;
-}
-
-namespace {
-
-// out[z][x][y] = in[z][y][x] for N x N slices: 64 x 64 tiles through LDS
-// (65-float rows, so the transposed reads do not share banks), coalesced
-// reads and writes.
-__global__ void __launch_bounds__(256) k_transpose(const float* __restrict__ in, float* __restrict__ out, int N) {
-    __shared__ float t[64][65];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 64;
-    const int64_t slab = static_cast<int64_t>(N) * N;
-    const float* src = in + blockIdx.z * slab;
-    float* dst = out + blockIdx.z * slab;
-    for (int r = ty; r < 64; r += 4) {
-        const int y = y0 + r, x = x0 + tx;
-        if (y < N && x < N) t[r][tx] = src[static_cast<int64_t>(y) * N + x];
-    }
-    __syncthreads();
-    for (int r = ty; r < 64; r += 4) {
-        const int x = x0 + r, y = y0 + tx;
-        if (y < N && x < N) dst[static_cast<int64_t>(x) * N + y] = t[tx][r];
-    }
-}
-
-template <int K, bool ROWS>
-hipError_t launch_radon_k(const GeoTables& g, const float* vol, int n_rows, float* sino, hipStream_t st) {
-    const int jgroups = (g.n + 63) / 64;
-    const int groups = ROWS ? (g.n_rows_major + W - 1) / W : (g.n_order - g.n_rows_major + W - 1) / W;
-    if (groups == 0) return hipSuccess;
-    const size_t lds = sizeof(float) * radon_lines<K>() * K * kRadonStrip +
-                       sizeof(int2) * 2 * W * static_cast<size_t>(g.nb);
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K, ROWS>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-    }
-    const dim3 grid(static_cast<unsigned>(jgroups * groups), static_cast<unsigned>((n_rows + K - 1) / K));
-    hipLaunchKernelGGL((k_radon<K, ROWS>), grid, dim3(64 * W), lds, st, g, vol, n_rows, sino);
-    return hipGetLastError();
-}
-
-template <int K>
-hipError_t launch_radon_both(const GeoTables& g, const float* vol, const float* volT, int n_rows, float* sino,
-                             hipStream_t st) {
-    hipError_t e = launch_radon_k<K, true>(g, vol, n_rows, sino, st);
-    if (e != hipSuccess) return e;
-    return launch_radon_k<K, false>(g, volT, n_rows, sino, st);
-}
-
-}  // namespace
-
-size_t radon_workspace_bytes(const GeoTables& g, int n_rows) {
-    return g.n_rows_major < g.n_order ? sizeof(float) * static_cast<size_t>(n_rows) * g.N * g.N : 0;
-}
-
-// Angles that sweep columns (|sin| > |cos|) read a transposed copy of the
-// volume, so their lines are contiguous too.  32 slices per work-group
-// amortise each candidate's coordinate; smaller chunks use 16 or 8.
-hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
-                        hipStream_t st) {
-    const float* volT = vol;
-    if (g.n_rows_major < g.n_order) {
-        const dim3 tg(static_cast<unsigned>((g.N + 63) / 64), static_cast<unsigned>((g.N + 63) / 64),
-                      static_cast<unsigned>(n_rows));
-        hipLaunchKernelGGL(k_transpose, tg, dim3(256), 0, st, vol, workspace, g.N);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        volT = workspace;
-    }
-    if (n_rows > 16) return launch_radon_both<32>(g, vol, volT, n_rows, sino, st);
-    return n_rows > 8 ? launch_radon_both<16>(g, vol, volT, n_rows, sino, st)
-                      : launch_radon_both<8>(g, vol, volT, n_rows, sino, st);
 }
 
 }  // namespace tp
