@@ -25,6 +25,9 @@ Functions follow the paper (arXiv 2209.08450):
   iterative methods as the use of such a pair in Sections 1 and 5).
 * ``fbp`` -- the composition, with optional FP16/BF16 rounding of stored
   filtered rows (Section 2.1 on 16-bit storage).
+* ``fourier_backproject`` / ``fourier_fbp`` -- the Fourier-domain
+  backprojection ("FourierRec", Sections 2.2 and 3): each padded filtered row
+  evaluated along the ray by its trigonometric interpolant, summed directly.
 * ``power_lambda_max`` / ``ls_solve`` -- gradient least squares with the pair.
 
 Parity status: every function here is pinned by closed forms, invariants or
@@ -52,6 +55,11 @@ from .fbp import (  # noqa: F401
     radon,
     fbp,
     fbp_points,
+    filter_rows_padded,
+    fourier_backproject,
+    fourier_backproject_points,
+    fourier_fbp,
+    fourier_fbp_points,
     power_lambda_max,
     ls_gradient,
     ls_solve,

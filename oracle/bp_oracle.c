@@ -139,3 +139,47 @@ void oracle_radon(const double *f, int64_t nz, int64_t N, const double *angles,
         }
     }
 }
+
+/*
+ * Fourier-domain backprojection ("FourierRec", paper Sections 2.2 and 3: the
+ * backprojection evaluated with exponentials in the frequency domain instead
+ * of linear interpolation in space).  What that method evaluates, written out
+ * without any gridding or fast transform:
+ *
+ *   f(x, y) = scale * sum_a y_a(m_a),   m_a = x cos(theta_a) + y sin(theta_a) + pos0
+ *   y_a(m)  = (1/L) Re sum_{k=-L/2}^{L/2} w_k Y_a[k mod L] exp(2 pi i k m / L)
+ *   w_k = 1/2 for k = -L/2 and k = L/2, else 1
+ *
+ * y_a is the real trigonometric interpolant of the padded filtered row whose
+ * DFT is Y_a (length L); pos0 is the padded-row position of the rotation axis.
+ * Y: one slice, [na][L] complex as separate real and imaginary arrays.
+ * Output at the listed voxels (ix[p], iy[p]); x = ix - floor(N/2), likewise y.
+ */
+void oracle_fourier_backproject_points(const double *Yre, const double *Yim, int64_t na, int64_t L,
+                                       const double *angles, double pos0, int64_t N, double scale,
+                                       const int64_t *ix, const int64_t *iy, int64_t npts, double *out)
+{
+    const int64_t half = N / 2;
+    const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npts; ++p) {
+        const double x = (double)(ix[p] - half);
+        const double y = (double)(iy[p] - half);
+        double acc = 0.0;
+        for (int64_t a = 0; a < na; ++a) {
+            const double m = x * cos(angles[a]) + y * sin(angles[a]) + pos0;
+            const double *yr = Yre + a * L;
+            const double *yi = Yim + a * L;
+            double row = 0.0;
+            for (int64_t k = -L / 2; k <= L / 2; ++k) {
+                const double wk = (k == -L / 2 || k == L / 2) ? 0.5 : 1.0;
+                const int64_t kk = ((k % L) + L) % L;
+                const double ph = two_pi * (double)k * m / (double)L;
+                /* Re(Y exp(i ph)) */
+                row += wk * (yr[kk] * cos(ph) - yi[kk] * sin(ph));
+            }
+            acc += row / (double)L;
+        }
+        out[p] = scale * acc;
+    }
+}

@@ -42,6 +42,8 @@ def _load():
         lib.oracle_backproject_points.restype = None
         lib.oracle_radon.argtypes = [pd, i64, i64, pd, d, i64, i64, pd]
         lib.oracle_radon.restype = None
+        lib.oracle_fourier_backproject_points.argtypes = [pd, pd, i64, i64, pd, d, i64, d, pi, pi, i64, pd]
+        lib.oracle_fourier_backproject_points.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -372,6 +374,77 @@ def fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, st
                   np.asarray(flat_slice)[:, None, :])[0]
     q = _round_storage(filter_rows(p, kind=kind), storage)
     return backproject_points(q, angles, center, N, ix, iy)
+
+
+# --------------------------------------------------------------------------
+# Fourier-domain backprojection (FourierRec).
+# --------------------------------------------------------------------------
+def filter_rows_padded(p: np.ndarray, L: int | None = None, kind: str = "ramp"):
+    """Uncropped filtered rows y = IFFT(H_W * FFT(pad(p))), FP64: returns (y, off)."""
+    n = p.shape[-1]
+    L = pad_len(n) if L is None else L
+    u, off = pad_rows(np.asarray(p, dtype=np.float64), L)
+    y = np.fft.ifft(np.fft.fft(u, axis=-1) * filter_response(L, kind), axis=-1).real
+    return y, off
+
+
+def fourier_backproject_points(y: np.ndarray, angles, pos0: float, N: int, ix, iy,
+                               scale: float | None = None) -> np.ndarray:
+    """Backprojection of one slice's padded rows y: [n_angles][L] with the
+    trigonometric interpolant of each row, at voxels (ix[k], iy[k]).
+
+    f(x, y) = scale * sum_a y_a(x cos + y sin + pos0), where y_a(m) is the real
+    trigonometric interpolant of row a (both Nyquist terms at half weight), so
+    y_a(m) = y[a][m] at integer m.  pos0 is the padded-row position of the
+    rotation axis (centre + pad offset).  Readings: the paper names the method
+    (Fourier-based backprojection with exponential interpolation kernels in
+    the frequency domain, Sections 2.2 and 3) without formulas; this is the
+    sum such a method approximates, evaluated directly (FP64 C loop).
+    """
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    na, L = y.shape
+    Y = np.fft.fft(y, axis=-1)
+    yre = np.ascontiguousarray(Y.real)
+    yim = np.ascontiguousarray(Y.imag)
+    ang = np.ascontiguousarray(angles, dtype=np.float64)
+    assert ang.shape == (na,)
+    ix = np.ascontiguousarray(ix, dtype=np.int64)
+    iy = np.ascontiguousarray(iy, dtype=np.int64)
+    if scale is None:
+        scale = math.pi / na
+    out = np.empty(ix.shape[0], dtype=np.float64)
+    _load().oracle_fourier_backproject_points(_pd(yre), _pd(yim), na, L, _pd(ang), float(pos0), N,
+                                              float(scale), _pi(ix), _pi(iy), ix.shape[0], _pd(out))
+    return out
+
+
+def fourier_backproject(y: np.ndarray, angles, pos0: float, N: int, scale: float | None = None) -> np.ndarray:
+    """``fourier_backproject_points`` at every voxel of each slice: y [nz][n_angles][L] -> [nz][N][N]."""
+    y = np.asarray(y, dtype=np.float64)
+    if y.ndim == 2:
+        y = y[None]
+    iy, ix = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    ix = ix.ravel()
+    iy = iy.ravel()
+    return np.stack([fourier_backproject_points(y[z], angles, pos0, N, ix, iy, scale).reshape(N, N)
+                     for z in range(y.shape[0])])
+
+
+def fourier_fbp(proj, dark, flat, angles, center: float, N: int | None = None, kind: str = "ramp"):
+    """FourierRec FBP: normalise, pad, filter, then ``fourier_backproject``
+    with pos0 = center + pad offset; scale pi / n_angles."""
+    p = normalize(proj, dark, flat)
+    n = p.shape[-1]
+    y, off = filter_rows_padded(p, kind=kind)
+    return fourier_backproject(y, angles, center + off, n if N is None else N)
+
+
+def fourier_fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, kind="ramp"):
+    """FourierRec FBP of one slice at listed voxels (raw counts of one detector row)."""
+    p = normalize(np.asarray(proj_slice)[:, None, :], np.asarray(dark_slice)[:, None, :],
+                  np.asarray(flat_slice)[:, None, :])[0]
+    y, off = filter_rows_padded(p, kind=kind)
+    return fourier_backproject_points(y, angles, center + off, N, ix, iy)
 
 
 # --------------------------------------------------------------------------
