@@ -214,6 +214,65 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan,
                               void* workspace, size_t workspace_bytes,
                               float* vol, void* stream, void* const* events);
 
+/* --------------------------------------------------------------------------
+ * Fourier-domain filtered backprojection ("FourierRec"; paper, Section 2.2:
+ * the backprojection evaluated with exponential interpolation kernels in the
+ * frequency domain, and Section 3, where it is the reference method).
+ *
+ * What it computes: for every slice,
+ *   vol(x, y) = (pi / n_angles) * sum_a y_a(x cos(theta_a) + y sin(theta_a) + center + off)
+ * where y_a is the real trigonometric interpolant of the padded, filtered row
+ * (pad length L = 2^ceil(log2(2 n_det)), edge padding, data at
+ * off = (L - n_det) / 2, both Nyquist terms at half weight): the same
+ * normalise -> pad -> filter steps as tp_fbp_chunk, then band-limited instead
+ * of linear interpolation along each ray (x = ix - N/2, y = iy - N/2).
+ *
+ * How: two slices travel as the real and imaginary parts of one complex row.
+ * Each row's spectrum (FFT, times the filter response and the phase of the
+ * axis position) is a line of samples through the origin of the 2-D frequency
+ * plane (Fourier slice theorem).  A deterministic gather resamples those polar
+ * samples onto a Cartesian grid of M = max(L, 2^ceil(log2(2N))) points per
+ * side with a truncated Gaussian, a 2-D inverse FFT returns to image space and
+ * division by the Gaussian's transform undoes the resampling kernel
+ * (unequally spaced FFT with oversampling >= 2).  half_width is the Gaussian's
+ * truncation radius in grid points (0 selects 6; 3..8 allowed): relative error
+ * about exp(-2.2 half_width) of the exact sum, plus FP32 rounding.
+ *
+ * Inputs as for tp_fbp_chunk (raw counts, strides, dark/flat frames; n_angles,
+ * n_det from the plan); vol: dev float [n_rows][N][N] (overwritten);
+ * kind: filter window (tables built on first use, see tp_fourier_prepare).
+ * workspace: dev, 256-byte aligned, not overlapping the inputs or vol.
+ * tp_fourier_workspace_bytes(plan, n_rows) bytes process every pair of rows in
+ * one pass; a smaller workspace (at least tp_fourier_workspace_bytes(plan, 2))
+ * processes the rows in several passes of as many pairs as fit.  Its contents
+ * are scratch.  Errors: TP_EINVAL for bad arguments (checked before any
+ * launch), TP_EUNSUPPORTED for M > 16384 or tables missing during capture.
+ * ------------------------------------------------------------------------ */
+size_t tp_fourier_workspace_bytes(const tp_plan* plan, int32_t n_rows);
+/* Builds the Fourier path's tables for (plan, kind, half_width) outside any
+ * graph capture (they are otherwise built on first use). */
+tp_status tp_fourier_prepare(const tp_plan* plan, tp_filter_kind kind, int32_t half_width);
+tp_status tp_fourier_fbp_chunk(const tp_plan* plan,
+                               const uint16_t* proj, int64_t proj_stride,
+                               const uint16_t* dark, int32_t n_dark,
+                               const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                               int32_t n_rows, tp_filter_kind kind, int32_t half_width,
+                               void* workspace, size_t workspace_bytes,
+                               float* vol, void* stream);
+/* As tp_fourier_fbp_chunk, recording caller-created hipEvent_t handles on
+ * `stream` for per-stage timing of the first pass: events[0] before the
+ * dark/flat means, [1] before the spectra, [2] before the gather onto the
+ * Cartesian grid, [3] before the inverse FFT along grid rows, [4] before the
+ * inverse FFT along columns (with deconvolution), [5] after it (end of the
+ * first pass).  Any entry may be NULL; events may be NULL. */
+tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan,
+                                      const uint16_t* proj, int64_t proj_stride,
+                                      const uint16_t* dark, int32_t n_dark,
+                                      const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                                      int32_t n_rows, tp_filter_kind kind, int32_t half_width,
+                                      void* workspace, size_t workspace_bytes,
+                                      float* vol, void* stream, void* const* events);
+
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* tp_last_error(void);
 /* Library version string. */

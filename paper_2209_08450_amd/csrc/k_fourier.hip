@@ -1,0 +1,349 @@
+// Fourier-domain filtered backprojection (paper, Section 2.2: backprojection
+// evaluated with exponential interpolation kernels in the frequency domain;
+// Section 3 uses it as the reference method).
+//
+// By the Fourier slice theorem the spectrum of the projection at angle theta
+// is the line of the 2-D image spectrum through the origin in direction
+// theta.  Filtered backprojection with band-limited interpolation along each
+// ray is therefore a non-uniform inverse DFT from these polar samples to the
+// voxel grid:
+//   f(x) = sum_{a,k} c_{a,k} exp(2 pi i (k / L) theta_a . x),
+//   c_{a,k} = (pi / na) / L * w_k * H[k] * U_a[k] * exp(2 pi i k pos0 / L),
+// where U_a is the DFT of the padded row, H the filter response, w_k = 1/2 at
+// the two Nyquist terms and pos0 the padded-row position of the axis.  It is
+// evaluated as an unequally spaced FFT: every polar sample is spread with a
+// Gaussian phi(u) = exp(-|u|^2 / (4 tau)) onto a Cartesian grid of M points
+// per side (oversampling >= 2), the grid is inverse-transformed, and each
+// voxel is divided by the Gaussian's Fourier transform.
+//
+// Two slices travel as the real and imaginary parts of one complex row, so
+// every transform and the spreading are complex and the two reconstructions
+// come back as the real and imaginary parts of the image.
+//
+// Stages (one launch each):
+//   k_fr_spectra  normalise two rows, pad, FFT, multiply by the E table and
+//                 store the L + 1 signed-frequency samples of the angle;
+//   k_fr_grid     for every grid point, sum the Gaussian-weighted samples of
+//                 every angle whose ray passes within the truncation radius
+//                 (a gather: no atomics, a fixed summation order; FP64
+//                 accumulation over angles);
+//   k_fr_rows     inverse FFT along the grid's fast axis, keeping the N
+//                 output rows, stored in 16-wide column groups;
+//   k_fr_cols     inverse FFT along the other axis, deconvolution, split of
+//                 the two slices, store.
+#include "fft_device.h"
+
+namespace tp {
+namespace {
+
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr int kFrTile = 16;             // grid points per tile side (4 waves of 8x8)
+constexpr int kFrBatch = 16;            // angles staged per batch
+constexpr float kFrHalfDiag = 10.6066017f;   // 7.5 sqrt(2): tile centre to its farthest point
+constexpr float kFrWaveHalfDiag = 4.9497475f;  // 3.5 sqrt(2): the same for a wave's 8x8 block
+
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, 0.0f - a.y); }
+
+int fr_block(int L) {
+    int b = L / 16;
+    if (b < 64) b = 64;
+    if (b > 1024) b = 1024;
+    return b;
+}
+
+template <typename K>
+hipError_t fr_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+}
+
+// ---------------------------------------------------------------------------
+// Spectra: one work-group per (pair of slices, angle).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+k_fr_spectra(RawInput in, int rows, const float* __restrict__ dmean, const float* __restrict__ rden,
+             const float2* __restrict__ tw, FourierTables t, float2* __restrict__ spec) {
+    extern __shared__ float2 buf[];
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int L = t.L, n = t.n, off = (L - n) / 2, h = L / 2;
+    const int p = blockIdx.x / t.na;
+    const int a = blockIdx.x - p * t.na;
+    const int z0 = 2 * p;
+    const bool has1 = z0 + 1 < rows;
+    const uint16_t* p0 = in.proj + a * in.proj_stride + static_cast<int64_t>(z0) * n;
+    const uint16_t* p1 = has1 ? p0 + n : p0;
+    const float* d0 = dmean + static_cast<int64_t>(z0) * n;
+    const float* e0 = rden + static_cast<int64_t>(z0) * n;
+    const float* d1 = has1 ? d0 + n : d0;
+    const float* e1 = has1 ? e0 + n : e0;
+    // clamping the column onto the detector gives the edge-replicated padding
+    for (int m = tid; m < L; m += B) {
+        const int c = min(max(m - off, 0), n - 1);
+        const float v0 = neglog_counts(static_cast<float>(p0[c]), d0[c], e0[c]);
+        const float v1 = has1 ? neglog_counts(static_cast<float>(p1[c]), d1[c], e1[c]) : 0.0f;
+        buf[m] = make_float2(v0, v1);
+    }
+    __syncthreads();
+    fft_forward_lds(buf, L, t.log2L, tw);
+    const int sl = t.slot[a];
+    const bool rev = (sl & 1) != 0;
+    float2* row = spec + (static_cast<int64_t>(p) * t.na + (sl >> 1)) * t.SL;
+    for (int m = tid; m < L; m += B) {
+        const float2 X = buf[m];
+        const int k = m < h ? m : m - L;  // m = L/2 is the -L/2 term
+        row[(rev ? -k : k) + h] = cmul(X, t.E[k + h]);
+        if (m == h) row[(rev ? -h : h) + h] = cmul(X, t.E[L]);  // and its +L/2 copy
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gather onto the Cartesian frequency grid.
+//
+// Work-group: one 16x16 tile of one pair's grid, 4 waves of 8x8 points.  The
+// grid is periodic (M points per side), so tiles near its edge also gather
+// through their images shifted by +-M.  For each tile image only the angles
+// whose ray passes within (radius + half-diagonal) of its centre can
+// contribute; they form one interval of the sorted reduced angles (two when
+// it wraps past pi), found by binary search.  Each batch of 16 angles stages,
+// per angle, the window of samples the tile can reach; each lane then sums its
+// taps along the ray with the Gaussian weights from a two-ratio recurrence:
+//   w(k+1) = w(k) r(k),  r(k+1) = r(k) exp2(-2 kappa s^2).
+// The tile centre's along-ray position and perpendicular offset are formed in
+// FP64 (integer + FP32 fraction), lanes add only their in-tile offsets, so the
+// coordinates keep FP32 precision at any grid size.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lower_bound_f(const float* v, int n, float x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (v[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int upper_bound_f(const float* v, int n, float x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (v[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256)
+k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__ grid) {
+    extern __shared__ float2 stage[];  // [kFrBatch][sw]
+    __shared__ int s_kc[kFrBatch];
+    __shared__ float s_fc[kFrBatch], s_cp[kFrBatch], s_cb[kFrBatch], s_sb[kFrBatch];
+    const int M = t.M, hM = M / 2, tps = M / kFrTile;
+    const int p = blockIdx.x / t.ntiles;
+    const int tile = t.tile_order[blockIdx.x - p * t.ntiles];
+    const int ty = tile / tps, tx = tile - ty * tps;
+    const int ux0 = tx * kFrTile - hM, uy0 = ty * kFrTile - hM;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int ox = (w >> 1) * 8 + (l >> 3), oy = (w & 1) * 8 + (l & 7);
+    // lane and wave-centre offsets from the tile centre
+    const float dx = static_cast<float>(ox) - 7.5f, dy = static_cast<float>(oy) - 7.5f;
+    const float wdx = static_cast<float>((w >> 1) * 8) - 4.0f, wdy = static_cast<float>((w & 1) * 8) - 4.0f;
+    const float2* sp = spec + static_cast<int64_t>(p) * t.na * t.SL;
+    const int h = t.L / 2;
+    const float reach = t.msp + kFrHalfDiag + 1.0f;
+    // each angle's taps are summed in FP32, the angles in FP64: central grid
+    // points collect thousands of angles
+    double ax = 0.0, ay = 0.0;
+    for (int img = 0; img < 9; ++img) {
+        const float Cx = static_cast<float>(ux0 + (img % 3 - 1) * M) + 7.5f;
+        const float Cy = static_cast<float>(uy0 + (img / 3 - 1) * M) + 7.5f;
+        const float rho = sqrtf(Cx * Cx + Cy * Cy);
+        if (rho > static_cast<float>(hM) + reach) continue;  // samples lie within radius M/2
+        int lo0 = 0, hi0 = t.na, lo1 = 0, hi1 = 0;
+        if (rho > reach) {
+            const float d = asinf(reach / rho) + 1e-4f;
+            if (d < 1.5f) {
+                float al = atan2f(Cy, Cx);
+                if (al < 0.0f) al += kPiF;
+                if (al >= kPiF) al -= kPiF;
+                const float lo = al - d, hi = al + d;
+                if (lo < 0.0f) {
+                    lo0 = lower_bound_f(t.beta, t.na, lo + kPiF);
+                    hi1 = upper_bound_f(t.beta, t.na, hi);
+                } else if (hi >= kPiF) {
+                    lo0 = lower_bound_f(t.beta, t.na, lo);
+                    hi1 = upper_bound_f(t.beta, t.na, hi - kPiF);
+                } else {
+                    lo0 = lower_bound_f(t.beta, t.na, lo);
+                    hi0 = upper_bound_f(t.beta, t.na, hi);
+                }
+            }
+        }
+        const double Cxd = static_cast<double>(Cx), Cyd = static_cast<double>(Cy);
+        for (int rr = 0; rr < 2; ++rr) {
+            const int alo = rr ? lo1 : lo0, ahi = rr ? hi1 : hi0;
+            for (int a0 = alo; a0 < ahi; a0 += kFrBatch) {
+                const int cnt = min(kFrBatch, ahi - a0);
+                __syncthreads();  // the previous batch's reads are done
+                if (threadIdx.x < cnt) {
+                    const int ap = a0 + threadIdx.x;
+                    const double cbd = t.cbd[ap], sbd = t.sbd[ap];
+                    const double tc = (Cxd * cbd + Cyd * sbd) * static_cast<double>(t.inv_s);
+                    const double kc = floor(tc);
+                    s_kc[threadIdx.x] = static_cast<int>(kc);
+                    s_fc[threadIdx.x] = static_cast<float>(tc - kc);
+                    s_cp[threadIdx.x] = static_cast<float>(Cyd * cbd - Cxd * sbd);
+                    s_cb[threadIdx.x] = t.cb[ap];
+                    s_sb[threadIdx.x] = t.sb[ap];
+                }
+                __syncthreads();
+                for (int i = threadIdx.x; i < cnt * t.sw; i += blockDim.x) {
+                    const int j = i / t.sw;
+                    const int k = s_kc[j] - t.back + (i - j * t.sw);  // signed frequency index
+                    float2 v = make_float2(0.0f, 0.0f);
+                    if (k >= -h && k <= h) v = sp[static_cast<int64_t>(a0 + j) * t.SL + (k + h)];
+                    stage[i] = v;
+                }
+                __syncthreads();
+                for (int j = 0; j < cnt; ++j) {
+                    const float cb = s_cb[j], sb = s_sb[j], cp = s_cp[j];
+                    // no lane of this wave within the radius of the ray
+                    if (fabsf(cp + wdy * cb - wdx * sb) > t.msp + kFrWaveHalfDiag + 0.01f) continue;
+                    const float tr = s_fc[j] + (dx * cb + dy * sb) * t.inv_s;  // along-ray, samples, from kc
+                    const float dp = cp + dy * cb - dx * sb;                   // perpendicular, grid points
+                    const int k0 = static_cast<int>(floorf(tr)) - t.nt / 2 + 1;
+                    const float q = (tr - static_cast<float>(k0)) * t.s;     // distance to tap k0, grid points
+                    float wgt = fabsf(dp) <= t.msp ? exp2f(-t.kappa * (dp * dp + q * q)) : 0.0f;
+                    float r = exp2f(t.kappa * (2.0f * t.s * q - t.s * t.s));
+                    const int idx = min(max(k0 + t.back, 0), t.sw - t.nt);
+                    const float2* sv = stage + j * t.sw + idx;
+                    float px = 0.0f, py = 0.0f;
+                    for (int tap = 0; tap < t.nt; ++tap) {
+                        const float2 v = sv[tap];
+                        px = __builtin_fmaf(wgt, v.x, px);
+                        py = __builtin_fmaf(wgt, v.y, py);
+                        wgt *= r;
+                        r *= t.ratio2;
+                    }
+                    ax += static_cast<double>(px);
+                    ay += static_cast<double>(py);
+                }
+            }
+        }
+    }
+    const int gx = (ux0 + ox + M) & (M - 1), gy = (uy0 + oy + M) & (M - 1);
+    grid[(static_cast<int64_t>(p) * M + gx) * M + gy] = make_float2(static_cast<float>(ax), static_cast<float>(ay));
+}
+
+// ---------------------------------------------------------------------------
+// Inverse FFT along the grid's fast axis (frequency uy -> image y) for one
+// (pair, ux) row; the inverse transform is conj(FFT(conj(.))).  Outputs
+// y = iy - N/2 for iy in [0, N) go to cols[p][iy / 16][ux][iy % 16], so the
+// column pass reads 16 neighbouring image rows from one 128-byte line.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+k_fr_rows(const float2* __restrict__ grid, const float2* __restrict__ tw, FourierTables t,
+          float2* __restrict__ cols) {
+    extern __shared__ float2 buf[];
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int M = t.M, N = t.N, hN = N / 2;
+    const int64_t rid = blockIdx.x;
+    const int p = static_cast<int>(rid / M);
+    const int ux = static_cast<int>(rid - static_cast<int64_t>(p) * M);
+    const float2* g = grid + rid * M;
+    for (int m = tid; m < M; m += B) buf[m] = cconj(g[m]);
+    __syncthreads();
+    fft_forward_lds(buf, M, t.log2M, tw);
+    const int ng = (N + 15) / 16;
+    float2* cp = cols + static_cast<int64_t>(p) * ng * M * 16;
+    for (int m = tid; m < M; m += B) {
+        const int y = m < M / 2 ? m : m - M;
+        const int iy = y + hN;
+        if (iy >= 0 && iy < N) cp[(static_cast<int64_t>(iy >> 4) * M + ux) * 16 + (iy & 15)] = cconj(buf[m]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse FFT along ux for one (pair, image row iy), deconvolution by the
+// Gaussian's transform, and the split into the pair's two slices.  The 16
+// work-groups of one column group run back to back on one XCD (work-groups
+// are dealt to the 8 XCDs in turn), so their shared 128-byte lines are read
+// from that XCD's L2.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+k_fr_cols(const float2* __restrict__ cols, const float2* __restrict__ tw, FourierTables t, int pairs, int rows,
+          float* __restrict__ vol) {
+    extern __shared__ float2 buf[];
+    const int tid = threadIdx.x, B = blockDim.x;
+    const int M = t.M, N = t.N, hN = N / 2;
+    const int ng = (N + 15) / 16;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, r = b >> 3;
+    const int gidx = (r >> 4) * 8 + xcd;
+    const int p = gidx / ng, gi = gidx - p * ng;
+    const int iy = gi * 16 + (r & 15);
+    if (p >= pairs || iy >= N) return;  // whole work-group
+    const float2* src = cols + (static_cast<int64_t>(p) * ng + gi) * M * 16 + (iy & 15);
+    for (int m = tid; m < M; m += B) buf[m] = cconj(src[static_cast<int64_t>(m) * 16]);
+    __syncthreads();
+    fft_forward_lds(buf, M, t.log2M, tw);
+    const float fy = t.D[iy];
+    const int z0 = 2 * p;
+    const bool has1 = z0 + 1 < rows;
+    float* o0 = vol + (static_cast<int64_t>(z0) * N + iy) * N;
+    float* o1 = o0 + static_cast<int64_t>(N) * N;
+    for (int m = tid; m < M; m += B) {
+        const int x = m < M / 2 ? m : m - M;
+        const int ix = x + hN;
+        if (ix >= 0 && ix < N) {
+            const float2 v = buf[m];  // conj of the inverse transform: (re, -im)
+            const float f = t.D[ix] * fy;
+            o0[ix] = v.x * f;
+            if (has1) o1[ix] = (0.0f - v.y) * f;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fourier_spectra(const RawInput& in, int rows, const float* dmean, const float* rden,
+                                  const float2* tw_L, const FourierTables& t, float2* spec, hipStream_t st) {
+    const int pairs = (rows + 1) / 2;
+    const size_t lds = static_cast<size_t>(t.L) * sizeof(float2);
+    hipError_t e = fr_lds(k_fr_spectra, lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(pairs) * t.na));
+    hipLaunchKernelGGL(k_fr_spectra, grid, dim3(fr_block(t.L)), lds, st, in, rows, dmean, rden, tw_L, t, spec);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_grid(const FourierTables& t, const float2* spec, int pairs, float2* grid, hipStream_t st) {
+    const size_t lds = static_cast<size_t>(kFrBatch) * t.sw * sizeof(float2);
+    hipError_t e = fr_lds(k_fr_grid, lds);
+    if (e != hipSuccess) return e;
+    const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * t.ntiles));
+    hipLaunchKernelGGL(k_fr_grid, g, dim3(256), lds, st, t, spec, grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const float2* grid, int pairs,
+                               float2* cols, hipStream_t st) {
+    const size_t lds = static_cast<size_t>(t.M) * sizeof(float2);
+    hipError_t e = fr_lds(k_fr_rows, lds);
+    if (e != hipSuccess) return e;
+    const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * t.M));
+    hipLaunchKernelGGL(k_fr_rows, g, dim3(fr_block(t.M)), lds, st, grid, tw_M, t, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
+                               float* vol, hipStream_t st) {
+    const size_t lds = static_cast<size_t>(t.M) * sizeof(float2);
+    hipError_t e = fr_lds(k_fr_cols, lds);
+    if (e != hipSuccess) return e;
+    const int64_t groups = static_cast<int64_t>(pairs) * ((t.N + 15) / 16);
+    const dim3 g(static_cast<unsigned>(((groups + 7) / 8) * 8 * 16));
+    hipLaunchKernelGGL(k_fr_cols, g, dim3(fr_block(t.M)), lds, st, cols, tw_M, t, pairs, rows, vol);
+    return hipGetLastError();
+}
+
+}  // namespace tp

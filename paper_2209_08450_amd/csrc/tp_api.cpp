@@ -16,16 +16,25 @@
 
 #include "tp_internal.h"
 
+struct FourierEntry {
+    void* block = nullptr;  // one allocation holding the tables
+    tp::FourierTables t{};
+};
+
 struct tp_plan {
     int device = -1;
     int na = 0, n = 0, N = 0, nb = 0;
     double center = 0.0;
+    std::vector<double> angles;  // FP64 copy for tables built later
     void* dev_block = nullptr;  // one allocation holding every geometry table
     tp::GeoTables geo{};
     tp::FilterTables filt{};
     // backprojection tuning per storage type (F32, F16, BF16)
     int bp_k[3] = {16, 16, 16};
     int bp_a[3] = {8, 16, 8};
+    // Fourier-domain backprojection tables per (filter window, truncation radius)
+    mutable std::mutex fr_mu;
+    mutable std::map<std::pair<int, int>, FourierEntry> fr;
 };
 
 namespace {
@@ -233,6 +242,192 @@ tp_status check_raw(const uint16_t* proj, const uint16_t* dark, int32_t n_dark, 
     return TP_OK;
 }
 
+// ---- Fourier-domain backprojection: sizes, tables, workspace layout ----
+constexpr int kFourierDefaultHalfWidth = 6;
+constexpr int kFourierMaxSide = 16384;
+// Tile half-diagonal (7.5 sqrt(2)) of the gather's 16x16 tiles, as in the kernel.
+constexpr double kFrHalfDiag = 10.606601717798213;
+
+struct FrDims {
+    int L, M, SL, ng;  // pad length, grid side, samples per spectrum row, 16-row column groups
+    size_t spec_pair, cols_pair, grid_pair;
+};
+
+FrDims fr_dims(const tp_plan* plan) {
+    FrDims d{};
+    d.L = plan->filt.L;
+    d.M = std::max({d.L, 1 << ilog2(2 * static_cast<int64_t>(plan->N)), 64});
+    d.SL = d.L + 1;
+    d.ng = (plan->N + 15) / 16;
+    d.spec_pair = static_cast<size_t>(plan->na) * d.SL * sizeof(float2);
+    d.cols_pair = static_cast<size_t>(d.ng) * 16 * d.M * sizeof(float2);
+    d.grid_pair = static_cast<size_t>(d.M) * d.M * sizeof(float2);
+    return d;
+}
+
+// Workspace: dark/flat tables of every row, then (per pass of P pairs) a
+// region holding the spectra and later the column-group intermediate, then
+// the Cartesian grid.
+size_t fr_workspace(const tp_plan* plan, int32_t n_rows, int64_t P) {
+    const FrDims d = fr_dims(plan);
+    return tp_normalize_workspace_bytes(n_rows, plan->n) +
+           align256(static_cast<size_t>(P) * std::max(d.spec_pair, d.cols_pair)) +
+           align256(static_cast<size_t>(P) * d.grid_pair);
+}
+
+tp_status fourier_tables(const tp_plan* plan, tp_filter_kind kind, int msp, tp::FourierTables* out,
+                         hipStream_t st_for_capture_check) {
+    std::lock_guard<std::mutex> lk(plan->fr_mu);
+    const auto key = std::make_pair(static_cast<int>(kind), msp);
+    auto it = plan->fr.find(key);
+    if (it != plan->fr.end()) {
+        *out = it->second.t;
+        return TP_OK;
+    }
+    if (st_for_capture_check != nullptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st_for_capture_check, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            return fail(TP_EUNSUPPORTED,
+                        "Fourier tables for window %d, half width %d not built; call tp_fourier_prepare before "
+                        "capture", static_cast<int>(kind), msp);
+    }
+    const FrDims d = fr_dims(plan);
+    const int na = plan->na, n = plan->n, N = plan->N, L = d.L, M = d.M, h = L / 2;
+    const double s = static_cast<double>(M) / L;
+    const double tau = msp / (2.0 * std::sqrt(2.0) * M_PI);
+    const double kappa = 1.0 / (4.0 * tau * std::log(2.0));
+    const int nt = 2 * static_cast<int>(std::ceil(msp / s));
+    const int back = static_cast<int>(std::ceil((kFrHalfDiag + 1.0) / s)) + nt / 2;
+    const int sw = static_cast<int>(std::ceil(2.0 * (kFrHalfDiag + 1.0) / s)) + nt + 4;
+    const double pos0 = plan->center + (L - n) / 2;
+    // E[k + L/2] = (pi / na) / L * w_k * H[k] * exp(2 pi i k pos0 / L)
+    std::vector<double> H;
+    filter_response_fp64(L, kind, H);
+    std::vector<float2> E(static_cast<size_t>(L) + 1);
+    for (int k = -h; k <= h; ++k) {
+        const double wk = (k == -h || k == h) ? 0.5 : 1.0;
+        const double amp = (M_PI / na) / L * wk * H[static_cast<size_t>((k + L) % L)];
+        double fr = static_cast<double>(k) * pos0 / L;
+        fr -= std::floor(fr);
+        const double ph = 2.0 * M_PI * fr;
+        E[static_cast<size_t>(k + h)] =
+            make_float2(static_cast<float>(amp * std::cos(ph)), static_cast<float>(amp * std::sin(ph)));
+    }
+    // D[i] = 1 / phi_hat((i - N/2) / M), phi_hat(v) = sqrt(4 pi tau) exp(-4 pi^2 tau v^2)
+    std::vector<float> D(N);
+    for (int i = 0; i < N; ++i) {
+        const double v = static_cast<double>(i - N / 2) / M;
+        D[i] = static_cast<float>(std::exp(4.0 * M_PI * M_PI * tau * v * v) / std::sqrt(4.0 * M_PI * tau));
+    }
+    // angles reduced modulo pi into [0, pi), sorted; reversed when the reduction was by an odd multiple of pi
+    std::vector<double> beta(na);
+    std::vector<int> rev(na), idx(na);
+    for (int a = 0; a < na; ++a) {
+        double t2 = std::fmod(plan->angles[a], 2.0 * M_PI);
+        if (t2 < 0) t2 += 2.0 * M_PI;
+        if (t2 >= 2.0 * M_PI) t2 = 0.0;
+        rev[a] = t2 >= M_PI;
+        beta[a] = rev[a] ? t2 - M_PI : t2;
+        if (beta[a] >= M_PI) beta[a] = 0.0;
+        idx[a] = a;
+    }
+    std::sort(idx.begin(), idx.end(), [&](int p, int q) { return beta[p] < beta[q] || (beta[p] == beta[q] && p < q); });
+    std::vector<double> cbd(na), sbd(na);
+    std::vector<float> cb(na), sb(na), bf(na);
+    std::vector<int> slot(na);
+    for (int j = 0; j < na; ++j) {
+        const int a = idx[j];
+        cbd[j] = std::cos(beta[a]);
+        sbd[j] = std::sin(beta[a]);
+        cb[j] = static_cast<float>(cbd[j]);
+        sb[j] = static_cast<float>(sbd[j]);
+        bf[j] = static_cast<float>(beta[a]);
+        slot[a] = 2 * j + rev[a];
+    }
+    // 16x16 tiles of the grid, nearest the origin first (their angle lists are the longest)
+    const int tps = M / 16, ntiles = tps * tps;
+    std::vector<int> tiles(ntiles);
+    std::vector<double> dist(ntiles);
+    for (int i = 0; i < ntiles; ++i) {
+        const double cx = (i % tps) * 16 - M / 2 + 7.5, cy = (i / tps) * 16 - M / 2 + 7.5;
+        dist[i] = cx * cx + cy * cy;
+        tiles[i] = i;
+    }
+    std::sort(tiles.begin(), tiles.end(),
+              [&](int p, int q) { return dist[p] < dist[q] || (dist[p] == dist[q] && p < q); });
+
+    const size_t sE = align256(sizeof(float2) * E.size()), sD = align256(sizeof(float) * N);
+    const size_t sd = align256(sizeof(double) * na), sf = align256(sizeof(float) * na);
+    const size_t sT = align256(sizeof(int) * ntiles);
+    const size_t total = sE + sD + 2 * sd + 4 * sf + sT;
+    FourierEntry fe;
+    hipError_t e = hipMalloc(&fe.block, total);
+    if (e != hipSuccess) return fail(TP_ENOMEM, "hipMalloc(Fourier tables, %zu bytes): %s", total, hipGetErrorString(e));
+    char* b = static_cast<char*>(fe.block);
+    char* dE = b;
+    char* dD = dE + sE;
+    char* dcbd = dD + sD;
+    char* dsbd = dcbd + sd;
+    char* dcb = dsbd + sd;
+    char* dsb = dcb + sf;
+    char* dbeta = dsb + sf;
+    char* dslot = dbeta + sf;
+    char* dtile = dslot + sf;
+    e = hipMemcpy(dE, E.data(), sizeof(float2) * E.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dD, D.data(), sizeof(float) * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dcbd, cbd.data(), sizeof(double) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dsbd, sbd.data(), sizeof(double) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dcb, cb.data(), sizeof(float) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dsb, sb.data(), sizeof(float) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dbeta, bf.data(), sizeof(float) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dslot, slot.data(), sizeof(int) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dtile, tiles.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(fe.block);
+        return hip_fail(e, "hipMemcpy(Fourier tables)");
+    }
+    tp::FourierTables& t = fe.t;
+    t.E = reinterpret_cast<const float2*>(dE);
+    t.D = reinterpret_cast<const float*>(dD);
+    t.cbd = reinterpret_cast<const double*>(dcbd);
+    t.sbd = reinterpret_cast<const double*>(dsbd);
+    t.cb = reinterpret_cast<const float*>(dcb);
+    t.sb = reinterpret_cast<const float*>(dsb);
+    t.beta = reinterpret_cast<const float*>(dbeta);
+    t.slot = reinterpret_cast<const int*>(dslot);
+    t.tile_order = reinterpret_cast<const int*>(dtile);
+    t.na = na;
+    t.n = n;
+    t.N = N;
+    t.L = L;
+    t.log2L = ilog2(L);
+    t.M = M;
+    t.log2M = ilog2(M);
+    t.SL = d.SL;
+    t.nt = nt;
+    t.sw = sw;
+    t.ntiles = ntiles;
+    t.back = back;
+    t.s = static_cast<float>(s);
+    t.inv_s = static_cast<float>(1.0 / s);
+    t.msp = static_cast<float>(msp);
+    t.kappa = static_cast<float>(kappa);
+    t.ratio2 = static_cast<float>(std::exp2(-2.0 * kappa * s * s));
+    plan->fr.emplace(key, fe);
+    *out = t;
+    return TP_OK;
+}
+
+tp_status fourier_half_width(int32_t half_width, int* msp) {
+    if (half_width == 0) {
+        *msp = kFourierDefaultHalfWidth;
+        return TP_OK;
+    }
+    if (half_width < 3 || half_width > 8) return fail(TP_EINVAL, "half_width=%d not in 3..8 (or 0)", half_width);
+    *msp = half_width;
+    return TP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -346,6 +541,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
         delete p;
         return hip_fail(e, "hipMemcpy(plan tables)");
     }
+    p->angles.assign(g->angles, g->angles + na);
     p->na = na;
     p->n = g->n_det;
     p->N = N;
@@ -381,6 +577,10 @@ tp_status tp_plan_destroy(tp_plan* plan) {
     (void)hipGetDevice(&cur);
     if (cur != plan->device) (void)hipSetDevice(plan->device);
     hipError_t e = hipFree(plan->dev_block);
+    for (auto& kv : plan->fr) {
+        const hipError_t e2 = hipFree(kv.second.block);
+        if (e == hipSuccess) e = e2;
+    }
     if (cur != plan->device) (void)hipSetDevice(cur);
     delete plan;
     if (e != hipSuccess) return hip_fail(e, "hipFree(plan tables)");
@@ -590,6 +790,108 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
                                st);
     if (e != hipSuccess) return hip_fail(e, "backproject launch");
     if ((e = mark(3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return TP_OK;
+}
+
+size_t tp_fourier_workspace_bytes(const tp_plan* plan, int32_t n_rows) {
+    if (!plan || n_rows <= 0) return 0;
+    return fr_workspace(plan, n_rows, (n_rows + 1) / 2);
+}
+
+tp_status tp_fourier_prepare(const tp_plan* plan, tp_filter_kind kind, int32_t half_width) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
+    int msp = 0;
+    tp_status s = fourier_half_width(half_width, &msp);
+    if (s != TP_OK) return s;
+    const FrDims d = fr_dims(plan);
+    if (d.M > kFourierMaxSide) return fail(TP_EUNSUPPORTED, "Fourier grid side %d > %d", d.M, kFourierMaxSide);
+    tp::FourierTables t;
+    if ((s = fourier_tables(plan, kind, msp, &t, nullptr)) != TP_OK) return s;
+    tp::FilterTables fm;
+    return filter_tables(d.M, TP_RAMP, &fm, nullptr);
+}
+
+tp_status tp_fourier_fbp_chunk(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride, const uint16_t* dark,
+                               int32_t n_dark, const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                               int32_t n_rows, tp_filter_kind kind, int32_t half_width, void* workspace,
+                               size_t workspace_bytes, float* vol, void* stream) {
+    return tp_fourier_fbp_chunk_events(plan, proj, proj_stride, dark, n_dark, flat, n_flat, frame_stride, n_rows,
+                                       kind, half_width, workspace, workspace_bytes, vol, stream, nullptr);
+}
+
+tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride,
+                                      const uint16_t* dark, int32_t n_dark, const uint16_t* flat, int32_t n_flat,
+                                      int64_t frame_stride, int32_t n_rows, tp_filter_kind kind, int32_t half_width,
+                                      void* workspace, size_t workspace_bytes, float* vol, void* stream,
+                                      void* const* events) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, plan->na, n_rows,
+                            plan->n);
+    if (s != TP_OK) return s;
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
+    int msp = 0;
+    if ((s = fourier_half_width(half_width, &msp)) != TP_OK) return s;
+    if (!vol) return fail(TP_EINVAL, "vol is null");
+    if (!workspace) return fail(TP_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(TP_EINVAL, "workspace not 256-byte aligned");
+    const FrDims d = fr_dims(plan);
+    if (d.M > kFourierMaxSide) return fail(TP_EUNSUPPORTED, "Fourier grid side %d > %d", d.M, kFourierMaxSide);
+    const int pairs = (n_rows + 1) / 2;
+    const size_t df = tp_normalize_workspace_bytes(n_rows, plan->n);
+    if (workspace_bytes < fr_workspace(plan, n_rows, 1))
+        return fail(TP_EINVAL, "workspace %zu < %zu bytes (one pair of rows)", workspace_bytes,
+                    fr_workspace(plan, n_rows, 1));
+    int64_t P = static_cast<int64_t>((workspace_bytes - df) / (std::max(d.spec_pair, d.cols_pair) + d.grid_pair));
+    P = std::min<int64_t>(std::max<int64_t>(P, 1), pairs);
+    const int64_t ntiles = static_cast<int64_t>(d.M / 16) * (d.M / 16);
+    P = std::min<int64_t>(P, 0x7fffffffLL / std::max<int64_t>({ntiles, plan->na, d.M}));
+    while (P > 1 && fr_workspace(plan, n_rows, P) > workspace_bytes) --P;
+    if (P < 1) return fail(TP_EINVAL, "grid too large for one launch");
+    auto st = static_cast<hipStream_t>(stream);
+    tp::FourierTables t;
+    if ((s = fourier_tables(plan, kind, msp, &t, st)) != TP_OK) return s;
+    tp::FilterTables fm;
+    if ((s = filter_tables(d.M, TP_RAMP, &fm, st)) != TP_OK) return s;
+    float* dmean = static_cast<float*>(workspace);
+    float* den = reinterpret_cast<float*>(static_cast<char*>(workspace) + df / 2);
+    char* regA = static_cast<char*>(workspace) + df;
+    char* regB = regA + align256(static_cast<size_t>(P) * std::max(d.spec_pair, d.cols_pair));
+    float2* spec = reinterpret_cast<float2*>(regA);
+    float2* cols = reinterpret_cast<float2*>(regA);
+    float2* grid = reinterpret_cast<float2*>(regB);
+    tp::RawInput in{proj, proj_stride, dark, flat, frame_stride, n_dark, n_flat};
+    bool first = true;
+    auto mark = [&](int i) -> hipError_t {
+        if (!first || !events || !events[i]) return hipSuccess;
+        return hipEventRecord(static_cast<hipEvent_t>(events[i]), st);
+    };
+    hipError_t e = mark(0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    e = tp::launch_darkflat(in, n_rows, plan->n, dmean, den, st);
+    if (e != hipSuccess) return hip_fail(e, "darkflat launch");
+    for (int r0 = 0; r0 < n_rows; r0 += static_cast<int>(2 * P)) {
+        const int rows = std::min(static_cast<int>(2 * P), n_rows - r0);
+        const int pp = (rows + 1) / 2;
+        tp::RawInput ip = in;
+        ip.proj = proj + static_cast<int64_t>(r0) * plan->n;
+        const int64_t roff = static_cast<int64_t>(r0) * plan->n;
+        if ((e = mark(1)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_fourier_spectra(ip, rows, dmean + roff, den + roff, plan->filt.tw, t, spec, st);
+        if (e != hipSuccess) return hip_fail(e, "Fourier spectra launch");
+        if ((e = mark(2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_fourier_grid(t, spec, pp, grid, st);
+        if (e != hipSuccess) return hip_fail(e, "Fourier grid launch");
+        if ((e = mark(3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_fourier_rows(t, fm.tw, grid, pp, cols, st);
+        if (e != hipSuccess) return hip_fail(e, "Fourier row-transform launch");
+        if ((e = mark(4)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_fourier_cols(t, fm.tw, cols, pp, rows, vol + static_cast<int64_t>(r0) * plan->N * plan->N,
+                                    st);
+        if (e != hipSuccess) return hip_fail(e, "Fourier column-transform launch");
+        if ((e = mark(5)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        first = false;
+    }
     return TP_OK;
 }
 

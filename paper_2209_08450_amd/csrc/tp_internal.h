@@ -52,6 +52,32 @@ struct RawInput {
     int n_dark, n_flat;
 };
 
+// Tables of the Fourier-domain backprojection (one set per plan, filter
+// window and truncation radius).  Spectra rows are stored per pair of slices
+// and per angle in the order of the angles reduced modulo pi (sorted), each
+// row holding the L + 1 samples of signed frequency k = -L/2 .. L/2 at index
+// k + L/2 (reversed for angles whose reduction flipped the ray direction).
+struct FourierTables {
+    const float2* E;        // [L + 1] (pi / na) / L * w_k * H[k] * exp(2 pi i k pos0 / L)
+    const float* D;         // [N]     1 / (FT of the 1-D Gaussian at (i - N/2) / M)
+    const double* cbd;      // [na]    cos / sin of the sorted reduced angles, FP64
+    const double* sbd;
+    const float* cb;        // [na]    the same, FP32
+    const float* sb;
+    const float* beta;      // [na]    sorted reduced angles in [0, pi), FP32
+    const int* slot;        // [na]    angle a -> 2 * (sorted position) + (direction reversed)
+    const int* tile_order;  // [ntiles] 16x16 grid tiles, nearest the origin first
+    int na, n, N, L, log2L, M, log2M, SL;  // SL = L + 1 samples per row
+    int nt;                 // gather taps per lane along the ray
+    int sw;                 // staged samples per (tile, angle)
+    int ntiles;
+    int back;               // staged samples before the tile centre's sample: ceil((h + 1) / s) + nt / 2
+    float s, inv_s;         // grid points per frequency sample (M / L, a power of two >= 1)
+    float msp;              // truncation radius (grid points)
+    float kappa;            // log2(e) / (4 tau)
+    float ratio2;           // exp2(-2 kappa s^2): ratio of successive tap ratios
+};
+
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_darkflat(const RawInput& in, int n_rows, int n_det, float* dmean, float* den,
                            hipStream_t st);
@@ -69,6 +95,14 @@ size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_b
 size_t radon_workspace_bytes(const GeoTables& g, int n_rows);
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
                         hipStream_t st);
+
+hipError_t launch_fourier_spectra(const RawInput& in, int rows, const float* dmean, const float* rden,
+                                  const float2* tw_L, const FourierTables& t, float2* spec, hipStream_t st);
+hipError_t launch_fourier_grid(const FourierTables& t, const float2* spec, int pairs, float2* grid, hipStream_t st);
+hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const float2* grid, int pairs,
+                               float2* cols, hipStream_t st);
+hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
+                               float* vol, hipStream_t st);
 
 // ---- detector coordinate decisions shared by backprojection and radon ----
 // Offset of voxel (dx, dy) within its 32x32 tile at one angle; bf is the

@@ -64,6 +64,13 @@ _fbp_chunk = _proto("tp_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32,
                     _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp)
 _fbp_chunk_events = _proto("tp_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
                            _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp, ctypes.POINTER(_c_vp))
+_fourier_ws = _proto("tp_fourier_workspace_bytes", _c_sz, _c_vp, _c_i32)
+_fourier_prepare = _proto("tp_fourier_prepare", _c_i32, _c_vp, _c_i32, _c_i32)
+_fourier_chunk = _proto("tp_fourier_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
+                        _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp)
+_fourier_chunk_events = _proto("tp_fourier_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
+                               _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp,
+                               ctypes.POINTER(_c_vp))
 _last_error = _proto("tp_last_error", ctypes.c_char_p)
 _version = _proto("tp_version", ctypes.c_char_p)
 
@@ -192,6 +199,14 @@ class Plan:
 
     def radon_workspace_bytes(self, n_rows: int) -> int:
         return int(_radon_ws(self._h, int(n_rows)))
+
+    def fourier_workspace_bytes(self, n_rows: int) -> int:
+        """Workspace for the Fourier-domain FBP of n_rows rows in one pass."""
+        return int(_fourier_ws(self._h, int(n_rows)))
+
+    def fourier_prepare(self, kind="ramp", half_width: int = 0):
+        """Build the Fourier-domain path's tables (before graph capture)."""
+        _check(_fourier_prepare(self._h, filter_code(kind), int(half_width)))
 
 
 def filter_code(kind) -> int:
@@ -344,4 +359,49 @@ def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=N
                                  kcode, code, _dev(workspace, "workspace"),
                                  workspace.numel() * workspace.element_size(), _dev(out, "out"),
                                  _stream_ptr(stream), arr))
+    return out
+
+
+def fourier_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, stream=None, events=None,
+                      kind="ramp", half_width: int = 0):
+    """Raw counts of a row chunk -> Fourier-domain FBP slices [rows][N][N] (float32).
+
+    Same inputs as ``fbp_chunk``; the backprojection uses the trigonometric
+    interpolant of each padded filtered row, evaluated by gridding polar
+    spectra onto a Cartesian frequency grid (tp_fourier_fbp_chunk).
+    ``half_width``: Gaussian truncation radius in grid points (0 = 6).
+    ``workspace``: default ``plan.fourier_workspace_bytes(rows)`` bytes (one
+    pass); a smaller one runs the rows in several passes.
+    ``events``: optional list of six recorded-once ``torch.cuda.Event``
+    objects (or None entries), marked before the dark/flat means, the
+    spectra, the gather, the two inverse-FFT passes, and after the first pass.
+    """
+    torch = _torch()
+    n_angles, n_rows, n_det = (int(s) for s in proj.shape)
+    if n_angles != plan.n_angles or n_det != plan.n_det:
+        raise ValueError("proj does not match the plan geometry")
+    pp, ps = _raw_strides(proj, "proj", n_det)
+    dp, fs = _raw_strides(dark, "dark", n_det)
+    fp, fs2 = _raw_strides(flat, "flat", n_det)
+    if fs != fs2:
+        raise ValueError("dark and flat must share one frame stride")
+    if dark.shape[1] != n_rows or flat.shape[1] != n_rows:
+        raise ValueError("dark/flat rows must match proj rows")
+    kcode = filter_code(kind)
+    if workspace is None:
+        workspace = _workspace(plan.fourier_workspace_bytes(n_rows), proj.device)
+    if out is None:
+        out = torch.empty((n_rows, plan.n_vox, plan.n_vox), dtype=torch.float32, device=proj.device)
+    args = (plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode, int(half_width),
+            _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(), _dev(out, "out"),
+            _stream_ptr(stream))
+    if events is None:
+        _check(_fourier_chunk(*args))
+    else:
+        if len(events) != 6:
+            raise ValueError("events must hold six entries")
+        if any(e is not None and not e.cuda_event for e in events):
+            raise ValueError("record each event once before passing it (torch creates it lazily)")
+        arr = (_c_vp * 6)(*[_c_vp(e.cuda_event) if e is not None else _c_vp() for e in events])
+        _check(_fourier_chunk_events(*args, arr))
     return out

@@ -135,3 +135,15 @@ def test_normalize_validation(tp):
     assert tp._normalize(p, 0, p, 1, p, 1, 0, 4, 70000, 8, 0, p, p, 1 << 30, nul) == tp.TP_EINVAL
     assert tp._normalize_ws(2, 8) == 512
     assert tp._normalize_ws(0, 8) == 0
+
+
+def test_fourier_validation_without_plan(tp):
+    nul = ctypes.c_void_p()
+    p = ctypes.c_void_p(0x100000)
+    assert tp._fourier_ws(nul, 8) == 0
+    assert tp._fourier_prepare(nul, tp.TP_RAMP, 0) == tp.TP_EINVAL and "plan" in tp.last_error()
+    st = tp._fourier_chunk(nul, p, 0, p, 1, p, 1, 0, 4, tp.TP_RAMP, 0, p, 1 << 20, p, nul)
+    assert st == tp.TP_EINVAL and "plan" in tp.last_error()
+    arr = (ctypes.c_void_p * 6)()
+    st = tp._fourier_chunk_events(nul, p, 0, p, 1, p, 1, 0, 4, tp.TP_RAMP, 0, p, 1 << 20, p, nul, arr)
+    assert st == tp.TP_EINVAL
