@@ -132,15 +132,19 @@ __device__ __forceinline__ int upper_bound_f(const float* v, int n, float x) {
     return lo;
 }
 
+template <int NT>
 __global__ void __launch_bounds__(256)
 k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__ grid) {
-    extern __shared__ float2 stage[];  // [kFrBatch][sw]
+    extern __shared__ float4 stage[];  // [kFrBatch][sw]: (sample k, sample -k)
     __shared__ int s_kc[kFrBatch];
-    __shared__ float s_fc[kFrBatch], s_cp[kFrBatch], s_cb[kFrBatch], s_sb[kFrBatch];
+    __shared__ float4 s_geo[kFrBatch];  // (fraction of the centre's position, perpendicular offset, cos, sin)
     const int M = t.M, hM = M / 2, tps = M / kFrTile;
     const int p = blockIdx.x / t.ntiles;
     const int tile = t.tile_order[blockIdx.x - p * t.ntiles];
     const int ty = tile / tps, tx = tile - ty * tps;
+    // tile rows ty >= tps/2 (uy >= 0) also produce the mirror points -u;
+    // tile row 0 only supplies the grid row uy = -M/2, which no mirror reaches
+    const bool nyq = ty == 0;
     const int ux0 = tx * kFrTile - hM, uy0 = ty * kFrTile - hM;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int ox = (w >> 1) * 8 + (l >> 3), oy = (w & 1) * 8 + (l & 7);
@@ -152,7 +156,7 @@ k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__
     const float reach = t.msp + kFrHalfDiag + 1.0f;
     // each angle's taps are summed in FP32, the angles in FP64: central grid
     // points collect thousands of angles
-    double ax = 0.0, ay = 0.0;
+    double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
     for (int img = 0; img < 9; ++img) {
         const float Cx = static_cast<float>(ux0 + (img % 3 - 1) * M) + 7.5f;
         const float Cy = static_cast<float>(uy0 + (img / 3 - 1) * M) + 7.5f;
@@ -190,48 +194,64 @@ k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__
                     const double tc = (Cxd * cbd + Cyd * sbd) * static_cast<double>(t.inv_s);
                     const double kc = floor(tc);
                     s_kc[threadIdx.x] = static_cast<int>(kc);
-                    s_fc[threadIdx.x] = static_cast<float>(tc - kc);
-                    s_cp[threadIdx.x] = static_cast<float>(Cyd * cbd - Cxd * sbd);
-                    s_cb[threadIdx.x] = t.cb[ap];
-                    s_sb[threadIdx.x] = t.sb[ap];
+                    s_geo[threadIdx.x] = make_float4(static_cast<float>(tc - kc),
+                                                     static_cast<float>(Cyd * cbd - Cxd * sbd), t.cb[ap], t.sb[ap]);
                 }
                 __syncthreads();
                 for (int i = threadIdx.x; i < cnt * t.sw; i += blockDim.x) {
                     const int j = i / t.sw;
                     const int k = s_kc[j] - t.back + (i - j * t.sw);  // signed frequency index
-                    float2 v = make_float2(0.0f, 0.0f);
-                    if (k >= -h && k <= h) v = sp[static_cast<int64_t>(a0 + j) * t.SL + (k + h)];
-                    stage[i] = v;
+                    const float2* row = sp + static_cast<int64_t>(a0 + j) * t.SL + h;
+                    const float2 v = (k >= -h && k <= h) ? row[k] : make_float2(0.0f, 0.0f);
+                    const float2 u = (k >= -h && k <= h) ? row[-k] : make_float2(0.0f, 0.0f);
+                    stage[i] = make_float4(v.x, v.y, u.x, u.y);
                 }
                 __syncthreads();
                 for (int j = 0; j < cnt; ++j) {
-                    const float cb = s_cb[j], sb = s_sb[j], cp = s_cp[j];
+                    const float4 geo = s_geo[j];
+                    const float cb = geo.z, sb = geo.w, cp = geo.y;
                     // no lane of this wave within the radius of the ray
                     if (fabsf(cp + wdy * cb - wdx * sb) > t.msp + kFrWaveHalfDiag + 0.01f) continue;
-                    const float tr = s_fc[j] + (dx * cb + dy * sb) * t.inv_s;  // along-ray, samples, from kc
-                    const float dp = cp + dy * cb - dx * sb;                   // perpendicular, grid points
-                    const int k0 = static_cast<int>(floorf(tr)) - t.nt / 2 + 1;
-                    const float q = (tr - static_cast<float>(k0)) * t.s;     // distance to tap k0, grid points
+                    const float tr = geo.x + (dx * cb + dy * sb) * t.inv_s;  // along-ray, samples, from kc
+                    const float dp = cp + dy * cb - dx * sb;                  // perpendicular, grid points
+                    const int k0 = static_cast<int>(floorf(tr)) - NT / 2 + 1;
+                    const float q = (tr - static_cast<float>(k0)) * t.s;    // distance to tap k0, grid points
                     float wgt = fabsf(dp) <= t.msp ? exp2f(-t.kappa * (dp * dp + q * q)) : 0.0f;
                     float r = exp2f(t.kappa * (2.0f * t.s * q - t.s * t.s));
-                    const int idx = min(max(k0 + t.back, 0), t.sw - t.nt);
-                    const float2* sv = stage + j * t.sw + idx;
-                    float px = 0.0f, py = 0.0f;
-                    for (int tap = 0; tap < t.nt; ++tap) {
-                        const float2 v = sv[tap];
-                        px = __builtin_fmaf(wgt, v.x, px);
-                        py = __builtin_fmaf(wgt, v.y, py);
-                        wgt *= r;
-                        r *= t.ratio2;
+                    const int idx = min(max(k0 + t.back, 0), t.sw - NT);
+                    const float4* sv = stage + j * t.sw + idx;
+                    float pa = 0.0f, pb = 0.0f, pc = 0.0f, pd = 0.0f;
+#pragma unroll
+                    for (int tap = 0; tap < NT; ++tap) {
+                        const float4 v = sv[tap];
+                        pa = __builtin_fmaf(wgt, v.x, pa);
+                        pb = __builtin_fmaf(wgt, v.y, pb);
+                        pc = __builtin_fmaf(wgt, v.z, pc);
+                        pd = __builtin_fmaf(wgt, v.w, pd);
+                        if (tap + 1 < NT) {
+                            wgt *= r;
+                            r *= t.ratio2;
+                        }
                     }
-                    ax += static_cast<double>(px);
-                    ay += static_cast<double>(py);
+                    ax += static_cast<double>(pa);
+                    ay += static_cast<double>(pb);
+                    bx += static_cast<double>(pc);
+                    by += static_cast<double>(pd);
                 }
             }
         }
     }
-    const int gx = (ux0 + ox + M) & (M - 1), gy = (uy0 + oy + M) & (M - 1);
-    grid[(static_cast<int64_t>(p) * M + gx) * M + gy] = make_float2(static_cast<float>(ax), static_cast<float>(ay));
+    const int ux = ux0 + ox, uy = uy0 + oy;
+    if (nyq) {
+        if (uy == -hM) grid[(static_cast<int64_t>(p) * M + (ux & (M - 1))) * M + (uy & (M - 1))] =
+            make_float2(static_cast<float>(ax), static_cast<float>(ay));
+        return;
+    }
+    grid[(static_cast<int64_t>(p) * M + (ux & (M - 1))) * M + (uy & (M - 1))] =
+        make_float2(static_cast<float>(ax), static_cast<float>(ay));
+    if (uy > 0)  // the row uy = 0 is its own mirror
+        grid[(static_cast<int64_t>(p) * M + ((-ux) & (M - 1))) * M + ((-uy) & (M - 1))] =
+            make_float2(static_cast<float>(bx), static_cast<float>(by));
 }
 
 // ---------------------------------------------------------------------------
@@ -303,6 +323,16 @@ k_fr_cols(const float2* __restrict__ cols, const float2* __restrict__ tw, Fourie
     }
 }
 
+template <int NT>
+hipError_t launch_grid_nt(const FourierTables& t, const float2* spec, int pairs, float2* grid, hipStream_t st) {
+    const size_t lds = static_cast<size_t>(kFrBatch) * t.sw * sizeof(float4);
+    hipError_t e = fr_lds(k_fr_grid<NT>, lds);
+    if (e != hipSuccess) return e;
+    const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * t.ntiles));
+    hipLaunchKernelGGL((k_fr_grid<NT>), g, dim3(256), lds, st, t, spec, grid);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_fourier_spectra(const RawInput& in, int rows, const float* dmean, const float* rden,
@@ -316,13 +346,23 @@ hipError_t launch_fourier_spectra(const RawInput& in, int rows, const float* dme
     return hipGetLastError();
 }
 
+size_t fourier_grid_tiles(int M) {
+    const size_t tps = static_cast<size_t>(M) / kFrTile;
+    return tps * (tps / 2) + tps;  // rows with uy >= 0, plus the row holding uy = -M/2
+}
+
 hipError_t launch_fourier_grid(const FourierTables& t, const float2* spec, int pairs, float2* grid, hipStream_t st) {
-    const size_t lds = static_cast<size_t>(kFrBatch) * t.sw * sizeof(float2);
-    hipError_t e = fr_lds(k_fr_grid, lds);
-    if (e != hipSuccess) return e;
-    const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * t.ntiles));
-    hipLaunchKernelGGL(k_fr_grid, g, dim3(256), lds, st, t, spec, grid);
-    return hipGetLastError();
+    switch (t.nt) {
+        case 2: return launch_grid_nt<2>(t, spec, pairs, grid, st);
+        case 4: return launch_grid_nt<4>(t, spec, pairs, grid, st);
+        case 6: return launch_grid_nt<6>(t, spec, pairs, grid, st);
+        case 8: return launch_grid_nt<8>(t, spec, pairs, grid, st);
+        case 10: return launch_grid_nt<10>(t, spec, pairs, grid, st);
+        case 12: return launch_grid_nt<12>(t, spec, pairs, grid, st);
+        case 14: return launch_grid_nt<14>(t, spec, pairs, grid, st);
+        case 16: return launch_grid_nt<16>(t, spec, pairs, grid, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const float2* grid, int pairs,

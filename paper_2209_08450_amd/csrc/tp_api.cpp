@@ -344,17 +344,23 @@ tp_status fourier_tables(const tp_plan* plan, tp_filter_kind kind, int msp, tp::
         bf[j] = static_cast<float>(beta[a]);
         slot[a] = 2 * j + rev[a];
     }
-    // 16x16 tiles of the grid, nearest the origin first (their angle lists are the longest)
-    const int tps = M / 16, ntiles = tps * tps;
-    std::vector<int> tiles(ntiles);
-    std::vector<double> dist(ntiles);
-    for (int i = 0; i < ntiles; ++i) {
-        const double cx = (i % tps) * 16 - M / 2 + 7.5, cy = (i / tps) * 16 - M / 2 + 7.5;
-        dist[i] = cx * cx + cy * cy;
-        tiles[i] = i;
+    // The gather's 16x16 work tiles: the tile rows with uy >= 0 (each also
+    // produces the mirror points -u) and tile row 0 (for the grid row
+    // uy = -M/2), nearest the origin first: their angle lists are the longest.
+    const int tps = M / 16;
+    std::vector<int> tiles;
+    tiles.reserve(tp::fourier_grid_tiles(M));
+    for (int ty = 0; ty < tps; ++ty) {
+        if (ty != 0 && ty < tps / 2) continue;
+        for (int tx = 0; tx < tps; ++tx) tiles.push_back(ty * tps + tx);
     }
+    const int ntiles = static_cast<int>(tiles.size());
+    auto dist = [&](int i) {
+        const double cx = (i % tps) * 16 - M / 2 + 7.5, cy = (i / tps) * 16 - M / 2 + 7.5;
+        return cx * cx + cy * cy;
+    };
     std::sort(tiles.begin(), tiles.end(),
-              [&](int p, int q) { return dist[p] < dist[q] || (dist[p] == dist[q] && p < q); });
+              [&](int p, int q) { return dist(p) < dist(q) || (dist(p) == dist(q) && p < q); });
 
     const size_t sE = align256(sizeof(float2) * E.size()), sD = align256(sizeof(float) * N);
     const size_t sd = align256(sizeof(double) * na), sf = align256(sizeof(float) * na);
@@ -844,7 +850,7 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj,
                     fr_workspace(plan, n_rows, 1));
     int64_t P = static_cast<int64_t>((workspace_bytes - df) / (std::max(d.spec_pair, d.cols_pair) + d.grid_pair));
     P = std::min<int64_t>(std::max<int64_t>(P, 1), pairs);
-    const int64_t ntiles = static_cast<int64_t>(d.M / 16) * (d.M / 16);
+    const int64_t ntiles = static_cast<int64_t>(tp::fourier_grid_tiles(d.M));
     P = std::min<int64_t>(P, 0x7fffffffLL / std::max<int64_t>({ntiles, plan->na, d.M}));
     while (P > 1 && fr_workspace(plan, n_rows, P) > workspace_bytes) --P;
     if (P < 1) return fail(TP_EINVAL, "grid too large for one launch");

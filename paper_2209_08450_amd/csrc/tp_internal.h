@@ -66,7 +66,7 @@ struct FourierTables {
     const float* sb;
     const float* beta;      // [na]    sorted reduced angles in [0, pi), FP32
     const int* slot;        // [na]    angle a -> 2 * (sorted position) + (direction reversed)
-    const int* tile_order;  // [ntiles] 16x16 grid tiles, nearest the origin first
+    const int* tile_order;  // [ntiles] 16x16 work tiles of the gather, nearest the origin first
     int na, n, N, L, log2L, M, log2M, SL;  // SL = L + 1 samples per row
     int nt;                 // gather taps per lane along the ray
     int sw;                 // staged samples per (tile, angle)
@@ -98,6 +98,7 @@ hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float*
 
 hipError_t launch_fourier_spectra(const RawInput& in, int rows, const float* dmean, const float* rden,
                                   const float2* tw_L, const FourierTables& t, float2* spec, hipStream_t st);
+size_t fourier_grid_tiles(int M);  // work-groups per pair of the gather
 hipError_t launch_fourier_grid(const FourierTables& t, const float2* spec, int pairs, float2* grid, hipStream_t st);
 hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const float2* grid, int pairs,
                                float2* cols, hipStream_t st);
