@@ -76,6 +76,14 @@ def parse():
     ap.add_argument("--single-radon", action="store_true",
                     help="instead: one tp_radon of the differentiation workload (128 x 1024^2 x 900), then a 1 GiB "
                          "device copy (a short program for hardware-counter passes)")
+    ap.add_argument("--no-fourier", action="store_true",
+                    help="skip the Fourier-domain FBP section (tp_fourier_fbp_chunk on the same scan)")
+    ap.add_argument("--fourier-half-width", type=int, default=0, help="Gaussian truncation radius (0 = 6)")
+    ap.add_argument("--fourier-slices", type=int, default=3, help="slices checked against the oracle's direct sum")
+    ap.add_argument("--fourier-points", type=int, default=96, help="sampled voxels per checked slice")
+    ap.add_argument("--single-fourier", action="store_true",
+                    help="instead: one tp_fourier_fbp_chunk of the timed chunk shape, then a 1 GiB device copy "
+                         "(a short program for hardware-counter passes)")
     ap.add_argument("--single-launch", action="store_true",
                     help="instead: one tp_fbp_chunk of the timed launch shape, then a 1 GiB device copy "
                          "(a short program for hardware-counter runs; the copy calibrates the byte counters)")
@@ -118,6 +126,8 @@ def main():
         return main_single_launch(args)
     if args.single_radon:
         return main_single_radon(args)
+    if args.single_fourier:
+        return main_single_fourier(args)
 
     import numpy as np
     import torch
@@ -272,6 +282,11 @@ def main():
                          f"normalise, filter, backproject in FP64), {cpu_t:.1f} s",
                "s_per_volume_extrapolated": round(cpu_t / cpu_slices * rows, 1)}
 
+    # ---------------- Fourier-domain FBP on the same scan ----------------
+    fourier = None
+    if not args.no_fourier:
+        fourier = bench_fourier(args, scan, plan, vol, chunks, stream, updates, log)
+
     # ---------------- differentiation form: forward projector and least squares ----------------
     ls = None
     if not args.no_ls:
@@ -314,11 +329,139 @@ def main():
                      "flop_per_launch": FLOP_PER_UPDATE * bp_updates},
         "cpu_baseline": cpu,
         "differentiation": ls,
+        "fourierrec": fourier,
         "paper_context": {"linerec_fp32_2048cubed_total_s_A100_incl_io": 80.0},
     }
     if "f16" in results and "f32" in results:
         out["speedup_f16_vs_f32"] = round(results["f32"]["s_per_volume"] / results["f16"]["s_per_volume"], 3)
     print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def fourier_flop_per_pair(n_angles: int, pad_len: int, half_width: int) -> float:
+    """Algorithmic work of the gather for one pair of slices: every polar
+    sample (n_angles x (pad_len + 1)) meets the (2 half_width)^2 grid points
+    of its truncated Gaussian (one grid point per sample along the ray at the
+    paper's sizes); per meeting 2 flop for the weight (two-ratio recurrence)
+    and 4 for the complex-by-real multiply-accumulate."""
+    return float(n_angles) * (pad_len + 1) * (2 * half_width) ** 2 * 6
+
+
+def bench_fourier(args, scan, plan, vol, chunks, stream, updates, log):
+    """Fourier-domain FBP (tp_fourier_fbp_chunk) of the resident scan in the
+    same chunks: time per volume, per-stage times, the gather's roofline and
+    parity at sampled voxels against the oracle's direct sum (which is also
+    timed on the host)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2209_08450_amd import tp
+
+    n, na, rows = plan.n_det, plan.n_angles, vol.shape[0]
+    chunk = chunks[0][1] - chunks[0][0]
+    hw = args.fourier_half_width or 6
+    plan.fourier_prepare(args.filter, hw)
+    ws = torch.empty(plan.fourier_workspace_bytes(chunk), dtype=torch.uint8, device=vol.device)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in chunks]
+    for row in evs:
+        for e in row:
+            e.record(stream)
+
+    def step(record):
+        for ci, (z0, z1) in enumerate(chunks):
+            tp.fourier_fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1],
+                                 out=vol[z0:z1], workspace=ws, events=evs[ci] if record else None, kind=args.filter,
+                                 half_width=hw)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log(f"[fourier] warmup done; timing {args.steps} steps")
+    stage = np.zeros(5)
+    grid_ms = []
+    t0 = time.perf_counter()
+    for s_i in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        for row in evs:
+            d = [row[i].elapsed_time(row[i + 1]) for i in range(5)]
+            stage += d
+            grid_ms.append(d[2])
+        log(f"[fourier] step {s_i + 1}/{args.steps} done")
+    sec = (time.perf_counter() - t0) / args.steps
+    L = tp.pad_len(n)
+    flop = fourier_flop_per_pair(na, L, hw) * ((chunk + 1) // 2)
+    achieved = flop / (np.mean(grid_ms) * 1e-3) / 1e12
+    log(f"[fourier] {sec:.3f} s per volume, gather {np.mean(grid_ms):.2f} ms per chunk "
+        f"({achieved:.1f} TFLOP/s algorithmic)")
+    # parity at sampled voxels; the same oracle evaluations time the CPU side
+    ns = min(args.fourier_slices, rows)
+    zs = [int((k + 0.5) * rows / ns) for k in range(ns)] if ns > 0 else []
+    rng = np.random.default_rng(4096)
+    errs, num, den, cpu_t, cpu_pts = [], 0.0, 0.0, 0.0, 0
+    for z in zs:
+        ix = rng.integers(0, n, args.fourier_points)
+        iy = rng.integers(0, n, args.fourier_points)
+        got = vol[z][torch.from_numpy(iy).to(vol.device), torch.from_numpy(ix).to(vol.device)].cpu().numpy()
+        p = scan.proj[:, z, :].cpu().numpy().view(np.uint16)
+        d = scan.dark[:, z, :].cpu().numpy().view(np.uint16)
+        f = scan.flat[:, z, :].cpu().numpy().view(np.uint16)
+        log(f"[fourier] oracle direct sum at {args.fourier_points} voxels of slice {z}")
+        t1 = time.perf_counter()
+        want = oracle.fourier_fbp_points(p, d, f, scan.angles, plan.center, n, ix, iy, kind=args.filter)
+        cpu_t += time.perf_counter() - t1
+        cpu_pts += len(ix)
+        e = got.astype(np.float64) - want
+        num += float(np.sum(e ** 2))
+        den += float(np.sum(want ** 2))
+        errs.append(float(np.max(np.abs(e)) / np.max(np.abs(want))))
+    rel = math.sqrt(num / den) if den > 0 else None
+    if rel is not None:
+        log(f"[fourier] rel-L2 vs FP64 direct sum at sampled voxels: {rel:.3e}")
+    return {
+        "method": "Fourier-domain backprojection: polar spectra, Gaussian gather onto a 2x oversampled grid, "
+                  "2-D inverse FFT, deconvolution",
+        "half_width": hw,
+        "s_per_volume": round(sec, 4),
+        "gups_equivalent": round(updates / sec / 1e9, 2),
+        "stage_ms_per_step": {k: round(v / args.steps, 2) for k, v in
+                              zip(("darkflat", "spectra", "grid", "ifft_rows", "ifft_cols"), stage)},
+        "rel_l2_vs_fp64_direct_sum_sampled": rel,
+        "max_abs_over_max_ref_per_slice": errs,
+        "parity_sample": f"{args.fourier_points} voxels of each of slices {zs}",
+        "roofline_gather": {"bound": "alu", "kernel": "k_fr_grid", "achieved": round(achieved, 2),
+                            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                            "launch_ms": round(float(np.mean(grid_ms)), 3), "flop_per_launch": flop},
+        "cpu_oracle": {"value": round(cpu_pts * na / cpu_t / 1e9, 6) if cpu_t > 0 else None,
+                       "unit": "Gvoxel-angle updates/s", "cores": oracle.num_threads(),
+                       "sample": f"direct sum at {cpu_pts} voxels ({L + 1} terms per voxel-angle), {cpu_t:.1f} s"},
+    }
+
+
+def main_single_fourier(args):
+    """One tp_fourier_fbp_chunk of the timed chunk shape, then a 1 GiB device copy (counter calibration)."""
+    import torch
+
+    from paper_2209_08450_amd import synth, tp
+
+    dev = torch.device("cuda:0")
+    n, na, rows = args.n, args.angles, args.chunk
+    scan = synth.ellipsoid_scan_torch(seed=2, n_angles=na, n_rows=rows, n_det=n, device=dev, center=n / 2.0)
+    plan = tp.Plan(scan.angles, n, n / 2.0)
+    hw = args.fourier_half_width or 6
+    plan.fourier_prepare(args.filter, hw)
+    ws = torch.empty(plan.fourier_workspace_bytes(rows), dtype=torch.uint8, device=dev)
+    vol = torch.empty((rows, n, n), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    tp.fourier_fbp_chunk(plan, scan.proj, scan.dark, scan.flat, out=vol, workspace=ws, kind=args.filter,
+                         half_width=hw)
+    torch.cuda.synchronize()
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"single Fourier chunk {na} x {rows} x {n} done")
     plan.close()
 
 

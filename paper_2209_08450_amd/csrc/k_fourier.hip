@@ -323,6 +323,118 @@ k_fr_cols(const float2* __restrict__ cols, const float2* __restrict__ tw, Fourie
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variants of the three transform kernels for lengths
+// 1024..8192: thread t holds elements t + B s (B = length / 16) and the
+// radix-16 passes exchange only their outputs through LDS; after the last
+// pass slot s holds output index t + B s in natural order.
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ void __launch_bounds__(L / kRegPts)
+k_fr_spectra_reg(RawInput in, int rows, const float* __restrict__ dmean, const float* __restrict__ rden,
+                 const float2* __restrict__ tw, FourierTables t, float2* __restrict__ spec) {
+    extern __shared__ float2 lds[];
+    constexpr int B = L / kRegPts, h = L / 2;
+    const int tid = threadIdx.x;
+    const int n = t.n, off = (L - n) / 2;
+    const int p = blockIdx.x / t.na;
+    const int a = blockIdx.x - p * t.na;
+    const int z0 = 2 * p;
+    const bool has1 = z0 + 1 < rows;
+    const uint16_t* p0 = in.proj + a * in.proj_stride + static_cast<int64_t>(z0) * n;
+    const uint16_t* p1 = has1 ? p0 + n : p0;
+    const float* d0 = dmean + static_cast<int64_t>(z0) * n;
+    const float* e0 = rden + static_cast<int64_t>(z0) * n;
+    const float* d1 = has1 ? d0 + n : d0;
+    const float* e1 = has1 ? e0 + n : e0;
+    float2 x[kRegPts];
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int c = min(max(tid + B * s - off, 0), n - 1);
+        const float v0 = neglog_counts(static_cast<float>(p0[c]), d0[c], e0[c]);
+        const float v1 = has1 ? neglog_counts(static_cast<float>(p1[c]), d1[c], e1[c]) : 0.0f;
+        x[s] = make_float2(v0, v1);
+    }
+    reg_fft<L>(x, lds, tw, tid);
+    const int sl = t.slot[a];
+    const bool rev = (sl & 1) != 0;
+    float2* row = spec + (static_cast<int64_t>(p) * t.na + (sl >> 1)) * t.SL;
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int m = tid + B * s;
+        const int k = m < h ? m : m - L;
+        row[(rev ? -k : k) + h] = cmul(x[s], t.E[k + h]);
+        if (m == h) row[(rev ? -h : h) + h] = cmul(x[s], t.E[L]);
+    }
+}
+
+template <int M>
+__global__ void __launch_bounds__(M / kRegPts)
+k_fr_rows_reg(const float2* __restrict__ grid, const float2* __restrict__ tw, FourierTables t,
+              float2* __restrict__ cols) {
+    extern __shared__ float2 lds[];
+    constexpr int B = M / kRegPts;
+    const int tid = threadIdx.x;
+    const int N = t.N, hN = N / 2;
+    const int64_t rid = blockIdx.x;
+    const int p = static_cast<int>(rid / M);
+    const int ux = static_cast<int>(rid - static_cast<int64_t>(p) * M);
+    const float2* g = grid + rid * M;
+    float2 x[kRegPts];
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) x[s] = cconj(g[tid + B * s]);
+    reg_fft<M>(x, lds, tw, tid);
+    const int ng = (N + 15) / 16;
+    float2* cp = cols + static_cast<int64_t>(p) * ng * M * 16;
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int m = tid + B * s;
+        const int y = m < M / 2 ? m : m - M;
+        const int iy = y + hN;
+        if (iy >= 0 && iy < N) cp[(static_cast<int64_t>(iy >> 4) * M + ux) * 16 + (iy & 15)] = cconj(x[s]);
+    }
+}
+
+template <int M>
+__global__ void __launch_bounds__(M / kRegPts)
+k_fr_cols_reg(const float2* __restrict__ cols, const float2* __restrict__ tw, FourierTables t, int pairs, int rows,
+              float* __restrict__ vol) {
+    extern __shared__ float2 lds[];
+    constexpr int B = M / kRegPts;
+    const int tid = threadIdx.x;
+    const int N = t.N, hN = N / 2;
+    const int ng = (N + 15) / 16;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, r = b >> 3;
+    const int gidx = (r >> 4) * 8 + xcd;
+    const int p = gidx / ng, gi = gidx - p * ng;
+    const int iy = gi * 16 + (r & 15);
+    if (p >= pairs || iy >= N) return;  // whole work-group
+    const float2* src = cols + (static_cast<int64_t>(p) * ng + gi) * M * 16 + (iy & 15);
+    float2 x[kRegPts];
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) x[s] = cconj(src[static_cast<int64_t>(tid + B * s) * 16]);
+    reg_fft<M>(x, lds, tw, tid);
+    const float fy = t.D[iy];
+    const int z0 = 2 * p;
+    const bool has1 = z0 + 1 < rows;
+    float* o0 = vol + (static_cast<int64_t>(z0) * N + iy) * N;
+    float* o1 = o0 + static_cast<int64_t>(N) * N;
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int m = tid + B * s;
+        const int x0 = m < M / 2 ? m : m - M;
+        const int ix = x0 + hN;
+        if (ix >= 0 && ix < N) {
+            const float f = t.D[ix] * fy;
+            o0[ix] = x[s].x * f;
+            if (has1) o1[ix] = (0.0f - x[s].y) * f;
+        }
+    }
+}
+
+size_t reg_lds(int L) { return static_cast<size_t>(L + L / 16) * sizeof(float2); }
+
 template <int NT>
 hipError_t launch_grid_nt(const FourierTables& t, const float2* spec, int pairs, float2* grid, hipStream_t st) {
     const size_t lds = static_cast<size_t>(kFrBatch) * t.sw * sizeof(float4);
@@ -338,6 +450,23 @@ hipError_t launch_grid_nt(const FourierTables& t, const float2* spec, int pairs,
 hipError_t launch_fourier_spectra(const RawInput& in, int rows, const float* dmean, const float* rden,
                                   const float2* tw_L, const FourierTables& t, float2* spec, hipStream_t st) {
     const int pairs = (rows + 1) / 2;
+#define TP_FR_REG(LL)                                                                                      \
+    case LL: {                                                                                            \
+        const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * t.na));                          \
+        const hipError_t e = fr_lds(k_fr_spectra_reg<LL>, reg_lds(LL));                                   \
+        if (e != hipSuccess) return e;                                                                    \
+        hipLaunchKernelGGL((k_fr_spectra_reg<LL>), g, dim3(LL / kRegPts), reg_lds(LL), st, in, rows, dmean, rden, \
+                           tw_L, t, spec);                                                               \
+        return hipGetLastError();                                                                         \
+    }
+    switch (t.L) {
+        TP_FR_REG(1024)
+        TP_FR_REG(2048)
+        TP_FR_REG(4096)
+        TP_FR_REG(8192)
+        default: break;
+    }
+#undef TP_FR_REG
     const size_t lds = static_cast<size_t>(t.L) * sizeof(float2);
     hipError_t e = fr_lds(k_fr_spectra, lds);
     if (e != hipSuccess) return e;
@@ -367,6 +496,22 @@ hipError_t launch_fourier_grid(const FourierTables& t, const float2* spec, int p
 
 hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const float2* grid, int pairs,
                                float2* cols, hipStream_t st) {
+#define TP_FR_REG(MM)                                                                                      \
+    case MM: {                                                                                            \
+        const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * MM));                            \
+        const hipError_t e = fr_lds(k_fr_rows_reg<MM>, reg_lds(MM));                                      \
+        if (e != hipSuccess) return e;                                                                    \
+        hipLaunchKernelGGL((k_fr_rows_reg<MM>), g, dim3(MM / kRegPts), reg_lds(MM), st, grid, tw_M, t, cols); \
+        return hipGetLastError();                                                                         \
+    }
+    switch (t.M) {
+        TP_FR_REG(1024)
+        TP_FR_REG(2048)
+        TP_FR_REG(4096)
+        TP_FR_REG(8192)
+        default: break;
+    }
+#undef TP_FR_REG
     const size_t lds = static_cast<size_t>(t.M) * sizeof(float2);
     hipError_t e = fr_lds(k_fr_rows, lds);
     if (e != hipSuccess) return e;
@@ -377,11 +522,27 @@ hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const
 
 hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
                                float* vol, hipStream_t st) {
+    const int64_t groups = static_cast<int64_t>(pairs) * ((t.N + 15) / 16);
+    const dim3 g(static_cast<unsigned>(((groups + 7) / 8) * 8 * 16));
+#define TP_FR_REG(MM)                                                                                      \
+    case MM: {                                                                                            \
+        const hipError_t e = fr_lds(k_fr_cols_reg<MM>, reg_lds(MM));                                      \
+        if (e != hipSuccess) return e;                                                                    \
+        hipLaunchKernelGGL((k_fr_cols_reg<MM>), g, dim3(MM / kRegPts), reg_lds(MM), st, cols, tw_M, t, pairs, \
+                           rows, vol);                                                                    \
+        return hipGetLastError();                                                                         \
+    }
+    switch (t.M) {
+        TP_FR_REG(1024)
+        TP_FR_REG(2048)
+        TP_FR_REG(4096)
+        TP_FR_REG(8192)
+        default: break;
+    }
+#undef TP_FR_REG
     const size_t lds = static_cast<size_t>(t.M) * sizeof(float2);
     hipError_t e = fr_lds(k_fr_cols, lds);
     if (e != hipSuccess) return e;
-    const int64_t groups = static_cast<int64_t>(pairs) * ((t.N + 15) / 16);
-    const dim3 g(static_cast<unsigned>(((groups + 7) / 8) * 8 * 16));
     hipLaunchKernelGGL(k_fr_cols, g, dim3(fr_block(t.M)), lds, st, cols, tw_M, t, pairs, rows, vol);
     return hipGetLastError();
 }

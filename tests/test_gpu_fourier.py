@@ -138,6 +138,26 @@ def test_fourier_paper_geometry_sampled(tp):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n", [512, 4096])
+def test_fourier_register_transform_sizes(tp, n):
+    # pad length and grid side 1024 (n = 512) and 8192 (n = 4096): the
+    # register-resident transforms at their smallest and largest lengths
+    import torch
+    s = synth.phantom_2d_scan(seed=5, n_rows=2, n_angles=96, n_det=n, center=n / 2 - 0.25)
+    note(f"fourier 96 angles x 2 rows x {n}")
+    got = _run(tp, s)
+    rng = np.random.default_rng(13)
+    ix = rng.integers(0, n, 48)
+    iy = rng.integers(0, n, 48)
+    errs = []
+    for i in range(2):
+        want = oracle.fourier_fbp_points(s.proj[:, i], s.dark[:, i], s.flat[:, i], s.angles, s.center, n, ix, iy)
+        errs.append(rel_l2(got[i, iy, ix], want))
+    note(f"rel-L2 at sampled voxels {errs}")
+    assert max(errs) < 1e-5, errs
+    torch.cuda.empty_cache()
+
+
 def test_fourier_close_to_linear_interpolation_fbp(tp, scan64):
     # sanity: the two interpolations differ by the linear interpolation's
     # smoothing only
