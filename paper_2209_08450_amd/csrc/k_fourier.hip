@@ -26,7 +26,7 @@
 //   k_fr_grid     for every grid point, sum the Gaussian-weighted samples of
 //                 every angle whose ray passes within the truncation radius
 //                 (a gather: no atomics, a fixed summation order; FP64
-//                 accumulation over angles);
+//                 accumulation over batches of 16 angles);
 //   k_fr_rows     inverse FFT along the grid's fast axis, keeping the N
 //                 output rows, stored in 16-wide column groups;
 //   k_fr_cols     inverse FFT along the other axis, deconvolution, split of
@@ -154,8 +154,8 @@ k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__
     const float2* sp = spec + static_cast<int64_t>(p) * t.na * t.SL;
     const int h = t.L / 2;
     const float reach = t.msp + kFrHalfDiag + 1.0f;
-    // each angle's taps are summed in FP32, the angles in FP64: central grid
-    // points collect thousands of angles
+    // each batch of angles is summed in FP32, the batches in FP64: central
+    // grid points collect thousands of angles
     double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
     for (int img = 0; img < 9; ++img) {
         const float Cx = static_cast<float>(ux0 + (img % 3 - 1) * M) + 7.5f;
@@ -198,15 +198,20 @@ k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__
                                                      static_cast<float>(Cyd * cbd - Cxd * sbd), t.cb[ap], t.sb[ap]);
                 }
                 __syncthreads();
-                for (int i = threadIdx.x; i < cnt * t.sw; i += blockDim.x) {
-                    const int j = i / t.sw;
-                    const int k = s_kc[j] - t.back + (i - j * t.sw);  // signed frequency index
-                    const float2* row = sp + static_cast<int64_t>(a0 + j) * t.SL + h;
-                    const float2 v = (k >= -h && k <= h) ? row[k] : make_float2(0.0f, 0.0f);
-                    const float2 u = (k >= -h && k <= h) ? row[-k] : make_float2(0.0f, 0.0f);
-                    stage[i] = make_float4(v.x, v.y, u.x, u.y);
+                // wave w stages angles w, w + 4, ...; lane l the window's sample l (sw <= 64)
+                for (int j = w; j < cnt; j += 4) {
+                    if (l < t.sw) {
+                        const int k = s_kc[j] - t.back + l;  // signed frequency index
+                        const float2* row = sp + static_cast<int64_t>(a0 + j) * t.SL + h;
+                        const bool in = k >= -h && k <= h;
+                        const float2 v = in ? row[k] : make_float2(0.0f, 0.0f);
+                        const float2 u = in ? row[-k] : make_float2(0.0f, 0.0f);
+                        stage[j * t.sw + l] = make_float4(v.x, v.y, u.x, u.y);
+                    }
                 }
                 __syncthreads();
+                // FP32 partial sums over the batch (at most 16 angles x NT taps)
+                float pa = 0.0f, pb = 0.0f, pc = 0.0f, pd = 0.0f;
                 for (int j = 0; j < cnt; ++j) {
                     const float4 geo = s_geo[j];
                     const float cb = geo.z, sb = geo.w, cp = geo.y;
@@ -214,13 +219,15 @@ k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__
                     if (fabsf(cp + wdy * cb - wdx * sb) > t.msp + kFrWaveHalfDiag + 0.01f) continue;
                     const float tr = geo.x + (dx * cb + dy * sb) * t.inv_s;  // along-ray, samples, from kc
                     const float dp = cp + dy * cb - dx * sb;                  // perpendicular, grid points
-                    const int k0 = static_cast<int>(floorf(tr)) - NT / 2 + 1;
+                    if (fabsf(dp) > t.msp) continue;  // outside the band: no LDS reads for this lane
+                    const int k0 = coord_floor(tr) - NT / 2 + 1;
                     const float q = (tr - static_cast<float>(k0)) * t.s;    // distance to tap k0, grid points
-                    float wgt = fabsf(dp) <= t.msp ? exp2f(-t.kappa * (dp * dp + q * q)) : 0.0f;
-                    float r = exp2f(t.kappa * (2.0f * t.s * q - t.s * t.s));
+                    // for grid spacings s <= 8 and half widths 3..8 the exponents stay within
+                    // (-80, 70): the hardware exp2 needs no range handling
+                    float wgt = __builtin_amdgcn_exp2f(-t.kappa * (dp * dp + q * q));
+                    float r = __builtin_amdgcn_exp2f(t.kappa * (2.0f * t.s * q - t.s * t.s));
                     const int idx = min(max(k0 + t.back, 0), t.sw - NT);
                     const float4* sv = stage + j * t.sw + idx;
-                    float pa = 0.0f, pb = 0.0f, pc = 0.0f, pd = 0.0f;
 #pragma unroll
                     for (int tap = 0; tap < NT; ++tap) {
                         const float4 v = sv[tap];
@@ -233,11 +240,11 @@ k_fr_grid(FourierTables t, const float2* __restrict__ spec, float2* __restrict__
                             r *= t.ratio2;
                         }
                     }
-                    ax += static_cast<double>(pa);
-                    ay += static_cast<double>(pb);
-                    bx += static_cast<double>(pc);
-                    by += static_cast<double>(pd);
                 }
+                ax += static_cast<double>(pa);
+                ay += static_cast<double>(pb);
+                bx += static_cast<double>(pc);
+                by += static_cast<double>(pd);
             }
         }
     }
@@ -329,42 +336,66 @@ k_fr_cols(const float2* __restrict__ cols, const float2* __restrict__ tw, Fourie
 // radix-16 passes exchange only their outputs through LDS; after the last
 // pass slot s holds output index t + B s in natural order.
 // ---------------------------------------------------------------------------
+// Angles per work-group of the register spectra kernel: each angle's raw
+// counts are prefetched while the previous angle is transformed.
+constexpr int kFrAnglesPerGroup = 8;
+
 template <int L>
 __global__ void __launch_bounds__(L / kRegPts)
 k_fr_spectra_reg(RawInput in, int rows, const float* __restrict__ dmean, const float* __restrict__ rden,
                  const float2* __restrict__ tw, FourierTables t, float2* __restrict__ spec) {
     extern __shared__ float2 lds[];
     constexpr int B = L / kRegPts, h = L / 2;
-    const int tid = threadIdx.x;
     const int n = t.n, off = (L - n) / 2;
-    const int p = blockIdx.x / t.na;
-    const int a = blockIdx.x - p * t.na;
+    const int groups = (t.na + kFrAnglesPerGroup - 1) / kFrAnglesPerGroup;
+    const int p = blockIdx.x / groups;
+    const int a0 = (blockIdx.x - p * groups) * kFrAnglesPerGroup;
+    const int a1 = min(t.na, a0 + kFrAnglesPerGroup);
     const int z0 = 2 * p;
     const bool has1 = z0 + 1 < rows;
-    const uint16_t* p0 = in.proj + a * in.proj_stride + static_cast<int64_t>(z0) * n;
-    const uint16_t* p1 = has1 ? p0 + n : p0;
-    const float* d0 = dmean + static_cast<int64_t>(z0) * n;
-    const float* e0 = rden + static_cast<int64_t>(z0) * n;
-    const float* d1 = has1 ? d0 + n : d0;
-    const float* e1 = has1 ? e0 + n : e0;
-    float2 x[kRegPts];
+    const int64_t r0 = static_cast<int64_t>(z0) * n;
+    const int64_t r1 = has1 ? r0 + n : r0;
+    // slot s holds padded position t + B s; the column clamped onto the
+    // detector gives the edge-replicated padding
+    auto load_raw = [&](int a, int tid, uint32_t (&raw)[kRegPts]) {
+        const uint16_t* q0 = in.proj + a * in.proj_stride + r0;
+        const uint16_t* q1 = in.proj + a * in.proj_stride + r1;
 #pragma unroll
-    for (int s = 0; s < kRegPts; ++s) {
-        const int c = min(max(tid + B * s - off, 0), n - 1);
-        const float v0 = neglog_counts(static_cast<float>(p0[c]), d0[c], e0[c]);
-        const float v1 = has1 ? neglog_counts(static_cast<float>(p1[c]), d1[c], e1[c]) : 0.0f;
-        x[s] = make_float2(v0, v1);
-    }
-    reg_fft<L>(x, lds, tw, tid);
-    const int sl = t.slot[a];
-    const bool rev = (sl & 1) != 0;
-    float2* row = spec + (static_cast<int64_t>(p) * t.na + (sl >> 1)) * t.SL;
+        for (int s = 0; s < kRegPts; ++s) {
+            const int c = min(max(tid + B * s - off, 0), n - 1);
+            raw[s] = static_cast<uint32_t>(q0[c]) | (static_cast<uint32_t>(q1[c]) << 16);
+        }
+    };
+    uint32_t cur[kRegPts], nxt[kRegPts];
+    load_raw(a0, threadIdx.x, cur);
+#pragma unroll 1
+    for (int a = a0; a < a1; ++a) {
+        // an opaque thread index per angle keeps per-thread offsets from being
+        // hoisted into registers held across the loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        if (a + 1 < a1) load_raw(a + 1, tid, nxt);
+        float2 x[kRegPts];
 #pragma unroll
-    for (int s = 0; s < kRegPts; ++s) {
-        const int m = tid + B * s;
-        const int k = m < h ? m : m - L;
-        row[(rev ? -k : k) + h] = cmul(x[s], t.E[k + h]);
-        if (m == h) row[(rev ? -h : h) + h] = cmul(x[s], t.E[L]);
+        for (int s = 0; s < kRegPts; ++s) {
+            const int c = min(max(tid + B * s - off, 0), n - 1);
+            x[s] = make_float2(neglog_counts(static_cast<float>(cur[s] & 0xffffu), dmean[r0 + c], rden[r0 + c]),
+                               has1 ? neglog_counts(static_cast<float>(cur[s] >> 16), dmean[r1 + c], rden[r1 + c])
+                                    : 0.0f);
+        }
+        reg_fft<L>(x, lds, tw, tid);
+        const int sl = t.slot[a];
+        const bool rev = (sl & 1) != 0;
+        float2* row = spec + (static_cast<int64_t>(p) * t.na + (sl >> 1)) * t.SL;
+#pragma unroll
+        for (int s = 0; s < kRegPts; ++s) {
+            const int m = tid + B * s;
+            const int k = m < h ? m : m - L;
+            row[(rev ? -k : k) + h] = cmul(x[s], t.E[k + h]);
+            if (m == h) row[(rev ? -h : h) + h] = cmul(x[s], t.E[L]);
+        }
+#pragma unroll
+        for (int s = 0; s < kRegPts; ++s) cur[s] = nxt[s];
     }
 }
 
@@ -399,6 +430,7 @@ template <int M>
 __global__ void __launch_bounds__(M / kRegPts)
 k_fr_cols_reg(const float2* __restrict__ cols, const float2* __restrict__ tw, FourierTables t, int pairs, int rows,
               float* __restrict__ vol) {
+    // two neighbouring image rows (iy, iy + 1) per work-group: 16-byte loads
     extern __shared__ float2 lds[];
     constexpr int B = M / kRegPts;
     const int tid = threadIdx.x;
@@ -406,31 +438,40 @@ k_fr_cols_reg(const float2* __restrict__ cols, const float2* __restrict__ tw, Fo
     const int ng = (N + 15) / 16;
     const int b = blockIdx.x;
     const int xcd = b & 7, r = b >> 3;
-    const int gidx = (r >> 4) * 8 + xcd;
+    const int gidx = (r >> 3) * 8 + xcd;
     const int p = gidx / ng, gi = gidx - p * ng;
-    const int iy = gi * 16 + (r & 15);
+    const int iy = gi * 16 + 2 * (r & 7);
     if (p >= pairs || iy >= N) return;  // whole work-group
-    const float2* src = cols + (static_cast<int64_t>(p) * ng + gi) * M * 16 + (iy & 15);
-    float2 x[kRegPts];
+    const float4* src = reinterpret_cast<const float4*>(cols + (static_cast<int64_t>(p) * ng + gi) * M * 16 + (iy & 15));
+    float2 x[kRegPts], y[kRegPts];
 #pragma unroll
-    for (int s = 0; s < kRegPts; ++s) x[s] = cconj(src[static_cast<int64_t>(tid + B * s) * 16]);
-    reg_fft<M>(x, lds, tw, tid);
-    const float fy = t.D[iy];
+    for (int s = 0; s < kRegPts; ++s) {
+        const float4 v = src[static_cast<int64_t>(tid + B * s) * 8];
+        x[s] = make_float2(v.x, 0.0f - v.y);
+        y[s] = make_float2(v.z, 0.0f - v.w);
+    }
     const int z0 = 2 * p;
     const bool has1 = z0 + 1 < rows;
     float* o0 = vol + (static_cast<int64_t>(z0) * N + iy) * N;
     float* o1 = o0 + static_cast<int64_t>(N) * N;
+    // each row is transformed and stored before the next one is transformed
+    auto finish = [&](float2 (&v)[kRegPts], int row) {
+        reg_fft<M>(v, lds, tw, tid);
+        const float fy = t.D[iy + row];
 #pragma unroll
-    for (int s = 0; s < kRegPts; ++s) {
-        const int m = tid + B * s;
-        const int x0 = m < M / 2 ? m : m - M;
-        const int ix = x0 + hN;
-        if (ix >= 0 && ix < N) {
-            const float f = t.D[ix] * fy;
-            o0[ix] = x[s].x * f;
-            if (has1) o1[ix] = (0.0f - x[s].y) * f;
+        for (int s = 0; s < kRegPts; ++s) {
+            const int m = tid + B * s;
+            const int x0 = m < M / 2 ? m : m - M;
+            const int ix = x0 + hN;
+            if (ix >= 0 && ix < N) {
+                const float f = t.D[ix] * fy;
+                o0[row * N + ix] = v[s].x * f;
+                if (has1) o1[row * N + ix] = (0.0f - v[s].y) * f;
+            }
         }
-    }
+    };
+    finish(x, 0);
+    if (iy + 1 < N) finish(y, 1);
 }
 
 size_t reg_lds(int L) { return static_cast<size_t>(L + L / 16) * sizeof(float2); }
@@ -452,7 +493,8 @@ hipError_t launch_fourier_spectra(const RawInput& in, int rows, const float* dme
     const int pairs = (rows + 1) / 2;
 #define TP_FR_REG(LL)                                                                                      \
     case LL: {                                                                                            \
-        const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * t.na));                          \
+        const int64_t ag = (t.na + kFrAnglesPerGroup - 1) / kFrAnglesPerGroup;                             \
+        const dim3 g(static_cast<unsigned>(static_cast<int64_t>(pairs) * ag));                            \
         const hipError_t e = fr_lds(k_fr_spectra_reg<LL>, reg_lds(LL));                                   \
         if (e != hipSuccess) return e;                                                                    \
         hipLaunchKernelGGL((k_fr_spectra_reg<LL>), g, dim3(LL / kRegPts), reg_lds(LL), st, in, rows, dmean, rden, \
@@ -524,11 +566,12 @@ hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const
                                float* vol, hipStream_t st) {
     const int64_t groups = static_cast<int64_t>(pairs) * ((t.N + 15) / 16);
     const dim3 g(static_cast<unsigned>(((groups + 7) / 8) * 8 * 16));
+    const dim3 g2(static_cast<unsigned>(((groups + 7) / 8) * 8 * 8));  // two rows per work-group
 #define TP_FR_REG(MM)                                                                                      \
     case MM: {                                                                                            \
         const hipError_t e = fr_lds(k_fr_cols_reg<MM>, reg_lds(MM));                                      \
         if (e != hipSuccess) return e;                                                                    \
-        hipLaunchKernelGGL((k_fr_cols_reg<MM>), g, dim3(MM / kRegPts), reg_lds(MM), st, cols, tw_M, t, pairs, \
+        hipLaunchKernelGGL((k_fr_cols_reg<MM>), g2, dim3(MM / kRegPts), reg_lds(MM), st, cols, tw_M, t, pairs, \
                            rows, vol);                                                                    \
         return hipGetLastError();                                                                         \
     }

@@ -299,6 +299,9 @@ tp_status fourier_tables(const tp_plan* plan, tp_filter_kind kind, int msp, tp::
     const int nt = 2 * static_cast<int>(std::ceil(msp / s));
     const int back = static_cast<int>(std::ceil((kFrHalfDiag + 1.0) / s)) + nt / 2;
     const int sw = static_cast<int>(std::ceil(2.0 * (kFrHalfDiag + 1.0) / s)) + nt + 4;
+    if (s > 8.0 || sw > 64)
+        return fail(TP_EUNSUPPORTED, "Fourier grid of %d points per side for pad length %d (more than 8 grid "
+                    "points per frequency sample)", M, L);
     const double pos0 = plan->center + (L - n) / 2;
     // E[k + L/2] = (pi / na) / L * w_k * H[k] * exp(2 pi i k pos0 / L)
     std::vector<double> H;
