@@ -61,14 +61,23 @@ class ChunkPipeline:
     frames per chunk; storage: 'f16' / 'f32' / 'bf16' for the filtered rows;
     kind: filter window ('ramp', 'shepp', 'parzen'); use_graphs: capture each (size, buffer) once and replay it; poison: fill
     device and pinned buffers with NaN before each use (a missing dependency
-    then shows as NaN in the result).
+    then shows as NaN in the result).  method: 'linear' (tp_fbp_chunk) or
+    'fourier' (tp_fourier_fbp_chunk; storage is then unused and half_width
+    sets its Gaussian's truncation radius).
     """
 
     def __init__(self, plan: "tp.Plan", max_rows: int, n_dark: int, n_flat: int, storage="f16",
-                 use_graphs: bool = True, poison: bool = False, device=None, kind="ramp"):
+                 use_graphs: bool = True, poison: bool = False, device=None, kind="ramp", method="linear",
+                 half_width: int = 0):
         self.plan = plan
         self.kind = kind
         tp.filter_code(kind)  # reject unknown names early
+        if method not in ("linear", "fourier"):
+            raise ValueError(f"method must be 'linear' or 'fourier', not {method!r}")
+        self.method = method
+        self.half_width = int(half_width)
+        if method == "fourier":
+            plan.fourier_prepare(kind, self.half_width)  # tables before any capture
         self.device = torch.device(device or f"cuda:{torch.cuda.current_device()}")
         self.max_rows = int(max_rows)
         self.n_dark, self.n_flat = int(n_dark), int(n_flat)
@@ -93,7 +102,8 @@ class ChunkPipeline:
         self.dev_dark = [dev(self.n_dark * r * n, i16) for _ in range(2)]
         self.dev_flat = [dev(self.n_flat * r * n, i16) for _ in range(2)]
         self.dev_out = [dev(r * N * N, torch.float32) for _ in range(2)]
-        self.ws = dev(max(256, plan.fbp_workspace_bytes(r, storage)), torch.uint8)
+        ws_bytes = plan.fourier_workspace_bytes(r) if method == "fourier" else plan.fbp_workspace_bytes(r, storage)
+        self.ws = dev(max(256, ws_bytes), torch.uint8)
         # streams at default priority
         self.s_h2d = torch.cuda.Stream(device=self.device)
         self.s_comp = torch.cuda.Stream(device=self.device)
@@ -116,8 +126,12 @@ class ChunkPipeline:
         )
 
     def _compute(self, v):
-        tp.fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], self.storage, out=v["dev_out"],
-                     workspace=self.ws, kind=self.kind)
+        if self.method == "fourier":
+            tp.fourier_fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], out=v["dev_out"],
+                                 workspace=self.ws, kind=self.kind, half_width=self.half_width)
+        else:
+            tp.fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], self.storage, out=v["dev_out"],
+                         workspace=self.ws, kind=self.kind)
 
     def prepare(self, chunks):
         """Capture the graphs of every (chunk size, buffer) the run will use.

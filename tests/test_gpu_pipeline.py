@@ -69,6 +69,20 @@ def test_pipeline_parzen_bitwise_equals_monolithic(env):
     assert np.array_equal(got, want)
 
 
+def test_pipeline_fourier_bitwise_equals_monolithic(env):
+    # even chunk sizes keep the slice pairs of one monolithic call, so every
+    # pair goes through the same arithmetic
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    want = to_host(tp.fourier_fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), kind="parzen"))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, kind="parzen", method="fourier")
+    got = np.full((100, 128, 128), np.nan, np.float32)
+    note("pipeline fourier parzen graphs")
+    pl.run(pipeline.uneven_chunks(100, (32, 16)), _source(s), _sink(got))
+    assert np.array_equal(got, want)
+    assert pl.stats.graphs_captured > 0
+
+
 def test_graph_replays_repeat_with_eager_work_between(env):
     import torch
     tp, pipeline, _, s = env
