@@ -71,6 +71,9 @@ def parse():
                     help="instead: the host-to-host three-stream pipeline over uneven chunks "
                          "(defaults become 3000 angles x 2048 rows x 4096 columns, FP16 storage)")
     ap.add_argument("--pattern", default="32,64,128", help="chunk sizes of the pipeline mode")
+    ap.add_argument("--method", default="linear", choices=("linear", "fourier"),
+                    help="backprojector of the pipeline mode: linear interpolation (tp_fbp_chunk) or the "
+                         "Fourier-domain method (tp_fourier_fbp_chunk)")
     ap.add_argument("--no-ls", action="store_true",
                     help="skip the differentiation section (forward projector, adjoint, 30 LS steps)")
     ap.add_argument("--single-radon", action="store_true",
@@ -601,22 +604,34 @@ def main_pipeline(args):
     scan = synth.ellipsoid_scan_torch(seed=5, n_angles=na, n_rows=rows, n_det=n, device=dev, center=center)
     torch.cuda.synchronize()
     plan = tp.Plan(scan.angles, n, center)
-    k, a = tune.tune_backproject(plan, st, rows=16, use_cache=False)
-    log(f"autotuned backprojection ({st}): slices {k}, angles {a}")
+    fourier = args.method == "fourier"
+    if fourier:
+        plan.fourier_prepare(args.filter, 0)
+        k = a = None
+    else:
+        k, a = tune.tune_backproject(plan, st, rows=16, use_cache=False)
+        log(f"autotuned backprojection ({st}): slices {k}, angles {a}")
     chunks = pipeline.uneven_chunks(rows, pattern)
     updates = float(n) * n * na * rows
 
+    def compute(z0, z1, out, ws):
+        if fourier:
+            tp.fourier_fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], out=out,
+                                 workspace=ws, kind=args.filter)
+        else:
+            tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st, out=out,
+                         workspace=ws, kind=args.filter)
+
     # compute only, inputs resident on the device, same chunks
     vol_c = torch.empty((max(pattern), n, n), dtype=torch.float32, device=dev)
-    ws = torch.empty(plan.fbp_workspace_bytes(max(pattern), st), dtype=torch.uint8, device=dev)
+    ws_bytes = plan.fourier_workspace_bytes(max(pattern)) if fourier else plan.fbp_workspace_bytes(max(pattern), st)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     for z0, z1 in chunks[:3]:
-        tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st,
-                     out=vol_c[: z1 - z0], workspace=ws, kind=args.filter)
+        compute(z0, z1, vol_c[: z1 - z0], ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for z0, z1 in chunks:
-        tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st,
-                     out=vol_c[: z1 - z0], workspace=ws, kind=args.filter)
+        compute(z0, z1, vol_c[: z1 - z0], ws)
     torch.cuda.synchronize()
     t_compute = time.perf_counter() - t0
     log(f"compute only: {t_compute:.2f} s")
@@ -651,18 +666,19 @@ def main_pipeline(args):
                 kept[z] = v[z - z0].copy()
 
     pl = pipeline.ChunkPipeline(plan, max_rows=max(pattern), n_dark=dark_h.shape[0], n_flat=flat_h.shape[0],
-                                storage=st, use_graphs=True, kind=args.filter)
+                                storage=st, use_graphs=True, kind=args.filter, method=args.method)
     pl.prepare(chunks)
     log(f"pipeline: {len(chunks)} chunks, {pl.stats.graphs_captured} graphs; running")
     stats = pl.run(chunks, source, sink)
     log(f"pipeline: {stats.seconds:.2f} s host to host")
     rel = []
     rng = np.random.default_rng(0)
+    npts = 64 if fourier else 1024  # the Fourier oracle sums L + 1 terms per voxel and angle
     for z in sample_z:
-        ix, iy = rng.integers(0, n, 1024), rng.integers(0, n, 1024)
-        want = oracle.fbp_points(proj_h[:, z].view(np.uint16), dark_h[:, z].view(np.uint16),
-                                 flat_h[:, z].view(np.uint16), plan.angles, center, n, ix, iy,
-                                 kind=args.filter)
+        ix, iy = rng.integers(0, n, npts), rng.integers(0, n, npts)
+        ref = oracle.fourier_fbp_points if fourier else oracle.fbp_points
+        want = ref(proj_h[:, z].view(np.uint16), dark_h[:, z].view(np.uint16), flat_h[:, z].view(np.uint16),
+                   plan.angles, center, n, ix, iy, kind=args.filter)
         got = kept[z][iy, ix].astype(np.float64)
         rel.append(float(np.linalg.norm(got - want) / np.linalg.norm(want)))
     h2d = (proj_h.nbytes + dark_h.nbytes + flat_h.nbytes) / 1e9
@@ -676,9 +692,10 @@ def main_pipeline(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"fbp {n}x{n}x{rows} from {na} angles x {rows} rows x {n} cols 12-bit ellipsoid scan, "
-                               f"{FILTER_NAMES[args.filter]}",
-                   "storage": st, "chunks": list(pattern), "n_chunks": len(chunks), "graphs": stats.graphs_captured,
-                   "bp_tuning": [k, a]},
+                               f"{FILTER_NAMES[args.filter]}, "
+                               + ("Fourier-domain backprojection" if fourier else "linear-interpolation backprojection"),
+                   "storage": None if fourier else st, "chunks": list(pattern), "n_chunks": len(chunks),
+                   "graphs": stats.graphs_captured, "bp_tuning": None if fourier else [k, a]},
         "s_host_to_host": round(stats.seconds, 3),
         "s_compute_only_resident": round(t_compute, 3),
         "overlap_efficiency": round(t_compute / stats.seconds, 3),
