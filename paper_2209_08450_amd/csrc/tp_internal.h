@@ -126,10 +126,12 @@ __device__ __forceinline__ float coord_frac(float s) { return __builtin_amdgcn_f
 // Negative log of the flat/dark-corrected transmission (paper, Section 2.2):
 // -ln(max((P - D) * rden, 1e-6)) with rden = 1 / max(F - D, 1) stored per
 // pixel by the dark/flat pass (a multiply per sample instead of a divide).
-// Written as a subtraction from zero, not a negation.
+// The clamp keeps the argument a normal number, so the hardware base-2
+// logarithm needs none of the library's range handling: -ln t = -ln 2 * log2 t.
 constexpr float kMinTransmission = 1e-6f;
+constexpr float kNegLn2 = -0.693147180559945309f;
 __device__ __forceinline__ float neglog_counts(float P, float d, float rden) {
-    return 0.0f - logf(fmaxf((P - d) * rden, kMinTransmission));
+    return kNegLn2 * __builtin_amdgcn_logf(fmaxf((P - d) * rden, kMinTransmission));
 }
 
 __device__ __forceinline__ float load_as_float(const float* p, int64_t i) { return p[i]; }

@@ -88,6 +88,20 @@ def test_fourier_voxel_grid_sizes(tp, scan64, n_vox):
     assert rel_l2(got, want) < 1e-5
 
 
+@pytest.mark.parametrize("n,rows,center", [(63, 3, 30.0), (100, 1, 61.7), (64, 2, 20.25)])
+def test_fourier_detector_widths_and_axes(tp, n, rows, center):
+    # odd width (pad offset (L - n) / 2 rounds down), a width that is not a
+    # power of two with a single row (its partner is zero), an axis far from
+    # the detector centre
+    s = synth.phantom_2d_scan(seed=9, n_rows=rows, n_angles=72, n_det=n, center=center)
+    note(f"fourier n={n} rows={rows} centre={center}")
+    got = _run(tp, s)
+    want = _oracle(s, slice(0, rows))
+    e = rel_l2(got, want)
+    note(f"rel-L2 {e}")
+    assert e < 1e-5
+
+
 def test_fourier_passes_bitwise(tp, scan64):
     plan = tp.Plan(scan64.angles, 64, scan64.center)
     one = _run(tp, scan64, plan=plan)
