@@ -273,6 +273,37 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan,
                                       void* workspace, size_t workspace_bytes,
                                       float* vol, void* stream, void* const* events);
 
+/* --------------------------------------------------------------------------
+ * Storage reads and writes of the chunk pipeline (paper, Section 2.3: chunks
+ * are read from the storage drive and reconstructed chunks written back by
+ * their own threads, in parallel, overlapped with transfers and computation).
+ * Host-only calls: plain host pointers (pinned or pageable), blocking, safe to
+ * call from several threads at once on different buffers.  A failing call
+ * returns TP_EINVAL with the reason in tp_io_last_error() (thread-local,
+ * separate from tp_last_error); nothing is partially reported as success.
+ * Files are raw little-endian arrays (they stand in for the paper's HDF5
+ * datasets and TIFF slices).  When every file offset, length and the buffer
+ * are 4096-byte aligned the file is opened with O_DIRECT (bypassing the page
+ * cache), else buffered; a direct transfer the kernel refuses (EINVAL, or
+ * EFAULT for buffers it cannot pin, such as the GPU runtime's pinned host
+ * memory) is repeated buffered.  n_threads: 1..64 threads issue the pieces.
+ * ------------------------------------------------------------------------ */
+/* Reads detector rows [z0, z1) of a projection-major file holding, after
+ * header_bytes, [n_outer][n_rows][n_det] elements of elem_bytes each (n_outer
+ * = angles, or dark/flat frames) into dst [n_outer][z1 - z0][n_det]: n_outer
+ * pieces of (z1 - z0) * n_det elements. */
+tp_status tp_io_read_rows(const char* path, int64_t header_bytes, int32_t n_outer, int32_t n_rows, int32_t n_det,
+                          int32_t z0, int32_t z1, int32_t elem_bytes, void* dst, int32_t n_threads);
+/* Writes n_slices slices of slice_bytes each from src to the file (which must
+ * exist, see tp_io_create) at header_bytes + first_slice * slice_bytes: one
+ * piece per slice. */
+tp_status tp_io_write_slices(const char* path, int64_t header_bytes, int64_t first_slice, int32_t n_slices,
+                             int64_t slice_bytes, const void* src, int32_t n_threads);
+/* Creates (or truncates) the file and sets its size to `bytes`. */
+tp_status tp_io_create(const char* path, int64_t bytes);
+/* Thread-local description of the last failing tp_io_* call on this thread. */
+const char* tp_io_last_error(void);
+
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* tp_last_error(void);
 /* Library version string. */

@@ -22,6 +22,7 @@ tp_fbp_chunk call over all rows.
 """
 from __future__ import annotations
 
+import os
 import queue
 import threading
 from dataclasses import dataclass
@@ -43,6 +44,48 @@ def uneven_chunks(n_rows: int, pattern=(32, 64, 128), start_row: int = 0):
         z += c
         i += 1
     return out
+
+
+class FileSource:
+    """Pipeline source that reads each chunk's rows from raw projection-major
+    files (uint16 [n_angles][n_rows][n_det], dark and flat [frames][n_rows][n_det])
+    straight into the pipeline's pinned buffers with tp_io_read_rows: the
+    storage side of the paper's Section 2.3 pipeline, in native threads."""
+
+    def __init__(self, proj_path, dark_path, flat_path, n_angles: int, n_rows: int, n_det: int, n_dark: int,
+                 n_flat: int, threads: int = 16):
+        self.paths = (str(proj_path), str(dark_path), str(flat_path))
+        self.shape = (int(n_angles), int(n_rows), int(n_det), int(n_dark), int(n_flat))
+        self.threads = int(threads)
+
+    def __call__(self, z0, z1, p, d, f):
+        na, nr, n, nd, nf = self.shape
+        tp.io_read_rows(self.paths[0], na, nr, n, z0, z1, p, threads=self.threads)
+        tp.io_read_rows(self.paths[1], nd, nr, n, z0, z1, d, threads=self.threads)
+        tp.io_read_rows(self.paths[2], nf, nr, n, z0, z1, f, threads=self.threads)
+
+
+class FileSink:
+    """Pipeline sink that writes each chunk's slices (float32 [rows][N][N]) into
+    one raw volume file with tp_io_write_slices; the file is created at its
+    full size first."""
+
+    def __init__(self, path, n_rows: int, n_vox: int, threads: int = 16):
+        self.path = str(path)
+        self.slice_bytes = int(n_vox) * int(n_vox) * 4
+        self.threads = int(threads)
+        tp.io_create(self.path, int(n_rows) * self.slice_bytes)
+
+    def __call__(self, z0, z1, vol):
+        tp.io_write_slices(self.path, z0, vol, self.slice_bytes, threads=self.threads)
+
+    def flush(self):
+        """Force the written slices out to the drive (fsync)."""
+        fd = os.open(self.path, os.O_RDONLY)
+        try:
+            os.fsync(fd)
+        finally:
+            os.close(fd)
 
 
 @dataclass

@@ -71,6 +71,12 @@ _fourier_chunk = _proto("tp_fourier_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c
 _fourier_chunk_events = _proto("tp_fourier_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
                                _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp,
                                ctypes.POINTER(_c_vp))
+_io_read_rows = _proto("tp_io_read_rows", _c_i32, ctypes.c_char_p, _c_i64, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32,
+                       _c_i32, _c_vp, _c_i32)
+_io_write_slices = _proto("tp_io_write_slices", _c_i32, ctypes.c_char_p, _c_i64, _c_i64, _c_i32, _c_i64, _c_vp,
+                          _c_i32)
+_io_create = _proto("tp_io_create", _c_i32, ctypes.c_char_p, _c_i64)
+_io_last_error = _proto("tp_io_last_error", ctypes.c_char_p)
 _last_error = _proto("tp_last_error", ctypes.c_char_p)
 _version = _proto("tp_version", ctypes.c_char_p)
 
@@ -405,3 +411,49 @@ def fourier_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, st
         arr = (_c_vp * 6)(*[_c_vp(e.cuda_event) if e is not None else _c_vp() for e in events])
         _check(_fourier_chunk_events(*args, arr))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Storage reads and writes (host buffers: numpy arrays or CPU tensors)
+# ---------------------------------------------------------------------------
+def _host_ptr(buf, writable: bool):
+    if isinstance(buf, np.ndarray):
+        if not buf.flags.c_contiguous or (writable and not buf.flags.writeable):
+            raise ValueError("host buffer must be C-contiguous" + (" and writable" if writable else ""))
+        return ctypes.c_void_p(buf.ctypes.data), buf.nbytes
+    if getattr(buf, "is_cuda", False):
+        raise ValueError("storage calls take host buffers")
+    if not buf.is_contiguous():
+        raise ValueError("host buffer must be contiguous")
+    return ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()
+
+
+def _io_check(status: int):
+    if status != TP_OK:
+        raise TpError(status, _io_last_error().decode())
+
+
+def io_read_rows(path, n_outer: int, n_rows: int, n_det: int, z0: int, z1: int, dst, threads: int = 8,
+                 header_bytes: int = 0, elem_bytes: int = 2):
+    """Rows [z0, z1) of a projection-major file [n_outer][n_rows][n_det] into
+    dst [n_outer][z1 - z0][n_det] (tp_io_read_rows)."""
+    ptr, nbytes = _host_ptr(dst, True)
+    if nbytes < n_outer * (z1 - z0) * n_det * elem_bytes:
+        raise ValueError("destination buffer too small")
+    _io_check(_io_read_rows(os.fsencode(str(path)), int(header_bytes), int(n_outer), int(n_rows), int(n_det), int(z0),
+                            int(z1), int(elem_bytes), ptr, int(threads)))
+    return dst
+
+
+def io_write_slices(path, first_slice: int, src, slice_bytes: int, threads: int = 8, header_bytes: int = 0):
+    """Slices src [n][...] (n * slice_bytes bytes) at slice first_slice of the file (tp_io_write_slices)."""
+    ptr, nbytes = _host_ptr(src, False)
+    if nbytes % slice_bytes:
+        raise ValueError("source is not a whole number of slices")
+    _io_check(_io_write_slices(os.fsencode(str(path)), int(header_bytes), int(first_slice), nbytes // slice_bytes,
+                               int(slice_bytes), ptr, int(threads)))
+
+
+def io_create(path, nbytes: int):
+    """Create (or truncate) a file of nbytes bytes (tp_io_create)."""
+    _io_check(_io_create(os.fsencode(str(path)), int(nbytes)))

@@ -83,6 +83,26 @@ def test_pipeline_fourier_bitwise_equals_monolithic(env):
     assert pl.stats.graphs_captured > 0
 
 
+def test_pipeline_files_to_file_bitwise_equals_monolithic(env, tmp_path):
+    # storage on both ends: the source reads row chunks from raw projection-major
+    # files, the sink writes slices into one volume file (native reader and
+    # writer threads)
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    want = _monolithic(tp, plan, s, "f16")
+    na, rows, n = s.proj.shape
+    for name, arr in (("proj", s.proj), ("dark", s.dark), ("flat", s.flat)):
+        np.ascontiguousarray(arr).tofile(tmp_path / f"{name}.raw")
+    src = pipeline.FileSource(tmp_path / "proj.raw", tmp_path / "dark.raw", tmp_path / "flat.raw", na, rows, n,
+                              s.dark.shape[0], s.flat.shape[0], threads=4)
+    sink = pipeline.FileSink(tmp_path / "vol.raw", rows, 128, threads=4)
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=s.dark.shape[0], n_flat=s.flat.shape[0], storage="f16")
+    note("pipeline files to file f16")
+    pl.run(pipeline.uneven_chunks(rows, (32, 9)), src, sink)
+    got = np.fromfile(tmp_path / "vol.raw", np.float32).reshape(rows, 128, 128)
+    assert np.array_equal(got, want)
+
+
 def test_graph_replays_repeat_with_eager_work_between(env):
     import torch
     tp, pipeline, _, s = env
