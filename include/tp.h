@@ -284,9 +284,10 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan,
  * Files are raw little-endian arrays (they stand in for the paper's HDF5
  * datasets and TIFF slices).  When every file offset, length and the buffer
  * are 4096-byte aligned the file is opened with O_DIRECT (bypassing the page
- * cache), else buffered; a direct transfer the kernel refuses (EINVAL, or
- * EFAULT for buffers it cannot pin, such as the GPU runtime's pinned host
- * memory) is repeated buffered.  n_threads: 1..64 threads issue the pieces.
+ * cache), else buffered; buffers the kernel cannot pin for a direct transfer
+ * (EFAULT, such as the GPU runtime's pinned host memory) go through per-thread
+ * aligned bounce buffers, and filesystems that refuse direct transfers
+ * (EINVAL) get buffered I/O.  n_threads: 1..64 threads issue the pieces.
  * ------------------------------------------------------------------------ */
 /* Reads detector rows [z0, z1) of a projection-major file holding, after
  * header_bytes, [n_outer][n_rows][n_det] elements of elem_bytes each (n_outer
@@ -296,7 +297,8 @@ tp_status tp_io_read_rows(const char* path, int64_t header_bytes, int32_t n_oute
                           int32_t z0, int32_t z1, int32_t elem_bytes, void* dst, int32_t n_threads);
 /* Writes n_slices slices of slice_bytes each from src to the file (which must
  * exist, see tp_io_create) at header_bytes + first_slice * slice_bytes: one
- * piece per slice. */
+ * piece per slice.  Writeback of the range to the drive is started before
+ * returning (not waited for), so a later flush finds little left to write. */
 tp_status tp_io_write_slices(const char* path, int64_t header_bytes, int64_t first_slice, int32_t n_slices,
                              int64_t slice_bytes, const void* src, int32_t n_threads);
 /* Creates (or truncates) the file and sets its size to `bytes`. */

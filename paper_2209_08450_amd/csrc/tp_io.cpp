@@ -10,8 +10,10 @@
 // contiguous in the output file and are written with pwrite() the same way.
 // When the file offsets, the lengths and the host buffer are 4096-byte aligned
 // the file is opened with O_DIRECT, so the transfer does not pass through the
-// page cache (the measured rate is the drive's, not RAM's); otherwise, or when
-// the kernel refuses the direct transfer, with buffered I/O.
+// page cache (the measured rate is the drive's, not RAM's); a buffer the
+// kernel cannot pin for the transfer goes through per-thread aligned bounce
+// buffers (still direct); a filesystem that refuses direct transfers gets
+// buffered I/O.
 #ifndef _GNU_SOURCE
 #define _GNU_SOURCE
 #endif
@@ -25,6 +27,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -76,37 +79,67 @@ struct Piece {
     int64_t file_off, buf_off, len;
 };
 
-// Runs the pieces on n_threads threads; returns the first failure.  A direct
-// transfer that is refused (EINVAL, EFAULT) is repeated with buffered I/O.
-tp_status run_pieces(const char* path, bool write, char* buf, const std::vector<Piece>& pieces, int n_threads,
-                     bool try_direct);
+// How a call moves its pieces.
+enum class Mode {
+    kBuffered,      // through the page cache
+    kDirect,        // O_DIRECT into / out of the caller's buffer
+    kDirectBounce,  // O_DIRECT through a per-thread aligned buffer plus a memcpy
+};
+constexpr int64_t kBounceBytes = int64_t{16} << 20;
 
+// Runs the pieces on n_threads threads; on failure *err_no holds the errno
+// (0 for a file that is too short).
 tp_status run_pieces_once(const char* path, bool write, char* buf, const std::vector<Piece>& pieces, int n_threads,
-                          bool try_direct, bool* direct_rejected) {
-    *direct_rejected = false;
-    int flags = write ? O_WRONLY : O_RDONLY;
-    int fd = -1;
-    bool direct = false;
-    if (try_direct) {
-        fd = open(path, flags | O_DIRECT);
-        direct = fd >= 0;
+                          Mode mode, int* err_no, bool* open_failed) {
+    *err_no = 0;
+    *open_failed = false;
+    const int flags = (write ? O_WRONLY : O_RDONLY) | (mode == Mode::kBuffered ? 0 : O_DIRECT);
+    const int fd = open(path, flags);
+    if (fd < 0) {
+        *err_no = errno;
+        *open_failed = true;
+        return TP_EINVAL;
     }
-    if (fd < 0) fd = open(path, flags);
-    if (fd < 0) return io_fail("cannot open %s: %s", path, strerror(errno));
     std::atomic<size_t> next{0};
     std::atomic<int> failed{0}, fail_errno{0};
     auto worker = [&]() {
-        for (;;) {
-            const size_t i = next.fetch_add(1);
-            if (i >= pieces.size() || failed.load()) return;
-            const Piece& p = pieces[i];
-            int e = 0;
-            if (!full_io(fd, buf + p.buf_off, p.len, p.file_off, write, &e)) {
-                fail_errno.store(e);
+        char* bounce = nullptr;
+        if (mode == Mode::kDirectBounce) {
+            void* p = nullptr;
+            if (posix_memalign(&p, static_cast<size_t>(kAlign), static_cast<size_t>(kBounceBytes)) != 0) {
+                fail_errno.store(ENOMEM);
                 failed.store(1);
                 return;
             }
+            bounce = static_cast<char*>(p);
         }
+        for (;;) {
+            const size_t i = next.fetch_add(1);
+            if (i >= pieces.size() || failed.load()) break;
+            const Piece& pc = pieces[i];
+            int e = 0;
+            bool ok = true;
+            if (bounce == nullptr) {
+                ok = full_io(fd, buf + pc.buf_off, pc.len, pc.file_off, write, &e);
+            } else {
+                for (int64_t done = 0; ok && done < pc.len; done += kBounceBytes) {
+                    const int64_t n = std::min(kBounceBytes, pc.len - done);
+                    if (write) {
+                        std::memcpy(bounce, buf + pc.buf_off + done, static_cast<size_t>(n));
+                        ok = full_io(fd, bounce, n, pc.file_off + done, true, &e);
+                    } else {
+                        ok = full_io(fd, bounce, n, pc.file_off + done, false, &e);
+                        if (ok) std::memcpy(buf + pc.buf_off + done, bounce, static_cast<size_t>(n));
+                    }
+                }
+            }
+            if (!ok) {
+                fail_errno.store(e);
+                failed.store(1);
+                break;
+            }
+        }
+        free(bounce);
     };
     const int nt = std::max(1, std::min({n_threads, kMaxThreads, static_cast<int>(pieces.size())}));
     std::vector<std::thread> th;
@@ -115,26 +148,37 @@ tp_status run_pieces_once(const char* path, bool write, char* buf, const std::ve
     for (auto& t : th) t.join();
     close(fd);
     if (failed.load()) {
-        const int e = fail_errno.load();
-        // EINVAL: the filesystem refuses direct transfers; EFAULT: the buffer
-        // is memory the kernel cannot pin for one (e.g. driver-pinned host
-        // memory of the GPU runtime)
-        if (direct && (e == EINVAL || e == EFAULT)) {
-            *direct_rejected = true;
-            return TP_EINVAL;
-        }
-        return io_fail("%s %s failed%s: %s", write ? "writing" : "reading", path, direct ? " (O_DIRECT)" : "",
-                       e ? strerror(e) : "file too short");
+        *err_no = fail_errno.load();
+        return TP_EINVAL;
     }
     return TP_OK;
 }
 
+// Aligned transfers go direct; a buffer the kernel cannot pin for a direct
+// transfer (EFAULT: e.g. the GPU runtime's pinned host memory) goes through
+// bounce buffers; a filesystem that refuses direct transfers (EINVAL at open
+// or transfer) gets buffered I/O.
 tp_status run_pieces(const char* path, bool write, char* buf, const std::vector<Piece>& pieces, int n_threads,
                      bool try_direct) {
-    bool rejected = false;
-    const tp_status st = run_pieces_once(path, write, buf, pieces, n_threads, try_direct, &rejected);
-    if (st != TP_OK && rejected) return run_pieces_once(path, write, buf, pieces, n_threads, false, &rejected);
-    return st;
+    int e = 0;
+    bool open_failed = false;
+    Mode mode = try_direct ? Mode::kDirect : Mode::kBuffered;
+    tp_status st = run_pieces_once(path, write, buf, pieces, n_threads, mode, &e, &open_failed);
+    if (st != TP_OK && mode == Mode::kDirect && e == EFAULT) {
+        mode = Mode::kDirectBounce;
+        st = run_pieces_once(path, write, buf, pieces, n_threads, mode, &e, &open_failed);
+    }
+    if (st != TP_OK && mode != Mode::kBuffered && e == EINVAL) {
+        mode = Mode::kBuffered;
+        st = run_pieces_once(path, write, buf, pieces, n_threads, mode, &e, &open_failed);
+    }
+    if (st != TP_OK && open_failed) return io_fail("cannot open %s: %s", path, strerror(e));
+    if (st != TP_OK) {
+        const char* how = mode == Mode::kBuffered ? "" : (mode == Mode::kDirect ? " (O_DIRECT)" : " (O_DIRECT, bounce)");
+        return io_fail("%s %s failed%s: %s", write ? "writing" : "reading", path, how,
+                       e ? strerror(e) : "file too short");
+    }
+    return TP_OK;
 }
 
 }  // namespace
@@ -173,7 +217,18 @@ tp_status tp_io_write_slices(const char* path, int64_t header_bytes, int64_t fir
     for (int32_t s = 0; s < n_slices; ++s)
         pieces[static_cast<size_t>(s)] =
             Piece{header_bytes + (first_slice + s) * slice_bytes, static_cast<int64_t>(s) * slice_bytes, slice_bytes};
-    return run_pieces(path, true, static_cast<char*>(const_cast<void*>(src)), pieces, n_threads, direct);
+    const tp_status st = run_pieces(path, true, static_cast<char*>(const_cast<void*>(src)), pieces, n_threads, direct);
+    if (st != TP_OK) return st;
+    // Start writing the range out now (without waiting): buffered writes would
+    // otherwise sit in the page cache until a final flush, and the drive would
+    // not work while later chunks are read and reconstructed.
+    const int fd = open(path, O_WRONLY);
+    if (fd >= 0) {
+        (void)sync_file_range(fd, header_bytes + first_slice * slice_bytes,
+                              static_cast<int64_t>(n_slices) * slice_bytes, SYNC_FILE_RANGE_WRITE);
+        close(fd);
+    }
+    return TP_OK;
 }
 
 tp_status tp_io_create(const char* path, int64_t bytes) {
