@@ -172,6 +172,23 @@ def test_fourier_register_transform_sizes(tp, n):
     torch.cuda.empty_cache()
 
 
+def test_fourier_widest_detector(tp):
+    # 8192 columns: pad length and grid side 16384, the largest supported
+    # (LDS transforms with 1024 threads and 128 KB of LDS), one row
+    import torch
+    s = synth.phantom_2d_scan(seed=6, n_rows=1, n_angles=24, n_det=8192, center=4095.5)
+    note("fourier 24 angles x 1 row x 8192")
+    got = _run(tp, s)
+    rng = np.random.default_rng(14)
+    ix = rng.integers(0, 8192, 48)
+    iy = rng.integers(0, 8192, 48)
+    want = oracle.fourier_fbp_points(s.proj[:, 0], s.dark[:, 0], s.flat[:, 0], s.angles, s.center, 8192, ix, iy)
+    e = rel_l2(got[0, iy, ix], want)
+    note(f"rel-L2 at sampled voxels {e}")
+    assert e < 1e-5
+    torch.cuda.empty_cache()
+
+
 def test_fourier_close_to_linear_interpolation_fbp(tp, scan64):
     # sanity: the two interpolations differ by the linear interpolation's
     # smoothing only
