@@ -28,6 +28,9 @@ Functions follow the paper (arXiv 2209.08450):
 * ``fourier_backproject`` / ``fourier_fbp`` -- the Fourier-domain
   backprojection ("FourierRec", Sections 2.2 and 3): each padded filtered row
   evaluated along the ray by its trigonometric interpolant, summed directly.
+* ``lamino_backproject`` -- the direct backprojector in laminographic
+  geometry (tilted rotation axis, bilinear interpolation; Section 2.2 names
+  this use of the direct method).
 * ``power_lambda_max`` / ``ls_solve`` -- gradient least squares with the pair.
 
 Parity status: every function here is pinned by closed forms, invariants or
@@ -60,6 +63,8 @@ from .fbp import (  # noqa: F401
     fourier_backproject_points,
     fourier_fbp,
     fourier_fbp_points,
+    lamino_backproject,
+    lamino_backproject_points,
     power_lambda_max,
     ls_gradient,
     ls_solve,

@@ -183,3 +183,55 @@ void oracle_fourier_backproject_points(const double *Yre, const double *Yim, int
         out[p] = scale * acc;
     }
 }
+
+/*
+ * Laminographic backprojection (paper, Section 2.2: the direct line-integral
+ * backprojector is kept because it also serves laminographic geometry, where
+ * the rotation axis is tilted with respect to the beam).  Reading of the
+ * geometry: rotation axis tilted by phi from the beam (phi = pi/2 is
+ * ordinary tomography); at rotation angle theta the voxel (x, y, z) is seen
+ * at detector column u and row v
+ *
+ *   u = x cos(theta) + y sin(theta) + center_u
+ *   v = (-x sin(theta) + y cos(theta)) cos(phi) + z sin(phi) + center_v
+ *
+ * with x = ix - floor(N/2), y = iy - floor(N/2), z = iz - floor(Nz/2), and
+ *
+ *   f(ix, iy, iz) = scale * sum_a  bilinear(Q_a, v, u)
+ *
+ * where Q_a is the filtered projection [rows][n] of angle a and taps outside
+ * the detector read zero.  q: [na][rows][n].  Output at the listed voxels.
+ */
+static double lam_tap(const double *img, int64_t rows, int64_t n, int64_t r, int64_t c)
+{
+    return (r >= 0 && r < rows && c >= 0 && c < n) ? img[r * n + c] : 0.0;
+}
+
+void oracle_lamino_backproject_points(const double *q, int64_t na, int64_t rows, int64_t n,
+                                      const double *angles, double center_u, double center_v,
+                                      double phi, int64_t N, int64_t Nz, double scale,
+                                      const int64_t *ix, const int64_t *iy, const int64_t *iz,
+                                      int64_t npts, double *out)
+{
+    const double cphi = cos(phi), sphi = sin(phi);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < npts; ++p) {
+        const double x = (double)(ix[p] - N / 2);
+        const double y = (double)(iy[p] - N / 2);
+        const double z = (double)(iz[p] - Nz / 2);
+        double acc = 0.0;
+        for (int64_t a = 0; a < na; ++a) {
+            const double c = cos(angles[a]), s = sin(angles[a]);
+            const double u = x * c + y * s + center_u;
+            const double v = (-x * s + y * c) * cphi + z * sphi + center_v;
+            const double fu = floor(u), fv = floor(v);
+            const int64_t c0 = (int64_t)fu, r0 = (int64_t)fv;
+            const double wu = u - fu, wv = v - fv;
+            const double *img = q + a * rows * n;
+            const double top = (1.0 - wu) * lam_tap(img, rows, n, r0, c0) + wu * lam_tap(img, rows, n, r0, c0 + 1);
+            const double bot = (1.0 - wu) * lam_tap(img, rows, n, r0 + 1, c0) + wu * lam_tap(img, rows, n, r0 + 1, c0 + 1);
+            acc += (1.0 - wv) * top + wv * bot;
+        }
+        out[p] = scale * acc;
+    }
+}

@@ -44,6 +44,9 @@ def _load():
         lib.oracle_radon.restype = None
         lib.oracle_fourier_backproject_points.argtypes = [pd, pd, i64, i64, pd, d, i64, d, pi, pi, i64, pd]
         lib.oracle_fourier_backproject_points.restype = None
+        lib.oracle_lamino_backproject_points.argtypes = [pd, i64, i64, i64, pd, d, d, d, i64, i64, d, pi, pi, pi,
+                                                          i64, pd]
+        lib.oracle_lamino_backproject_points.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -445,6 +448,47 @@ def fourier_fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix
                   np.asarray(flat_slice)[:, None, :])[0]
     y, off = filter_rows_padded(p, kind=kind)
     return fourier_backproject_points(y, angles, center + off, N, ix, iy)
+
+
+# --------------------------------------------------------------------------
+# Laminographic backprojection.
+# --------------------------------------------------------------------------
+def lamino_backproject_points(q: np.ndarray, angles, center_u: float, center_v: float, phi: float, N: int, Nz: int,
+                              ix, iy, iz, scale: float | None = None) -> np.ndarray:
+    """Laminographic backprojection of filtered projections q [n_angles][rows][n]
+    at voxels (ix, iy, iz), FP64 (C loop).
+
+    Reading of the geometry (the paper names laminography as a use of the
+    direct backprojector without defining it): the rotation axis is tilted by
+    phi from the beam (phi = pi/2 is tomography); voxel (x, y, z) is seen at
+    column u = x cos + y sin + center_u and row
+    v = (-x sin + y cos) cos(phi) + z sin(phi) + center_v, bilinear
+    interpolation, zero off the detector; x = ix - N//2, y = iy - N//2,
+    z = iz - Nz//2; scale defaults to pi / n_angles.
+    """
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    na, rows, n = q.shape
+    ang = np.ascontiguousarray(angles, dtype=np.float64)
+    assert ang.shape == (na,)
+    ix = np.ascontiguousarray(ix, dtype=np.int64)
+    iy = np.ascontiguousarray(iy, dtype=np.int64)
+    iz = np.ascontiguousarray(iz, dtype=np.int64)
+    if scale is None:
+        scale = math.pi / na
+    out = np.empty(ix.shape[0], dtype=np.float64)
+    _load().oracle_lamino_backproject_points(_pd(q), na, rows, n, _pd(ang), float(center_u), float(center_v),
+                                             float(phi), N, Nz, float(scale), _pi(ix), _pi(iy), _pi(iz),
+                                             ix.shape[0], _pd(out))
+    return out
+
+
+def lamino_backproject(q: np.ndarray, angles, center_u: float, center_v: float, phi: float, N: int, Nz: int,
+                       scale: float | None = None) -> np.ndarray:
+    """``lamino_backproject_points`` at every voxel: -> [Nz][N][N]."""
+    iz, iy, ix = np.meshgrid(np.arange(Nz), np.arange(N), np.arange(N), indexing="ij")
+    v = lamino_backproject_points(q, angles, center_u, center_v, phi, N, Nz, ix.ravel(), iy.ravel(), iz.ravel(),
+                                  scale)
+    return v.reshape(Nz, N, N)
 
 
 # --------------------------------------------------------------------------
