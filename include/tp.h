@@ -274,6 +274,28 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan,
                                       float* vol, void* stream, void* const* events);
 
 /* --------------------------------------------------------------------------
+ * Laminographic backprojection (paper, Section 2.2: the direct line-integral
+ * backprojector is kept because it also serves laminography, where the
+ * rotation axis is tilted with respect to the beam).  Geometry (a reading:
+ * the paper does not define it): axis tilted by `tilt` = phi in (0, pi) from
+ * the beam, phi = pi/2 being tomography; voxel (x, y, z) of the
+ * [n_slices][N][N] volume (x = ix - N/2, y = iy - N/2, z = iz - n_slices/2)
+ * is seen at detector column u = x cos + y sin + center (the plan's axis) and
+ * row v = (-x sin + y cos) cos(phi) + z sin(phi) + center_v, and
+ *   vol = scale * sum_a bilinear(filt_a, v, u),  zero off the detector.
+ * filt: dev [n_angles][det_rows][n_det] in in_dtype (projections filtered
+ * along detector rows, e.g. by tp_filter); vol: dev float [nz][N][N] receives
+ * slices z0 .. z0 + nz - 1 (overwritten).  Tables are built on first use per
+ * (tilt, center_v, n_slices) (tp_lamino_prepare first when the call will be
+ * graph-captured; else TP_EUNSUPPORTED during capture).  TP_EINVAL for bad
+ * arguments, checked before any launch.
+ * ------------------------------------------------------------------------ */
+tp_status tp_lamino_prepare(const tp_plan* plan, double tilt, double center_v, int32_t n_slices);
+tp_status tp_lamino_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtype, int32_t det_rows,
+                                double tilt, double center_v, int32_t n_slices, int32_t z0, int32_t nz,
+                                float scale, float* vol, void* stream);
+
+/* --------------------------------------------------------------------------
  * Storage reads and writes of the chunk pipeline (paper, Section 2.3: chunks
  * are read from the storage drive and reconstructed chunks written back by
  * their own threads, in parallel, overlapped with transfers and computation).

@@ -21,6 +21,11 @@ struct FourierEntry {
     tp::FourierTables t{};
 };
 
+struct LaminoEntry {
+    void* block = nullptr;
+    tp::LaminoTables t{};
+};
+
 struct tp_plan {
     int device = -1;
     int na = 0, n = 0, N = 0, nb = 0;
@@ -35,6 +40,8 @@ struct tp_plan {
     // Fourier-domain backprojection tables per (filter window, truncation radius)
     mutable std::mutex fr_mu;
     mutable std::map<std::pair<int, int>, FourierEntry> fr;
+    // laminographic backprojection tables per (tilt, row centre, slice count)
+    mutable std::map<std::tuple<double, double, int>, LaminoEntry> lam;
 };
 
 namespace {
@@ -427,6 +434,98 @@ tp_status fourier_tables(const tp_plan* plan, tp_filter_kind kind, int msp, tp::
     return TP_OK;
 }
 
+tp_status lamino_tables(const tp_plan* plan, double tilt, double center_v, int Nz, tp::LaminoTables* out,
+                        hipStream_t st_for_capture_check) {
+    std::lock_guard<std::mutex> lk(plan->fr_mu);
+    const auto key = std::make_tuple(tilt, center_v, Nz);
+    auto it = plan->lam.find(key);
+    if (it != plan->lam.end()) {
+        *out = it->second.t;
+        return TP_OK;
+    }
+    if (st_for_capture_check != nullptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st_for_capture_check, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            return fail(TP_EUNSUPPORTED, "laminography tables not built; call tp_lamino_prepare before capture");
+    }
+    const int na = plan->na, nb = plan->nb, N = plan->N;
+    const double cphi = std::cos(tilt), sphi = std::sin(tilt);
+    std::vector<int> vxi(static_cast<size_t>(nb) * na), vyi(static_cast<size_t>(nb) * na), vzi(Nz);
+    std::vector<float> vxf(vxi.size()), vyf(vyi.size()), vzf(Nz), dvdx(na), dvdy(na);
+    for (int a = 0; a < na; ++a) {
+        const double c = std::cos(plan->angles[a]), sn = std::sin(plan->angles[a]);
+        dvdx[a] = static_cast<float>(-sn * cphi);
+        dvdy[a] = static_cast<float>(c * cphi);
+        for (int b = 0; b < nb; ++b) {
+            const double o = static_cast<double>(b * tp::kGeoTile - N / 2);
+            const double X = o * (-sn * cphi), Y = o * (c * cphi);
+            const double fx = std::floor(X), fy = std::floor(Y);
+            const size_t i = static_cast<size_t>(b) * na + a;
+            vxi[i] = static_cast<int>(fx);
+            vxf[i] = static_cast<float>(X - fx);
+            vyi[i] = static_cast<int>(fy);
+            vyf[i] = static_cast<float>(Y - fy);
+        }
+    }
+    for (int z = 0; z < Nz; ++z) {
+        const double Z = static_cast<double>(z - Nz / 2) * sphi + center_v;
+        const double fz = std::floor(Z);
+        vzi[z] = static_cast<int>(fz);
+        vzf[z] = static_cast<float>(Z - fz);
+    }
+    const size_t sT = align256(sizeof(int) * vxi.size()), sZ = align256(sizeof(int) * Nz), sA = align256(sizeof(float) * na);
+    const size_t total = 4 * sT + 2 * sZ + 2 * sA;
+    LaminoEntry le;
+    hipError_t e = hipMalloc(&le.block, total);
+    if (e != hipSuccess) return fail(TP_ENOMEM, "hipMalloc(laminography tables, %zu bytes): %s", total, hipGetErrorString(e));
+    char* p = static_cast<char*>(le.block);
+    char* d_vxi = p;
+    char* d_vxf = d_vxi + sT;
+    char* d_vyi = d_vxf + sT;
+    char* d_vyf = d_vyi + sT;
+    char* d_vzi = d_vyf + sT;
+    char* d_vzf = d_vzi + sZ;
+    char* d_dx = d_vzf + sZ;
+    char* d_dy = d_dx + sA;
+    const size_t tb = sizeof(int) * vxi.size();
+    e = hipMemcpy(d_vxi, vxi.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_vxf, vxf.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_vyi, vyi.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_vyf, vyf.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_vzi, vzi.data(), sizeof(int) * Nz, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_vzf, vzf.data(), sizeof(float) * Nz, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_dx, dvdx.data(), sizeof(float) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_dy, dvdy.data(), sizeof(float) * na, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(le.block);
+        return hip_fail(e, "hipMemcpy(laminography tables)");
+    }
+    tp::LaminoTables& t = le.t;
+    t.vxi = reinterpret_cast<const int*>(d_vxi);
+    t.vxf = reinterpret_cast<const float*>(d_vxf);
+    t.vyi = reinterpret_cast<const int*>(d_vyi);
+    t.vyf = reinterpret_cast<const float*>(d_vyf);
+    t.vzi = reinterpret_cast<const int*>(d_vzi);
+    t.vzf = reinterpret_cast<const float*>(d_vzf);
+    t.dvdx = reinterpret_cast<const float*>(d_dx);
+    t.dvdy = reinterpret_cast<const float*>(d_dy);
+    t.dvdz = static_cast<float>(sphi);
+    t.Nz = Nz;
+    t.rows = 0;
+    plan->lam.emplace(key, le);
+    *out = t;
+    return TP_OK;
+}
+
+tp_status lamino_check(const tp_plan* plan, double tilt, double center_v, int32_t n_slices) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (!std::isfinite(tilt) || tilt <= 0.0 || tilt >= M_PI)
+        return fail(TP_EINVAL, "tilt %g must lie in (0, pi)", tilt);
+    if (!std::isfinite(center_v) || std::fabs(center_v) > 1e6) return fail(TP_EINVAL, "center_v %g out of range", center_v);
+    if (n_slices <= 0 || n_slices > 1000000) return fail(TP_EINVAL, "n_slices=%d out of range", n_slices);
+    return TP_OK;
+}
+
 tp_status fourier_half_width(int32_t half_width, int* msp) {
     if (half_width == 0) {
         *msp = kFourierDefaultHalfWidth;
@@ -587,6 +686,10 @@ tp_status tp_plan_destroy(tp_plan* plan) {
     if (cur != plan->device) (void)hipSetDevice(plan->device);
     hipError_t e = hipFree(plan->dev_block);
     for (auto& kv : plan->fr) {
+        const hipError_t e2 = hipFree(kv.second.block);
+        if (e == hipSuccess) e = e2;
+    }
+    for (auto& kv : plan->lam) {
         const hipError_t e2 = hipFree(kv.second.block);
         if (e == hipSuccess) e = e2;
     }
@@ -799,6 +902,35 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
                                st);
     if (e != hipSuccess) return hip_fail(e, "backproject launch");
     if ((e = mark(3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return TP_OK;
+}
+
+tp_status tp_lamino_prepare(const tp_plan* plan, double tilt, double center_v, int32_t n_slices) {
+    tp_status s = lamino_check(plan, tilt, center_v, n_slices);
+    if (s != TP_OK) return s;
+    tp::LaminoTables t;
+    return lamino_tables(plan, tilt, center_v, n_slices, &t, nullptr);
+}
+
+tp_status tp_lamino_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtype, int32_t det_rows,
+                                double tilt, double center_v, int32_t n_slices, int32_t z0, int32_t nz, float scale,
+                                float* vol, void* stream) {
+    tp_status s = lamino_check(plan, tilt, center_v, n_slices);
+    if (s != TP_OK) return s;
+    if (!filt || !vol) return fail(TP_EINVAL, "null filt or vol");
+    if (!valid_dtype(in_dtype)) return fail(TP_EINVAL, "bad dtype %d", in_dtype);
+    if (det_rows <= 0) return fail(TP_EINVAL, "det_rows=%d must be positive", det_rows);
+    if (z0 < 0 || nz <= 0 || z0 + static_cast<int64_t>(nz) > n_slices)
+        return fail(TP_EINVAL, "slices [%d, %d) outside [0, %d)", z0, z0 + nz, n_slices);
+    if ((nz + tp::lamino_slices_per_block() - 1) / tp::lamino_slices_per_block() > 65535)
+        return fail(TP_EINVAL, "nz=%d too large for one call", nz);
+    if (!std::isfinite(scale)) return fail(TP_EINVAL, "scale is not finite");
+    auto st = static_cast<hipStream_t>(stream);
+    tp::LaminoTables t;
+    if ((s = lamino_tables(plan, tilt, center_v, n_slices, &t, st)) != TP_OK) return s;
+    t.rows = det_rows;
+    const hipError_t e = tp::launch_lamino(plan->geo, t, filt, in_dtype, z0, nz, scale, vol, st);
+    if (e != hipSuccess) return hip_fail(e, "laminography launch");
     return TP_OK;
 }
 

@@ -78,6 +78,23 @@ struct FourierTables {
     float ratio2;           // exp2(-2 kappa s^2): ratio of successive tap ratios
 };
 
+// Tables of the laminographic backprojection (one set per plan, tilt, row
+// centre and slice count): the detector row coordinate of a tile origin,
+// split into integer + FP32 fraction per tile edge and angle and per slice.
+struct LaminoTables {
+    const int* vxi;    // [nb][na] floor((bx*32 - N/2) * (-sin cos_phi))
+    const float* vxf;  // [nb][na] fraction of the same
+    const int* vyi;    // [nb][na] floor((by*32 - N/2) * (cos cos_phi))
+    const float* vyf;
+    const int* vzi;    // [Nz]     floor((iz - Nz/2) sin_phi + center_v)
+    const float* vzf;
+    const float* dvdx; // [na]     -sin(theta) cos(phi), FP32
+    const float* dvdy; // [na]      cos(theta) cos(phi)
+    float dvdz;        //          sin(phi)
+    int Nz;            // slices of the whole volume
+    int rows;          // detector rows of the projections (per call)
+};
+
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_darkflat(const RawInput& in, int n_rows, int n_det, float* dmean, float* den,
                            hipStream_t st);
@@ -104,6 +121,11 @@ hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const
                                float2* cols, hipStream_t st);
 hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
                                float* vol, hipStream_t st);
+
+int lamino_max_rows();
+int lamino_slices_per_block();
+hipError_t launch_lamino(const GeoTables& g, const LaminoTables& t, const void* filt, tp_dtype dt, int z0, int nz,
+                         float scale, float* vol, hipStream_t st);
 
 // ---- detector coordinate decisions shared by backprojection and radon ----
 // Offset of voxel (dx, dy) within its 32x32 tile at one angle; bf is the

@@ -71,6 +71,9 @@ _fourier_chunk = _proto("tp_fourier_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c
 _fourier_chunk_events = _proto("tp_fourier_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
                                _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp,
                                ctypes.POINTER(_c_vp))
+_lamino_prepare = _proto("tp_lamino_prepare", _c_i32, _c_vp, _c_d, _c_d, _c_i32)
+_lamino = _proto("tp_lamino_backproject", _c_i32, _c_vp, _c_vp, _c_i32, _c_i32, _c_d, _c_d, _c_i32, _c_i32, _c_i32,
+                 _c_f, _c_vp, _c_vp)
 _io_read_rows = _proto("tp_io_read_rows", _c_i32, ctypes.c_char_p, _c_i64, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32,
                        _c_i32, _c_vp, _c_i32)
 _io_write_slices = _proto("tp_io_write_slices", _c_i32, ctypes.c_char_p, _c_i64, _c_i64, _c_i32, _c_i64, _c_vp,
@@ -410,6 +413,32 @@ def fourier_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, st
             raise ValueError("record each event once before passing it (torch creates it lazily)")
         arr = (_c_vp * 6)(*[_c_vp(e.cuda_event) if e is not None else _c_vp() for e in events])
         _check(_fourier_chunk_events(*args, arr))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Laminography
+# ---------------------------------------------------------------------------
+def lamino_prepare(plan: Plan, tilt: float, center_v: float, n_slices: int):
+    """Build the laminographic tables for (tilt, center_v, n_slices) (tp_lamino_prepare)."""
+    _check(_lamino_prepare(plan.handle, float(tilt), float(center_v), int(n_slices)))
+
+
+def lamino_backproject(plan: Plan, filt, tilt: float, center_v: float, n_slices: int, z0: int = 0, nz=None,
+                       scale=None, out=None, stream=None):
+    """Laminographic backprojection of filtered projections filt [n_angles][det_rows][n_det]
+    (device, float32 / float16 / bfloat16) into slices z0 .. z0+nz-1 of an n_slices-slice
+    volume: out [nz][N][N] float32 (tp_lamino_backproject).  tilt: angle of the rotation
+    axis to the beam in (0, pi), pi/2 = tomography; scale defaults to pi / n_angles."""
+    torch = _torch()
+    if filt.dim() != 3 or filt.shape[0] != plan.n_angles or filt.shape[2] != plan.n_det or not filt.is_contiguous():
+        raise ValueError("filt must be a contiguous [n_angles][det_rows][n_det] device tensor")
+    nz = int(n_slices) - int(z0) if nz is None else int(nz)
+    if out is None:
+        out = torch.empty((nz, plan.n_vox, plan.n_vox), dtype=torch.float32, device=filt.device)
+    scale = math.pi / plan.n_angles if scale is None else float(scale)
+    _check(_lamino(plan.handle, _dev(filt, "filt"), dtype_code(filt.dtype), int(filt.shape[1]), float(tilt),
+                   float(center_v), int(n_slices), int(z0), nz, scale, _dev(out, "out"), _stream_ptr(stream)))
     return out
 
 

@@ -147,3 +147,10 @@ def test_fourier_validation_without_plan(tp):
     arr = (ctypes.c_void_p * 6)()
     st = tp._fourier_chunk_events(nul, p, 0, p, 1, p, 1, 0, 4, tp.TP_RAMP, 0, p, 1 << 20, p, nul, arr)
     assert st == tp.TP_EINVAL
+
+
+def test_lamino_validation_without_plan(tp):
+    nul = ctypes.c_void_p()
+    p = ctypes.c_void_p(0x100000)
+    assert tp._lamino_prepare(nul, 0.5, 0.0, 8) == tp.TP_EINVAL and "plan" in tp.last_error()
+    assert tp._lamino(nul, p, tp.TP_F32, 8, 0.5, 0.0, 8, 0, 8, 1.0, p, nul) == tp.TP_EINVAL
