@@ -87,6 +87,10 @@ def parse():
     ap.add_argument("--fourier-half-width", type=int, default=0, help="Gaussian truncation radius (0 = 6)")
     ap.add_argument("--fourier-slices", type=int, default=3, help="slices checked against the oracle's direct sum")
     ap.add_argument("--fourier-points", type=int, default=96, help="sampled voxels per checked slice")
+    ap.add_argument("--no-lamino", action="store_true",
+                    help="skip the laminography section (2048^2 x 256 slab from 2048 angles, axis tilted 63 degrees)")
+    ap.add_argument("--single-lamino", action="store_true",
+                    help="instead: one laminographic backprojection of the bench's slab workload")
     ap.add_argument("--single-fourier", action="store_true",
                     help="instead: one tp_fourier_fbp_chunk of the timed chunk shape, then a 1 GiB device copy "
                          "(a short program for hardware-counter passes)")
@@ -134,6 +138,8 @@ def main():
         return main_single_radon(args)
     if args.single_fourier:
         return main_single_fourier(args)
+    if args.single_lamino:
+        return main_single_lamino(args)
 
     import numpy as np
     import torch
@@ -293,6 +299,13 @@ def main():
     if not args.no_fourier:
         fourier = bench_fourier(args, scan, plan, vol, chunks, stream, updates, log)
 
+    # ---------------- laminography (tilted axis) ----------------
+    lamino = None
+    if not args.no_lamino:
+        del scan, vol
+        torch.cuda.empty_cache()
+        lamino = bench_lamino(args, log)
+
     # ---------------- differentiation form: forward projector and least squares ----------------
     ls = None
     if not args.no_ls:
@@ -336,6 +349,7 @@ def main():
         "cpu_baseline": cpu,
         "differentiation": ls,
         "fourierrec": fourier,
+        "laminography": lamino,
         "paper_context": {"linerec_fp32_2048cubed_total_s_A100_incl_io": 80.0},
     }
     if "f16" in results and "f32" in results:
@@ -443,6 +457,108 @@ def bench_fourier(args, scan, plan, vol, chunks, stream, updates, log):
                        "unit": "Gvoxel-angle updates/s", "cores": oracle.num_threads(),
                        "sample": f"direct sum at {cpu_pts} voxels ({L + 1} terms per voxel-angle), {cpu_t:.1f} s"},
     }
+
+
+LAMINO = dict(n=2048, rows=2048, angles=2048, slices=256, tilt=1.1, center_v=1023.5)
+LAMINO_FLOP_PER_UPDATE = 8  # bilinear: 3 lerps (2 each); accumulate 1; row coordinate 1
+
+
+def lamino_setup(dev):
+    """The laminography workload: random FP16 filtered projections of a
+    2048 x 2048 detector at 2048 angles over a full turn, axis tilted by
+    1.1 rad (63 degrees) from the beam, reconstructed into a 256-slice slab of
+    2048^2 (timing does not depend on the values; parity is checked against
+    the oracle at sampled voxels)."""
+    import numpy as np
+    import torch
+
+    from paper_2209_08450_amd import tp
+
+    c = LAMINO
+    ang = np.arange(c["angles"]) * 2 * math.pi / c["angles"]
+    g = torch.Generator(device=dev).manual_seed(63)
+    filt = torch.randn((c["angles"], c["rows"], c["n"]), generator=g, device=dev, dtype=torch.float16)
+    plan = tp.Plan(ang, c["n"], c["n"] / 2 - 0.5, c["n"])
+    tp.lamino_prepare(plan, c["tilt"], c["center_v"], c["slices"])
+    return plan, filt, ang
+
+
+def bench_lamino(args, log):
+    """Laminographic backprojection of the slab workload: time per call (HIP
+    events on the launch stream), updates/s, roofline, sampled parity."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2209_08450_amd import tp
+
+    dev = torch.device("cuda:0")
+    c = LAMINO
+    plan, filt, ang = lamino_setup(dev)
+    out = torch.empty((c["slices"], c["n"], c["n"]), dtype=torch.float32, device=dev)
+
+    def run():
+        tp.lamino_backproject(plan, filt, c["tilt"], c["center_v"], c["slices"], out=out)
+
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(max(args.steps, 2)):
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    updates = float(c["n"]) ** 2 * c["slices"] * c["angles"]
+    achieved = LAMINO_FLOP_PER_UPDATE * updates / (ms * 1e-3) / 1e12
+    log(f"[lamino] {ms:.1f} ms per call, {updates / (ms * 1e-3) / 1e12:.2f}e12 updates/s, "
+        f"{achieved:.1f} TFLOP/s algorithmic")
+    # parity at full detector and slab size on every 64th angle (32 angles),
+    # so the FP64 oracle's copy of the projections stays near 1 GB
+    sub = slice(0, c["angles"], 64)
+    plan_s = tp.Plan(ang[sub], c["n"], plan.center, c["n"])
+    filt_s = filt[sub].contiguous()
+    tp.lamino_backproject(plan_s, filt_s, c["tilt"], c["center_v"], c["slices"], out=out)
+    rng = np.random.default_rng(7)
+    ix, iy, iz = rng.integers(0, c["n"], 64), rng.integers(0, c["n"], 64), rng.integers(0, c["slices"], 64)
+    got = out[torch.from_numpy(iz).to(dev), torch.from_numpy(iy).to(dev), torch.from_numpy(ix).to(dev)].cpu().numpy()
+    q = filt_s.float().cpu().numpy().astype(np.float64)
+    want = oracle.lamino_backproject_points(q, ang[sub], plan.center, c["center_v"], c["tilt"], c["n"], c["slices"],
+                                            ix, iy, iz)
+    rel = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    log(f"[lamino] rel-L2 vs FP64 oracle (32 angles, 64 voxels): {rel:.2e}")
+    plan_s.close()
+    plan.close()
+    return {
+        "workload": f"{c['slices']} x {c['n']}^2 slab from {c['angles']} angles over 360 degrees of a "
+                    f"{c['rows']} x {c['n']} detector, axis tilted {c['tilt']} rad from the beam, FP16 projections",
+        "ms_per_call": round(ms, 3),
+        "gups": round(updates / (ms * 1e-3) / 1e9, 1),
+        "rel_l2_vs_fp64_oracle_sampled": rel,
+        "parity_sample": "64 voxels, the same slab from every 64th angle (32 angles)",
+        "roofline": {"bound": "alu", "kernel": "k_lamino", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "flop_per_update": LAMINO_FLOP_PER_UPDATE},
+    }
+
+
+def main_single_lamino(args):
+    """One laminographic backprojection of the slab workload (a short program for profiler runs)."""
+    import torch
+
+    from paper_2209_08450_amd import tp
+
+    dev = torch.device("cuda:0")
+    c = LAMINO
+    plan, filt, ang = lamino_setup(dev)
+    out = torch.empty((c["slices"], c["n"], c["n"]), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    tp.lamino_backproject(plan, filt, c["tilt"], c["center_v"], c["slices"], out=out)
+    torch.cuda.synchronize()
+    log("single laminographic backprojection done")
+    plan.close()
 
 
 def main_single_fourier(args):

@@ -12,14 +12,16 @@
 // Work-group: a 32 x 32 tile of (x, y) voxels and kLamK consecutive slices;
 // thread (tx, ty) owns voxels (tx, ty + 8 i), i < 4, of every slice.  Angles
 // are processed kLamA at a time: for each, the window of the projection that
-// the tile's voxels can reach (at most kLamRows rows x kLamCols columns:
-// the column range of a 32-voxel tile is < 31 sqrt(2) + 2, the row range
-// < 31 sqrt(2) |cos phi| + (kLamK - 1) sin phi + 2) is staged in LDS as FP32.
-// The column coordinate u is the backprojector's split expression (the plan's
-// tile tables, integer + FP32 fraction); the row coordinate v uses tables of
-// the same split form per tile edge and per slice, so both keep FP32
-// precision at any detector size, and each slice's coordinates are the same
-// however the volume is split into calls.  Every LDS index is clamped into the staged
+// the tile's voxels can reach (kLamCols columns: the column range of a
+// 32-voxel tile is < 31 sqrt(2) + 2; and at most 31 sqrt(2) |cos phi| +
+// (kLamK - 1) sin phi + 6 rows, sized per launch from the tilt) is staged in
+// LDS as FP32 pairs (sample, next column's sample minus it), so a bilinear
+// tap is one 16-byte read and two FMAs across the columns.  The column
+// coordinate u is the backprojector's split expression (the plan's tile
+// tables, integer + FP32 fraction); the row coordinate v uses tables of the
+// same split form per tile edge and per slice, so both keep FP32 precision at
+// any detector size, and each slice's coordinates are the same however the
+// volume is split into calls.  Every LDS index is clamped into the staged
 // window, which the window bounds (from the tile's corners, with one sample
 // of margin) make a no-op.
 #include "tp_internal.h"
@@ -27,16 +29,19 @@
 namespace tp {
 namespace {
 
-constexpr int kLamK = 4;      // slices per work-group
+constexpr int kLamK = 8;      // slices per work-group
 constexpr int kLamA = 4;      // angles staged per block
 constexpr int kLamCols = 48;  // staged columns
-constexpr int kLamRows = 64;  // staged rows (at most)
+constexpr int kLamRows = 64;  // staged rows (at most; a launch sizes its windows from the tilt)
+constexpr int kLamRowBatch = 3;  // window rows whose loads a lane issues before it waits
+static_assert(kLamA * 64 == 256, "one wave of the 256-thread work-group stages each angle's window");
 
 template <typename TI>
 __global__ void __launch_bounds__(256)
 k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int nz, float scale,
-         float* __restrict__ vol) {
-    __shared__ float win[kLamA][kLamRows][kLamCols];
+         float* __restrict__ vol, int wrows) {
+    // [kLamA][wrows][kLamCols] float2: windows of wrows rows (sized from the tilt by the launcher)
+    extern __shared__ float win_mem[];
     __shared__ int s_ci[kLamA], s_ri[kLamA], s_nr[kLamA];   // window origin (column, row), rows staged
     __shared__ int s_ui[kLamA], s_vi[kLamA];                // integer parts of the tile origin's u, v (x, y terms)
     __shared__ float s_uf[kLamA], s_vf[kLamA];              // FP32 fractions of the same
@@ -88,36 +93,92 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
             const int rhi = vi + hi + 2;
             s_ci[threadIdx.x] = ci;
             s_ri[threadIdx.x] = ri;
-            s_nr[threadIdx.x] = min(rhi - ri + 1, kLamRows);
+            s_nr[threadIdx.x] = min(rhi - ri + 1, wrows);
             s_ui[threadIdx.x] = ui;
             s_uf[threadIdx.x] = uf;
             s_vi[threadIdx.x] = vi;
             s_vf[threadIdx.x] = vf;
         }
         __syncthreads();
-        // stage the windows: rows r < nr, all kLamCols columns (zeros off the detector)
-        for (int j = 0; j < cnt; ++j) {
-            const int a = a0 + j;
-            const int nr = s_nr[j], r0 = s_ri[j], c0 = s_ci[j];
-            const TI* img = filt + static_cast<int64_t>(a) * t.rows * n;
-            for (int e = threadIdx.x; e < nr * kLamCols; e += blockDim.x) {
-                const int r = e / kLamCols, c = e - r * kLamCols;
-                const int row = r0 + r, col = c0 + c;
-                float v = 0.0f;
-                if (row >= 0 && row < t.rows && col >= 0 && col < n)
-                    v = load_as_float(img, static_cast<int64_t>(row) * n + col);
-                win[j][r][c] = v;
+        // stage the windows: wave j stages angle j's rows r < nr as pairs
+        // (sample at column c, sample at c + 1 minus it), c < kLamCols, zeros
+        // off the detector.  Lane (lr, lc) = (lane / 16, lane % 16) stages
+        // columns lc + 16 m (m < 3) of rows lr + 4 b.  Every load reads an
+        // in-bounds sample (an element off the detector reads the image's
+        // first one and is replaced by zero afterwards); the empty asm uses
+        // make each load unconditional, so a batch of kLamRowBatch rows of
+        // loads is issued before its first wait.
+        {
+            // the wave's angle, made scalar so the image base lives in scalar registers
+            const int j = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+            const int lane = threadIdx.x & 63;
+            if (j < cnt) {
+                const int nr = s_nr[j], r0 = s_ri[j], c0 = s_ci[j];
+                const TI* img = filt + static_cast<int64_t>(a0 + j) * t.rows * n;
+                const int lr = lane >> 4, lc = lane & 15;
+                int col[3][2];
+                bool cin[3][2];
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int c = c0 + lc + 16 * m + h;
+                        cin[m][h] = c >= 0 && c < n;
+                        col[m][h] = cin[m][h] ? c : 0;
+                    }
+                float2* w = reinterpret_cast<float2*>(win_mem) + j * wrows * kLamCols + lc;
+                for (int r = lr; r < nr; r += 4 * kLamRowBatch) {
+                    float x[kLamRowBatch][3][2];
+                    bool rin[kLamRowBatch];
+#pragma unroll
+                    for (int b = 0; b < kLamRowBatch; ++b) {
+                        const int rr = r + 4 * b, row = r0 + rr;
+                        rin[b] = rr < nr && row >= 0 && row < t.rows;
+                        // rows * n < 2^31 (checked by the host): 32-bit offsets from the image's base
+                        const unsigned base = rin[b] ? static_cast<unsigned>(row * n) : 0u;
+#pragma unroll
+                        for (int m = 0; m < 3; ++m)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h)
+                                x[b][m][h] = load_as_float(img + (base + static_cast<unsigned>(col[m][h])), 0);
+                    }
+#pragma unroll
+                    for (int b = 0; b < kLamRowBatch; ++b)
+#pragma unroll
+                        for (int m = 0; m < 3; ++m)
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) asm volatile("" : "+v"(x[b][m][h]));
+#pragma unroll
+                    for (int b = 0; b < kLamRowBatch; ++b) {
+                        const int rr = r + 4 * b;
+                        if (rr < nr) {
+#pragma unroll
+                            for (int m = 0; m < 3; ++m) {
+                                const float v0 = (rin[b] && cin[m][0]) ? x[b][m][0] : 0.0f;
+                                const float v1 = (rin[b] && cin[m][1]) ? x[b][m][1] : 0.0f;
+                                w[rr * kLamCols + 16 * m] = make_float2(v0, v1 - v0);
+                            }
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
             const int a = a0 + j;
             const float cs = g.cs[a], sn = g.sn[a], dvx = t.dvdx[a], dvy = t.dvdy[a];
-            const int ubase = s_ui[j] - s_ci[j], vbase = s_vi[j] - s_ri[j], nr = s_nr[j];
+            const int ubase = s_ui[j] - s_ci[j], vbase = s_vi[j] - s_ri[j];
+            // the largest row index a bilinear read may start at; the unsigned
+            // clamp also sends a negative index there (reads stay in the window)
+            const unsigned rmax = static_cast<unsigned>(s_nr[j] - 2);
             const float uf = s_uf[j], vf = s_vf[j];
             float cz[kLamK];  // the slice's row fraction plus the tile origin's (uniform)
+            int rb[kLamK];    // the slice's integer row offset into the window (uniform)
 #pragma unroll
-            for (int k = 0; k < kLamK; ++k) cz[k] = vf + fz[k];
+            for (int k = 0; k < kLamK; ++k) {
+                cz[k] = vf + fz[k];
+                rb[k] = vbase + iz[k];
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float dy = static_cast<float>(ty + 8 * i);
@@ -125,15 +186,18 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
                 const int c = min(max(coord_floor(u) + ubase, 0), kLamCols - 2);
                 const float wu = coord_frac(u);
                 const float va = __builtin_fmaf(dx, dvx, dy * dvy);  // the voxel's in-tile row offset
+                // byte offset of (angle j, row 0, column c) in the windows
+                const unsigned cb = static_cast<unsigned>((j * wrows * kLamCols + c) * sizeof(float2));
 #pragma unroll
                 for (int k = 0; k < kLamK; ++k) {
                     const float v = va + cz[k];
-                    const int r = min(max(coord_floor(v) + vbase + iz[k], 0), nr - 2);
+                    const unsigned r = min(static_cast<unsigned>(coord_floor(v) + rb[k]), rmax);
                     const float wv = coord_frac(v);
-                    const float q00 = win[j][r][c], q01 = win[j][r][c + 1];
-                    const float q10 = win[j][r + 1][c], q11 = win[j][r + 1][c + 1];
-                    const float top = __builtin_fmaf(wu, q01 - q00, q00);
-                    const float bot = __builtin_fmaf(wu, q11 - q10, q10);
+                    const float2* p = reinterpret_cast<const float2*>(
+                        reinterpret_cast<const char*>(win_mem) + (__umul24(r, kLamCols * sizeof(float2)) + cb));
+                    const float2 e0 = p[0], e1 = p[kLamCols];
+                    const float top = __builtin_fmaf(wu, e0.y, e0.x);
+                    const float bot = __builtin_fmaf(wu, e1.y, e1.x);
                     acc[i][k] += __builtin_fmaf(wv, bot - top, top);
                 }
             }
@@ -155,7 +219,18 @@ template <typename TI>
 hipError_t launch_lamino_t(const GeoTables& g, const LaminoTables& t, const void* filt, int z0, int nz, float scale,
                            float* vol, hipStream_t st) {
     const dim3 grid(static_cast<unsigned>(g.nb * g.nb), static_cast<unsigned>((nz + kLamK - 1) / kLamK));
-    hipLaunchKernelGGL((k_lamino<TI>), grid, dim3(256), 0, st, g, t, static_cast<const TI*>(filt), z0, nz, scale, vol);
+    // rows a tile's window can span: 31 sqrt(2) |cos phi| + (kLamK - 1) sin phi, plus the second tap,
+    // the one-row margins on both sides and FP32 slack
+    const float span = 31.0f * 1.41421356f * fabsf(t.dvdcos) + (kLamK - 1) * t.dvdz;
+    const int wrows = min(kLamRows, static_cast<int>(span) + 6);
+    const size_t lds = sizeof(float2) * kLamA * wrows * kLamCols;
+    if (lds > 65536) {  // small tilts: windows above the default dynamic LDS limit (at most 96 KiB)
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_lamino<TI>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_lamino<TI>), grid, dim3(256), lds, st, g, t, static_cast<const TI*>(filt), z0, nz, scale,
+                       vol, wrows);
     return hipGetLastError();
 }
 

@@ -510,6 +510,7 @@ tp_status lamino_tables(const tp_plan* plan, double tilt, double center_v, int N
     t.dvdx = reinterpret_cast<const float*>(d_dx);
     t.dvdy = reinterpret_cast<const float*>(d_dy);
     t.dvdz = static_cast<float>(sphi);
+    t.dvdcos = static_cast<float>(cphi);
     t.Nz = Nz;
     t.rows = 0;
     plan->lam.emplace(key, le);
@@ -920,6 +921,8 @@ tp_status tp_lamino_backproject(const tp_plan* plan, const void* filt, tp_dtype 
     if (!filt || !vol) return fail(TP_EINVAL, "null filt or vol");
     if (!valid_dtype(in_dtype)) return fail(TP_EINVAL, "bad dtype %d", in_dtype);
     if (det_rows <= 0) return fail(TP_EINVAL, "det_rows=%d must be positive", det_rows);
+    if (static_cast<int64_t>(det_rows) * plan->n >= (int64_t{1} << 31))
+        return fail(TP_EINVAL, "det_rows=%d x n_det=%d samples per projection exceed 2^31", det_rows, plan->n);
     if (z0 < 0 || nz <= 0 || z0 + static_cast<int64_t>(nz) > n_slices)
         return fail(TP_EINVAL, "slices [%d, %d) outside [0, %d)", z0, z0 + nz, n_slices);
     if ((nz + tp::lamino_slices_per_block() - 1) / tp::lamino_slices_per_block() > 65535)

@@ -91,6 +91,7 @@ struct LaminoTables {
     const float* dvdx; // [na]     -sin(theta) cos(phi), FP32
     const float* dvdy; // [na]      cos(theta) cos(phi)
     float dvdz;        //          sin(phi)
+    float dvdcos;      //          cos(phi)
     int Nz;            // slices of the whole volume
     int rows;          // detector rows of the projections (per call)
 };

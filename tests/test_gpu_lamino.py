@@ -27,10 +27,11 @@ def _case(seed, na, rows, n):
     return q, ang
 
 
-@pytest.mark.parametrize("tilt", [0.45, 1.1, 2.4])
+@pytest.mark.parametrize("tilt", [0.05, 0.45, 1.1, 2.4])
 def test_lamino_matches_oracle(tp, tilt):
     # 40 angles over a full turn, 30 detector rows x 50 columns, a 45^2 x 13
-    # volume (tiles of 32 past the edge, slice blocks of 4 with a ragged end)
+    # volume (tiles of 32 past the edge, slice blocks of 8 with a ragged end);
+    # tilt 0.05 needs windows of 50 rows (more than 64 KiB of LDS)
     q, ang = _case(1, 40, 30, 50)
     N, Nz, cu, cv = 45, 13, 24.3, 14.6
     plan = tp.Plan(ang, 50, cu, N)
