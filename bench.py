@@ -105,6 +105,26 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
+def load_lamino_traffic():
+    """HBM traffic per laminography launch from committed rocprofv3 counters,
+    if they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_lamino.json")
+    src = os.path.join(ROOT, "paper_2209_08450_amd", "csrc", "k_lamino.hip")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    if d.get("kernel_sha") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+        return None
+    e = d.get("f16") or {}
+    c = LAMINO
+    if (e.get("n"), e.get("angles"), e.get("slices"), e.get("tilt")) != (c["n"], c["angles"], c["slices"], c["tilt"]):
+        return None
+    return float(e["bytes_per_launch"])
+
+
 def load_traffic(storage: str, chunk: int, n: int, angles: int):
     """HBM traffic per backprojection launch from committed rocprofv3 counters,
     if they were taken on the current kernel source and this launch shape."""
@@ -540,12 +560,13 @@ def bench_lamino(args, log):
         "parity_sample": "64 voxels, the same slab from every 64th angle (32 angles)",
         "roofline": {"bound": "alu", "kernel": "k_lamino", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "flop_per_update": LAMINO_FLOP_PER_UPDATE},
+                     "flop_per_update": LAMINO_FLOP_PER_UPDATE, "traffic": load_lamino_traffic()},
     }
 
 
 def main_single_lamino(args):
-    """One laminographic backprojection of the slab workload (a short program for profiler runs)."""
+    """One laminographic backprojection of the slab workload, then a 1 GiB
+    device copy (a short program for profiler and counter runs)."""
     import torch
 
     from paper_2209_08450_amd import tp
@@ -556,6 +577,11 @@ def main_single_lamino(args):
     out = torch.empty((c["slices"], c["n"], c["n"]), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     tp.lamino_backproject(plan, filt, c["tilt"], c["center_v"], c["slices"], out=out)
+    torch.cuda.synchronize()
+    del out, filt
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)  # calibration copy: 1 GiB read + 1 GiB written
+    b = torch.empty_like(a)
+    b.copy_(a)
     torch.cuda.synchronize()
     log("single laminographic backprojection done")
     plan.close()

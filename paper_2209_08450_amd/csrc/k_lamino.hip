@@ -36,18 +36,35 @@ constexpr int kLamRows = 64;  // staged rows (at most; a launch sizes its window
 constexpr int kLamRowBatch = 3;  // window rows whose loads a lane issues before it waits
 static_assert(kLamA * 64 == 256, "one wave of the 256-thread work-group stages each angle's window");
 
+constexpr int kXcds = 8;  // XCDs of the chip (work-group ids go to them round robin)
+
+// Bijection of [0, total): work-group id b runs on XCD b % kXcds as that
+// XCD's (b / kXcds)-th work-group; XCD x receives items
+// [x q + min(x, r), ...) of the q = total / kXcds (+1 for x < r) it runs.
+__device__ __forceinline__ int lamino_work_item(int b, int total) {
+    const int q = total / kXcds, r = total - q * kXcds;
+    const int x = b % kXcds, s = b / kXcds;
+    return x * q + min(x, r) + s;
+}
+
 template <typename TI>
 __global__ void __launch_bounds__(256)
 k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int nz, float scale,
-         float* __restrict__ vol, int wrows) {
+         float* __restrict__ vol, int wrows, int nzb) {
     // [kLamA][wrows][kLamCols] float2: windows of wrows rows (sized from the tilt by the launcher)
     extern __shared__ float win_mem[];
     __shared__ int s_ci[kLamA], s_ri[kLamA], s_nr[kLamA];   // window origin (column, row), rows staged
     __shared__ int s_ui[kLamA], s_vi[kLamA];                // integer parts of the tile origin's u, v (x, y terms)
     __shared__ float s_uf[kLamA], s_vf[kLamA];              // FP32 fractions of the same
     const int nb = g.nb, na = g.na, N = g.N, n = g.n;
-    const int bx = blockIdx.x % nb, by = blockIdx.x / nb;
-    const int zl0 = blockIdx.y * kLamK;         // first slice of this block, relative to z0
+    // Work item of this work-group: the hardware hands work-group ids to the
+    // XCDs round robin, and the remap gives each XCD a contiguous range of
+    // work items, ordered slice block first, so the slice blocks of one tile
+    // run together on one XCD and share their overlapping windows in its L2.
+    const int w = lamino_work_item(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+    const int tile = w / nzb;
+    const int bx = tile % nb, by = tile / nb;
+    const int zl0 = (w - tile * nzb) * kLamK;   // first slice of this block, relative to z0
     const int zs = z0 + zl0;                    // ... and absolute in the volume
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const float dx = static_cast<float>(tx);
@@ -218,7 +235,8 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
 template <typename TI>
 hipError_t launch_lamino_t(const GeoTables& g, const LaminoTables& t, const void* filt, int z0, int nz, float scale,
                            float* vol, hipStream_t st) {
-    const dim3 grid(static_cast<unsigned>(g.nb * g.nb), static_cast<unsigned>((nz + kLamK - 1) / kLamK));
+    const int nzb = (nz + kLamK - 1) / kLamK;
+    const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(g.nb) * g.nb * nzb));  // < 2^31 (checked by the host)
     // rows a tile's window can span: 31 sqrt(2) |cos phi| + (kLamK - 1) sin phi, plus the second tap,
     // the one-row margins on both sides and FP32 slack
     const float span = 31.0f * 1.41421356f * fabsf(t.dvdcos) + (kLamK - 1) * t.dvdz;
@@ -230,7 +248,7 @@ hipError_t launch_lamino_t(const GeoTables& g, const LaminoTables& t, const void
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_lamino<TI>), grid, dim3(256), lds, st, g, t, static_cast<const TI*>(filt), z0, nz, scale,
-                       vol, wrows);
+                       vol, wrows, nzb);
     return hipGetLastError();
 }
 
