@@ -16,14 +16,17 @@
 // 32-voxel tile is < 31 sqrt(2) + 2; and at most 31 sqrt(2) |cos phi| +
 // (kLamK - 1) sin phi + 6 rows, sized per launch from the tilt) is staged in
 // LDS as FP32 pairs (sample, next column's sample minus it), so a bilinear
-// tap is one 16-byte read and two FMAs across the columns.  The column
-// coordinate u is the backprojector's split expression (the plan's tile
-// tables, integer + FP32 fraction); the row coordinate v uses tables of the
-// same split form per tile edge and per slice, so both keep FP32 precision at
-// any detector size, and each slice's coordinates are the same however the
-// volume is split into calls.  Every LDS index is clamped into the staged
-// window, which the window bounds (from the tile's corners, with one sample
-// of margin) make a no-op.
+// tap is one 16-byte read and two FMAs across the columns.  The blocks of
+// angles are software-pipelined: while a block is accumulated, the table
+// entries of the block after next and the window samples of the next block
+// (up to 4 kLamPre rows) are in flight into registers, and are written to
+// LDS after the block's last read.  The column coordinate u is the
+// backprojector's split expression (the plan's tile tables, integer + FP32
+// fraction); the row coordinate v uses tables of the same split form per
+// tile edge and per slice, so both keep FP32 precision at any detector size,
+// and each slice's coordinates are the same however the volume is split into
+// calls.  Every LDS index is clamped into the staged window, which the window
+// bounds (from the tile's corners, with one sample of margin) make a no-op.
 #include "tp_internal.h"
 
 namespace tp {
@@ -33,7 +36,7 @@ constexpr int kLamK = 8;      // slices per work-group
 constexpr int kLamA = 4;      // angles staged per block
 constexpr int kLamCols = 48;  // staged columns
 constexpr int kLamRows = 64;  // staged rows (at most; a launch sizes its windows from the tilt)
-constexpr int kLamRowBatch = 3;  // window rows whose loads a lane issues before it waits
+constexpr int kLamPre = 8;  // window rows per lane loaded one block ahead (4 kLamPre = 32 rows)
 static_assert(kLamA * 64 == 256, "one wave of the 256-thread work-group stages each angle's window");
 
 constexpr int kXcds = 8;  // XCDs of the chip (work-group ids go to them round robin)
@@ -47,15 +50,58 @@ __device__ __forceinline__ int lamino_work_item(int b, int total) {
     return x * q + min(x, r) + s;
 }
 
+// A stored sample as loaded (its bits, zero-extended to 32), and its value:
+// the conversion is deferred so loads issued a block ahead are not waited for.
+__device__ __forceinline__ uint32_t lam_raw(const float* p) { return __float_as_uint(*p); }
+__device__ __forceinline__ uint32_t lam_raw(const __half* p) { return *reinterpret_cast<const uint16_t*>(p); }
+__device__ __forceinline__ uint32_t lam_raw(const uint16_t* p) { return *p; }
+template <typename TI> __device__ __forceinline__ float lam_value(uint32_t r);
+template <> __device__ __forceinline__ float lam_value<float>(uint32_t r) { return __uint_as_float(r); }
+template <> __device__ __forceinline__ float lam_value<__half>(uint32_t r) {
+    return __half2float(__ushort_as_half(static_cast<unsigned short>(r)));
+}
+template <> __device__ __forceinline__ float lam_value<uint16_t>(uint32_t r) { return __uint_as_float(r << 16); }
+
+// One angle's per-tile table entries, as loaded (summed when used, so the
+// loads of the next block can be in flight during this block's compute).
+struct LamEntry {
+    float cs, sn, dvx, dvy, xf, yf, vxf, vyf;
+    int xi, yi, vxi, vyi;
+};
+
+__device__ __forceinline__ LamEntry lam_entry(const GeoTables& g, const LaminoTables& t, int bx, int by, int a) {
+    LamEntry e;
+    const int na = g.na;
+    e.cs = g.cs[a];
+    e.sn = g.sn[a];
+    e.dvx = t.dvdx[a];
+    e.dvy = t.dvdy[a];
+    e.xi = g.xi[bx * na + a];
+    e.yi = g.yi[by * na + a];
+    e.xf = g.xf[bx * na + a];
+    e.yf = g.yf[by * na + a];
+    e.vxi = t.vxi[bx * na + a];
+    e.vyi = t.vyi[by * na + a];
+    e.vxf = t.vxf[bx * na + a];
+    e.vyf = t.vyf[by * na + a];
+    return e;
+}
+
+// Three work-groups per CU is what the windows' LDS allows at mid tilts, so
+// the kernel may use the registers of three waves per SIMD (168 VGPRs): the
+// next block's window is held in registers while the current one is used.
 template <typename TI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int nz, float scale,
          float* __restrict__ vol, int wrows, int nzb) {
     // [kLamA][wrows][kLamCols] float2: windows of wrows rows (sized from the tilt by the launcher)
     extern __shared__ float win_mem[];
-    __shared__ int s_ci[kLamA], s_ri[kLamA], s_nr[kLamA];   // window origin (column, row), rows staged
-    __shared__ int s_ui[kLamA], s_vi[kLamA];                // integer parts of the tile origin's u, v (x, y terms)
-    __shared__ float s_uf[kLamA], s_vf[kLamA];              // FP32 fractions of the same
+    // per-angle window parameters, double-buffered by block parity: the next
+    // block's are written while the current block's are read
+    __shared__ int s_ci[2][kLamA], s_ri[2][kLamA], s_nr[2][kLamA];  // window origin (column, row), rows staged
+    __shared__ int s_ui[2][kLamA], s_vi[2][kLamA];                  // integer parts of the tile origin's u, v
+    __shared__ float s_uf[2][kLamA], s_vf[2][kLamA];                // FP32 fractions of the same
+    __shared__ float s_cs[2][kLamA], s_sn[2][kLamA], s_dvx[2][kLamA], s_dvy[2][kLamA];
     const int nb = g.nb, na = g.na, N = g.N, n = g.n;
     // Work item of this work-group: the hardware hands work-group ids to the
     // XCDs round robin, and the remap gives each XCD a contiguous range of
@@ -84,22 +130,28 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
 #pragma unroll
         for (int k = 0; k < kLamK; ++k) acc[i][k] = 0.0f;
 
-    for (int a0 = 0; a0 < na; a0 += kLamA) {
-        const int cnt = min(kLamA, na - a0);
-        __syncthreads();  // the previous block's windows are no longer read
-        if (threadIdx.x < cnt) {
-            const int a = a0 + threadIdx.x;
-            const float cs = g.cs[a], sn = g.sn[a];
-            const int ui = g.xi[bx * na + a] + g.yi[by * na + a];
-            const float uf = g.xf[bx * na + a] + g.yf[by * na + a];
-            const int vi = t.vxi[bx * na + a] + t.vyi[by * na + a];
-            const float vf = t.vxf[bx * na + a] + t.vyf[by * na + a];
-            const float dvx = t.dvdx[a], dvy = t.dvdy[a];
+    // the staging wave's angle (scalar) and its lane's place in the 4 x 16 lane grid
+    const int sj = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15;
+    // source lane of the next column: (lc + 1) mod 16 in the same row group
+    const int nbr_lane = (lr << 4) | ((lc + 1) & 15);
+
+    // Setup threads (the first kLamA of wave 0) hold the table entries of the
+    // next block, loaded one block ahead.
+    LamEntry ent{};
+    if (threadIdx.x < kLamA && static_cast<int>(threadIdx.x) < na) ent = lam_entry(g, t, bx, by, threadIdx.x);
+
+    // Window bounds of block b0 (angles b0 .. b0 + cnt - 1) from the held
+    // entries into parameter buffer `buf`, then the entries of the block after.
+    auto setup = [&](int b0, int buf) {
+        const int cnt = min(kLamA, na - b0);
+        if (static_cast<int>(threadIdx.x) < cnt) {
+            const int ui = ent.xi + ent.yi, vi = ent.vxi + ent.vyi;
+            const float uf = ent.xf + ent.yf, vf = ent.vxf + ent.vyf;
             // extremes of the in-tile offsets over the tile's corners, per slice
-            const float umin = fminf(0.0f, 31.0f * cs) + fminf(0.0f, 31.0f * sn);
-            const float vmin = fminf(0.0f, 31.0f * dvx) + fminf(0.0f, 31.0f * dvy);
-            const float vmax = fmaxf(0.0f, 31.0f * dvx) + fmaxf(0.0f, 31.0f * dvy);
-            const int ci = ui + coord_floor(uf + umin) - 1;
+            const float umin = fminf(0.0f, 31.0f * ent.cs) + fminf(0.0f, 31.0f * ent.sn);
+            const float vmin = fminf(0.0f, 31.0f * ent.dvx) + fminf(0.0f, 31.0f * ent.dvy);
+            const float vmax = fmaxf(0.0f, 31.0f * ent.dvx) + fmaxf(0.0f, 31.0f * ent.dvy);
             int lo = 1 << 30, hi = -(1 << 30);
 #pragma unroll
             for (int k = 0; k < kLamK; ++k) {
@@ -108,87 +160,127 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
             }
             const int ri = vi + lo - 1;
             const int rhi = vi + hi + 2;
-            s_ci[threadIdx.x] = ci;
-            s_ri[threadIdx.x] = ri;
-            s_nr[threadIdx.x] = min(rhi - ri + 1, wrows);
-            s_ui[threadIdx.x] = ui;
-            s_uf[threadIdx.x] = uf;
-            s_vi[threadIdx.x] = vi;
-            s_vf[threadIdx.x] = vf;
+            const int q = threadIdx.x;
+            s_ci[buf][q] = ui + coord_floor(uf + umin) - 1;
+            s_ri[buf][q] = ri;
+            s_nr[buf][q] = min(rhi - ri + 1, wrows);
+            s_ui[buf][q] = ui;
+            s_uf[buf][q] = uf;
+            s_vi[buf][q] = vi;
+            s_vf[buf][q] = vf;
+            s_cs[buf][q] = ent.cs;
+            s_sn[buf][q] = ent.sn;
+            s_dvx[buf][q] = ent.dvx;
+            s_dvy[buf][q] = ent.dvy;
+            const int an = b0 + kLamA + q;
+            if (an < na) ent = lam_entry(g, t, bx, by, an);
         }
-        __syncthreads();
-        // stage the windows: wave j stages angle j's rows r < nr as pairs
-        // (sample at column c, sample at c + 1 minus it), c < kLamCols, zeros
-        // off the detector.  Lane (lr, lc) = (lane / 16, lane % 16) stages
-        // columns lc + 16 m (m < 3) of rows lr + 4 b.  Every load reads an
-        // in-bounds sample (an element off the detector reads the image's
-        // first one and is replaced by zero afterwards); the empty asm uses
-        // make each load unconditional, so a batch of kLamRowBatch rows of
-        // loads is issued before its first wait.
-        {
-            // the wave's angle, made scalar so the image base lives in scalar registers
-            const int j = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-            const int lane = threadIdx.x & 63;
-            if (j < cnt) {
-                const int nr = s_nr[j], r0 = s_ri[j], c0 = s_ci[j];
-                const TI* img = filt + static_cast<int64_t>(a0 + j) * t.rows * n;
-                const int lr = lane >> 4, lc = lane & 15;
-                int col[3][2];
-                bool cin[3][2];
+    };
+
+    // Window staging of wave sj's angle of the block whose parameters are in
+    // `buf`: lane (lr, lc) covers columns lc + 16 m (m < 3) of rows lr + 4 p.
+    // The first kLamPre rows per lane are loaded into registers by issue()
+    // (no wait) and written by store(); rows past 4 kLamPre (small tilts
+    // only) are loaded and written by store() itself.  Every load reads an
+    // in-bounds sample; an element off the detector is replaced by zero.
+    uint32_t X[kLamPre][3];
+    auto col_of = [&](int c0, int m, bool* in) {
+        const int c = c0 + lc + 16 * m;
+        *in = c >= 0 && c < n;
+        return *in ? c : 0;
+    };
+    auto issue = [&](int b0, int buf) {
+        if (sj < min(kLamA, na - b0)) {
+            const int nr = s_nr[buf][sj], r0 = s_ri[buf][sj], c0 = s_ci[buf][sj];
+            const TI* img = filt + static_cast<int64_t>(b0 + sj) * t.rows * n;
+            int col[3];
+            bool cin[3];
 #pragma unroll
-                for (int m = 0; m < 3; ++m)
+            for (int m = 0; m < 3; ++m) col[m] = col_of(c0, m, &cin[m]);
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int c = c0 + lc + 16 * m + h;
-                        cin[m][h] = c >= 0 && c < n;
-                        col[m][h] = cin[m][h] ? c : 0;
+            for (int p = 0; p < kLamPre; ++p) {
+                const int rr = lr + 4 * p, row = r0 + rr;
+                const bool rin = rr < nr && row >= 0 && row < t.rows;
+                // rows * n < 2^31 (checked by the host): 32-bit offsets from the image's base
+                const unsigned base = rin ? static_cast<unsigned>(row * n) : 0u;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) X[p][m] = lam_raw(img + (base + static_cast<unsigned>(col[m])));
+            }
+        }
+    };
+    // one row of the window: masked values v[m] at columns lc + 16 m; the
+    // next column's value comes from the neighbouring lane (lane 15 of a row
+    // group takes lane 0's next chunk; column kLamCols, never read, gets 0)
+    auto put_row = [&](float2* wrow, const float v[3], bool store) {
+        const float s0 = __shfl(v[0], nbr_lane), s1 = __shfl(v[1], nbr_lane), s2 = __shfl(v[2], nbr_lane);
+        const bool wrap = lc == 15;
+        const float n0 = wrap ? s1 : s0, n1 = wrap ? s2 : s1, n2 = wrap ? v[2] : s2;
+        if (store) {
+            wrow[0] = make_float2(v[0], n0 - v[0]);
+            wrow[16] = make_float2(v[1], n1 - v[1]);
+            wrow[32] = make_float2(v[2], n2 - v[2]);
+        }
+    };
+    auto store = [&](int b0, int buf) {
+        if (sj < min(kLamA, na - b0)) {
+            const int nr = s_nr[buf][sj], r0 = s_ri[buf][sj], c0 = s_ci[buf][sj];
+            bool cin[3];
+            int col[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) col[m] = col_of(c0, m, &cin[m]);
+            float2* wj = reinterpret_cast<float2*>(win_mem) + sj * wrows * kLamCols + lc;
+#pragma unroll
+            for (int p = 0; p < kLamPre; ++p) {
+                const int rr = lr + 4 * p, row = r0 + rr;
+                const bool rin = rr < nr && row >= 0 && row < t.rows;
+                float v[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    asm volatile("" : "+v"(X[p][m]));
+                    v[m] = (rin && cin[m]) ? lam_value<TI>(X[p][m]) : 0.0f;
+                }
+                put_row(wj + rr * kLamCols, v, rr < nr);
+            }
+            if (nr > 4 * kLamPre) {  // wave-uniform
+                const TI* img = filt + static_cast<int64_t>(b0 + sj) * t.rows * n;
+                for (int rr = lr + 4 * kLamPre; rr - lr < nr; rr += 4) {
+                    const int row = r0 + rr;
+                    const bool rin = rr < nr && row >= 0 && row < t.rows;
+                    const unsigned base = rin ? static_cast<unsigned>(row * n) : 0u;
+                    float v[3];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        const float x = load_as_float(img + (base + static_cast<unsigned>(col[m])), 0);
+                        v[m] = (rin && cin[m]) ? x : 0.0f;
                     }
-                float2* w = reinterpret_cast<float2*>(win_mem) + j * wrows * kLamCols + lc;
-                for (int r = lr; r < nr; r += 4 * kLamRowBatch) {
-                    float x[kLamRowBatch][3][2];
-                    bool rin[kLamRowBatch];
-#pragma unroll
-                    for (int b = 0; b < kLamRowBatch; ++b) {
-                        const int rr = r + 4 * b, row = r0 + rr;
-                        rin[b] = rr < nr && row >= 0 && row < t.rows;
-                        // rows * n < 2^31 (checked by the host): 32-bit offsets from the image's base
-                        const unsigned base = rin[b] ? static_cast<unsigned>(row * n) : 0u;
-#pragma unroll
-                        for (int m = 0; m < 3; ++m)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h)
-                                x[b][m][h] = load_as_float(img + (base + static_cast<unsigned>(col[m][h])), 0);
-                    }
-#pragma unroll
-                    for (int b = 0; b < kLamRowBatch; ++b)
-#pragma unroll
-                        for (int m = 0; m < 3; ++m)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) asm volatile("" : "+v"(x[b][m][h]));
-#pragma unroll
-                    for (int b = 0; b < kLamRowBatch; ++b) {
-                        const int rr = r + 4 * b;
-                        if (rr < nr) {
-#pragma unroll
-                            for (int m = 0; m < 3; ++m) {
-                                const float v0 = (rin[b] && cin[m][0]) ? x[b][m][0] : 0.0f;
-                                const float v1 = (rin[b] && cin[m][1]) ? x[b][m][1] : 0.0f;
-                                w[rr * kLamCols + 16 * m] = make_float2(v0, v1 - v0);
-                            }
-                        }
-                    }
+                    put_row(wj + rr * kLamCols, v, rr < nr);
                 }
             }
         }
-        __syncthreads();
+    };
+
+    // prologue: block 0's parameters and window
+    setup(0, 0);
+    __syncthreads();
+    issue(0, 0);
+    store(0, 0);
+    __syncthreads();
+    for (int a0 = 0; a0 < na; a0 += kLamA) {
+        const int cur = (a0 / kLamA) & 1, nxt = cur ^ 1;
+        const int cnt = min(kLamA, na - a0);
+        const bool more = a0 + kLamA < na;  // uniform
+        if (more) {
+            setup(a0 + kLamA, nxt);
+            __syncthreads();  // the next block's parameters are visible
+            issue(a0 + kLamA, nxt);
+        }
         for (int j = 0; j < cnt; ++j) {
-            const int a = a0 + j;
-            const float cs = g.cs[a], sn = g.sn[a], dvx = t.dvdx[a], dvy = t.dvdy[a];
-            const int ubase = s_ui[j] - s_ci[j], vbase = s_vi[j] - s_ri[j];
+            const float cs = s_cs[cur][j], sn = s_sn[cur][j], dvx = s_dvx[cur][j], dvy = s_dvy[cur][j];
+            const int ubase = s_ui[cur][j] - s_ci[cur][j], vbase = s_vi[cur][j] - s_ri[cur][j];
             // the largest row index a bilinear read may start at; the unsigned
             // clamp also sends a negative index there (reads stay in the window)
-            const unsigned rmax = static_cast<unsigned>(s_nr[j] - 2);
-            const float uf = s_uf[j], vf = s_vf[j];
+            const unsigned rmax = static_cast<unsigned>(s_nr[cur][j] - 2);
+            const float uf = s_uf[cur][j], vf = s_vf[cur][j];
             float cz[kLamK];  // the slice's row fraction plus the tile origin's (uniform)
             int rb[kLamK];    // the slice's integer row offset into the window (uniform)
 #pragma unroll
@@ -205,19 +297,32 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
                 const float va = __builtin_fmaf(dx, dvx, dy * dvy);  // the voxel's in-tile row offset
                 // byte offset of (angle j, row 0, column c) in the windows
                 const unsigned cb = static_cast<unsigned>((j * wrows * kLamCols + c) * sizeof(float2));
+                // all slices' reads first, then the arithmetic, so the LDS
+                // reads of a voxel column are in flight together
+                float2 e0[kLamK], e1[kLamK];
+                float wv[kLamK];
 #pragma unroll
                 for (int k = 0; k < kLamK; ++k) {
                     const float v = va + cz[k];
                     const unsigned r = min(static_cast<unsigned>(coord_floor(v) + rb[k]), rmax);
-                    const float wv = coord_frac(v);
+                    wv[k] = coord_frac(v);
                     const float2* p = reinterpret_cast<const float2*>(
                         reinterpret_cast<const char*>(win_mem) + (__umul24(r, kLamCols * sizeof(float2)) + cb));
-                    const float2 e0 = p[0], e1 = p[kLamCols];
-                    const float top = __builtin_fmaf(wu, e0.y, e0.x);
-                    const float bot = __builtin_fmaf(wu, e1.y, e1.x);
-                    acc[i][k] += __builtin_fmaf(wv, bot - top, top);
+                    e0[k] = p[0];
+                    e1[k] = p[kLamCols];
+                }
+#pragma unroll
+                for (int k = 0; k < kLamK; ++k) {
+                    const float top = __builtin_fmaf(wu, e0[k].y, e0[k].x);
+                    const float bot = __builtin_fmaf(wu, e1[k].y, e1[k].x);
+                    acc[i][k] += __builtin_fmaf(wv[k], bot - top, top);
                 }
             }
+        }
+        if (more) {
+            __syncthreads();  // this block's windows are no longer read
+            store(a0 + kLamA, nxt);
+            __syncthreads();  // the next block's windows are visible
         }
     }
     const int x = bx * 32 + tx;
