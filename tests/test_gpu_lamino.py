@@ -44,6 +44,21 @@ def test_lamino_matches_oracle(tp, tilt):
     assert np.max(np.abs(got - want)) < 1e-5 * np.max(np.abs(want))
 
 
+@pytest.mark.parametrize("na", [1, 3, 5, 37])
+def test_lamino_ragged_angle_blocks(tp, na):
+    # angles are taken 4 at a time, the next block staged while the current
+    # one is summed: a single partial block, one full block plus a partial
+    # one, and a long run ending in a partial block
+    q, ang = _case(8, na, 18, 40)
+    ang = ang * 0.9 + 0.05 * np.arange(na) ** 1.5  # uneven spacing
+    N, Nz, cu, cv = 40, 9, 19.2, 8.6
+    plan = tp.Plan(ang, 40, cu, N)
+    got = to_host(tp.lamino_backproject(plan, to_dev(q), 0.9, cv, Nz)).astype(np.float64)
+    want = oracle.lamino_backproject(q.astype(np.float64), ang, cu, cv, 0.9, N, Nz)
+    assert rel_l2(got, want) < 1e-5
+    assert np.max(np.abs(got - want)) < 1e-5 * np.max(np.abs(want))
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
 def test_lamino_reduced_precision_inputs(tp, storage):
     import torch
