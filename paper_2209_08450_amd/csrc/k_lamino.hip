@@ -359,7 +359,6 @@ hipError_t launch_lamino_t(const GeoTables& g, const LaminoTables& t, const void
 
 }  // namespace
 
-int lamino_max_rows() { return kLamRows; }
 int lamino_slices_per_block() { return kLamK; }
 
 hipError_t launch_lamino(const GeoTables& g, const LaminoTables& t, const void* filt, tp_dtype dt, int z0, int nz,

@@ -123,7 +123,6 @@ hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const
 hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
                                float* vol, hipStream_t st);
 
-int lamino_max_rows();
 int lamino_slices_per_block();
 hipError_t launch_lamino(const GeoTables& g, const LaminoTables& t, const void* filt, tp_dtype dt, int z0, int nz,
                          float scale, float* vol, hipStream_t st);
