@@ -34,7 +34,7 @@ namespace {
 
 constexpr int kLamK = 8;      // slices per work-group
 constexpr int kLamA = 4;      // angles staged per block
-constexpr int kLamCols = 48;  // staged columns
+constexpr int kLamCols = 48;  // staged columns (also the row pitch of a window, in pairs)
 constexpr int kLamRows = 64;  // staged rows (at most; a launch sizes its windows from the tilt)
 constexpr int kLamPre = 8;  // window rows per lane loaded one block ahead (4 kLamPre = 32 rows)
 static_assert(kLamA * 64 == 256, "one wave of the 256-thread work-group stages each angle's window");
@@ -99,9 +99,14 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
     // per-angle window parameters, double-buffered by block parity: the next
     // block's are written while the current block's are read
     __shared__ int s_ci[2][kLamA], s_ri[2][kLamA], s_nr[2][kLamA];  // window origin (column, row), rows staged
-    __shared__ int s_ui[2][kLamA], s_vi[2][kLamA];                  // integer parts of the tile origin's u, v
-    __shared__ float s_uf[2][kLamA], s_vf[2][kLamA];                // FP32 fractions of the same
+    __shared__ int s_ui[2][kLamA];                                  // integer part of the tile origin's u
+    __shared__ float s_uf[2][kLamA];                                // its FP32 fraction
     __shared__ float s_cs[2][kLamA], s_sn[2][kLamA], s_dvx[2][kLamA], s_dvy[2][kLamA];
+    // each slice's row coordinate in the window at the tile origin: fractions
+    // of the slice and the tile origin, plus the slice's integer offset into
+    // the window (a sum rounded in FP32, the same for a slice in any call
+    // since its block is fixed)
+    __shared__ float s_cz[2][kLamA][kLamK];
     const int nb = g.nb, na = g.na, N = g.N, n = g.n;
     // Work item of this work-group: the hardware hands work-group ids to the
     // XCDs round robin, and the remap gives each XCD a contiguous range of
@@ -110,8 +115,9 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
     const int w = lamino_work_item(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
     const int tile = w / nzb;
     const int bx = tile % nb, by = tile / nb;
-    const int zl0 = (w - tile * nzb) * kLamK;   // first slice of this block, relative to z0
-    const int zs = z0 + zl0;                    // ... and absolute in the volume
+    // slice blocks are aligned to multiples of kLamK in the whole volume, so a
+    // slice's block, window and arithmetic do not depend on the call's range
+    const int zs = (z0 / kLamK + (w - tile * nzb)) * kLamK;  // first slice of this block (absolute)
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const float dx = static_cast<float>(tx);
     // each slice's own row term (integer + fraction) from the per-slice table,
@@ -120,7 +126,7 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
     int iz[kLamK];
 #pragma unroll
     for (int k = 0; k < kLamK; ++k) {
-        const int z = min(zs + k, t.Nz - 1);  // slices past the range are computed, never stored
+        const int z = min(zs + k, t.Nz - 1);  // slices outside the call's range are computed, never stored
         fz[k] = t.vzf[z];
         iz[k] = t.vzi[z];
     }
@@ -161,13 +167,13 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
             const int ri = vi + lo - 1;
             const int rhi = vi + hi + 2;
             const int q = threadIdx.x;
+#pragma unroll
+            for (int k = 0; k < kLamK; ++k) s_cz[buf][q][k] = (vf + fz[k]) + static_cast<float>(vi - ri + iz[k]);
             s_ci[buf][q] = ui + coord_floor(uf + umin) - 1;
             s_ri[buf][q] = ri;
             s_nr[buf][q] = min(rhi - ri + 1, wrows);
             s_ui[buf][q] = ui;
             s_uf[buf][q] = uf;
-            s_vi[buf][q] = vi;
-            s_vf[buf][q] = vf;
             s_cs[buf][q] = ent.cs;
             s_sn[buf][q] = ent.sn;
             s_dvx[buf][q] = ent.dvx;
@@ -276,18 +282,14 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
         }
         for (int j = 0; j < cnt; ++j) {
             const float cs = s_cs[cur][j], sn = s_sn[cur][j], dvx = s_dvx[cur][j], dvy = s_dvy[cur][j];
-            const int ubase = s_ui[cur][j] - s_ci[cur][j], vbase = s_vi[cur][j] - s_ri[cur][j];
+            const int ubase = s_ui[cur][j] - s_ci[cur][j];
             // the largest row index a bilinear read may start at; the unsigned
             // clamp also sends a negative index there (reads stay in the window)
             const unsigned rmax = static_cast<unsigned>(s_nr[cur][j] - 2);
-            const float uf = s_uf[cur][j], vf = s_vf[cur][j];
-            float cz[kLamK];  // the slice's row fraction plus the tile origin's (uniform)
-            int rb[kLamK];    // the slice's integer row offset into the window (uniform)
+            const float uf = s_uf[cur][j];
+            float cz[kLamK];
 #pragma unroll
-            for (int k = 0; k < kLamK; ++k) {
-                cz[k] = vf + fz[k];
-                rb[k] = vbase + iz[k];
-            }
+            for (int k = 0; k < kLamK; ++k) cz[k] = s_cz[cur][j][k];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float dy = static_cast<float>(ty + 8 * i);
@@ -303,8 +305,8 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
                 float wv[kLamK];
 #pragma unroll
                 for (int k = 0; k < kLamK; ++k) {
-                    const float v = va + cz[k];
-                    const unsigned r = min(static_cast<unsigned>(coord_floor(v) + rb[k]), rmax);
+                    const float v = va + cz[k];  // row in the window
+                    const unsigned r = min(static_cast<unsigned>(coord_floor(v)), rmax);
                     wv[k] = coord_frac(v);
                     const float2* p = reinterpret_cast<const float2*>(
                         reinterpret_cast<const char*>(win_mem) + (__umul24(r, kLamCols * sizeof(float2)) + cb));
@@ -331,8 +333,9 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
         const int y = by * 32 + ty + 8 * i;
 #pragma unroll
         for (int k = 0; k < kLamK; ++k) {
-            const int zl = zl0 + k;
-            if (x < N && y < N && zl < nz) vol[(static_cast<int64_t>(zl) * N + y) * N + x] = scale * acc[i][k];
+            const int zl = zs + k - z0;  // index in the call's output
+            if (x < N && y < N && zl >= 0 && zl < nz)
+                vol[(static_cast<int64_t>(zl) * N + y) * N + x] = scale * acc[i][k];
         }
     }
 }
@@ -340,7 +343,7 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
 template <typename TI>
 hipError_t launch_lamino_t(const GeoTables& g, const LaminoTables& t, const void* filt, int z0, int nz, float scale,
                            float* vol, hipStream_t st) {
-    const int nzb = (nz + kLamK - 1) / kLamK;
+    const int nzb = (z0 + nz - 1) / kLamK - z0 / kLamK + 1;  // blocks aligned to multiples of kLamK
     const dim3 grid(static_cast<unsigned>(static_cast<int64_t>(g.nb) * g.nb * nzb));  // < 2^31 (checked by the host)
     // rows a tile's window can span: 31 sqrt(2) |cos phi| + (kLamK - 1) sin phi, plus the second tap,
     // the one-row margins on both sides and FP32 slack

@@ -925,8 +925,9 @@ tp_status tp_lamino_backproject(const tp_plan* plan, const void* filt, tp_dtype 
         return fail(TP_EINVAL, "det_rows=%d x n_det=%d samples per projection exceed 2^31", det_rows, plan->n);
     if (z0 < 0 || nz <= 0 || z0 + static_cast<int64_t>(nz) > n_slices)
         return fail(TP_EINVAL, "slices [%d, %d) outside [0, %d)", z0, z0 + nz, n_slices);
+    const int kb = tp::lamino_slices_per_block();  // slice blocks are aligned to multiples of kb
     const int64_t lam_blocks = static_cast<int64_t>(plan->geo.nb) * plan->geo.nb *
-                               ((nz + tp::lamino_slices_per_block() - 1) / tp::lamino_slices_per_block());
+                               ((static_cast<int64_t>(z0) + nz - 1) / kb - z0 / kb + 1);
     if (lam_blocks >= (int64_t{1} << 31)) return fail(TP_EINVAL, "nz=%d too large for one call", nz);
     if (!std::isfinite(scale)) return fail(TP_EINVAL, "scale is not finite");
     auto st = static_cast<hipStream_t>(stream);
