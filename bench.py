@@ -100,6 +100,18 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name (for the oracle baseline), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_source_hash() -> str:
     p = os.path.join(ROOT, "paper_2209_08450_amd", "csrc", "k_backproject.hip")
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
@@ -312,7 +324,7 @@ def main():
                "kind": "oracle",
                "sample": f"{cpu_slices} full slices of the workload ({na} angles x {n} cols -> {n}^2; "
                          f"normalise, filter, backproject in FP64), {cpu_t:.1f} s",
-               "s_per_volume_extrapolated": round(cpu_t / cpu_slices * rows, 1)}
+               "s_per_volume_extrapolated": round(cpu_t / cpu_slices * rows, 1), "cpu_model": host_cpu_model()}
 
     # ---------------- Fourier-domain FBP on the same scan ----------------
     fourier = None
