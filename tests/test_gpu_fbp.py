@@ -113,6 +113,32 @@ def test_fbp_paper_scale_sampled(tp):
     assert max(e16) < 3e-3
 
 
+def test_fbp_bench_launch_shape_sampled(tp):
+    """The launch the 2048^3 benchmark times: one 256-row chunk of 2048 angles
+    x 2048 columns (default tuning, all three storage types) of a 12-bit
+    ellipsoid scan generated on the GPU; three rows spread over the chunk (its
+    first and last slice blocks included) checked at 512 sampled voxels each."""
+    import torch
+    s = synth.ellipsoid_scan_torch(seed=5, n_angles=2048, n_rows=256, n_det=2048, device="cuda", center=1024.0)
+    rows = [0, 129, 255]
+    host = {name: getattr(s, name)[:, rows].cpu().numpy().view(np.uint16) for name in ("proj", "dark", "flat")}
+    plan = tp.Plan(s.angles, 2048, s.center)
+    rng = np.random.default_rng(3)
+    pts = [(rng.integers(0, 2048, 512), rng.integers(0, 2048, 512)) for _ in rows]
+    want = [oracle.fbp_points(host["proj"][:, i], host["dark"][:, i], host["flat"][:, i], s.angles, s.center, 2048,
+                              ix, iy) for i, (ix, iy) in enumerate(pts)]
+    for storage, tol in (("f32", 1e-5), ("f16", 3e-3), ("bf16", 3e-3)):
+        note(f"fbp 2048 x 256 x 2048 {storage}")
+        vol = tp.fbp_chunk(plan, s.proj, s.dark, s.flat, storage)
+        got = vol[rows].cpu().numpy().astype(np.float64)
+        del vol
+        torch.cuda.empty_cache()
+        errs = [rel_l2(got[i][iy, ix], want[i]) for i, (ix, iy) in enumerate(pts)]
+        note(f"{storage} rel-L2 {errs}")
+        assert max(errs) < tol
+    plan.close()
+
+
 @pytest.mark.parametrize("kind", ["shepp", "parzen"])
 def test_fbp_windowed_filters(tp, scan16, kind):
     # the paper's filter choices; Parzen is its default
