@@ -152,6 +152,33 @@ def test_fourier_paper_geometry_sampled(tp):
     torch.cuda.empty_cache()
 
 
+def test_fourier_bench_launch_shape_sampled(tp):
+    """The launch the benchmark times: one 256-row chunk of 2048 angles x 2048
+    columns (128 slice pairs in one pass, grid side 4096) of a 12-bit
+    ellipsoid scan generated on the GPU; three rows spread over the chunk
+    checked at 40 sampled voxels each against the oracle's direct sum."""
+    import torch
+    s = synth.ellipsoid_scan_torch(seed=6, n_angles=2048, n_rows=256, n_det=2048, device="cuda", center=1024.0)
+    rows = [0, 129, 255]
+    host = {name: getattr(s, name)[:, rows].cpu().numpy().view(np.uint16) for name in ("proj", "dark", "flat")}
+    plan = tp.Plan(s.angles, 2048, s.center)
+    note("fourier 2048 x 256 x 2048")
+    vol = tp.fourier_fbp_chunk(plan, s.proj, s.dark, s.flat)
+    got = vol[rows].cpu().numpy().astype(np.float64)
+    del vol
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(13)
+    errs = []
+    for i in range(len(rows)):
+        ix, iy = rng.integers(0, 2048, 40), rng.integers(0, 2048, 40)
+        want = oracle.fourier_fbp_points(host["proj"][:, i], host["dark"][:, i], host["flat"][:, i], s.angles,
+                                         s.center, 2048, ix, iy)
+        errs.append(rel_l2(got[i, iy, ix], want))
+    note(f"rel-L2 at sampled voxels {errs}")
+    assert max(errs) < 1e-5, errs
+    plan.close()
+
+
 @pytest.mark.parametrize("n", [512, 4096])
 def test_fourier_register_transform_sizes(tp, n):
     # pad length and grid side 1024 (n = 512) and 8192 (n = 4096): the
