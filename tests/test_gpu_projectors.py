@@ -280,3 +280,35 @@ def test_radon_32_slice_groups(tp):
     # each slice alone gives the same bits as inside the group
     one = to_host(tp.radon(plan, to_dev(np.ascontiguousarray(x[33:34])))).astype(np.float64)
     assert np.array_equal(one[0], got[33])
+
+
+def test_projector_pair_differentiation_shape(tp):
+    # the least-squares workload's calls: 128 slices of 1024^2 from 900 angles
+    # (four 32-slice groups per launch), random volume; two whole slices of
+    # R f (the first and the last of the call) against the oracle, and the
+    # adjoint on the same shape by the dot-product identity
+    import torch
+    na, n, rows = 900, 1024, 128
+    ang = synth.uniform_angles(na)
+    plan = tp.Plan(ang, n, 511.5)
+    gen = torch.Generator(device="cuda").manual_seed(44)
+    x = torch.randn((rows, n, n), generator=gen, device="cuda")
+    note("radon 128 x 1024^2 x 900")
+    r = tp.radon(plan, x)
+    zs = [0, rows - 1]
+    xs = x[zs].cpu().numpy().astype(np.float64)
+    got = r[zs].cpu().numpy().astype(np.float64)
+    want = oracle.radon(xs, ang, 511.5, n)
+    errs = [rel_l2(got[i], want[i]) for i in range(len(zs))]
+    note(f"radon rel-L2 {errs}")
+    assert max(errs) < 1e-5
+    # <R x, y> = <x, R^T y> over the whole call with y = R x (both sides are
+    # |R x|^2, far from zero, so FP32 rounding stays a small relative error);
+    # sums in FP64
+    bt = tp.backproject(plan, r, scale=1.0)
+    lhs = float(torch.sum(r.double() * r.double()))
+    rhs = float(torch.sum(x.double() * bt.double()))
+    note(f"dot products {lhs} {rhs}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    del x, r, bt
+    torch.cuda.empty_cache()
