@@ -81,7 +81,11 @@ typedef struct {
 typedef struct tp_plan tp_plan;
 
 tp_status tp_plan_create(const tp_geometry* g, tp_plan** out);
-/* Frees the plan's tables; the caller must ensure no enqueued work still uses them. */
+/* Frees the plan's tables, including those built later on first use (the
+ * Fourier path's per window and truncation radius, laminography's per tilt,
+ * centre_v and slice count: about 2 MB each at 2048 angles x 2048 voxels).
+ * Those are kept until this call, since graph-captured launches refer to
+ * them; the caller must ensure no enqueued work still uses them. */
 tp_status tp_plan_destroy(tp_plan* plan);
 
 /* Tuning of the backprojection kernel for one storage type of its input
