@@ -100,6 +100,23 @@ def parse():
     return ap.parse_args()
 
 
+PEAK_HBM_GBS = 8000.0
+STORAGE_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
+
+
+def filter_roofline(storage: str, ms_per_volume: float, n_angles: int, rows: int, n_det: int) -> dict:
+    """Roofline entry of k_norm_filter for one volume: algorithmic bytes (2 B
+    raw in + the filtered sample out per sample; the dark/flat tables are
+    FP32 per row and column, negligible) over its measured time."""
+    nbytes = float(n_angles) * rows * n_det * (2 + STORAGE_BYTES[storage])
+    gbs = nbytes / (ms_per_volume * 1e-3) / 1e9 if ms_per_volume > 0 else None
+    return {"bound": "hbm", "kernel": "k_norm_filter_reg", "achieved": round(gbs, 1) if gbs else None,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4) if gbs else None,
+            "bytes_per_volume": nbytes, "ms_per_volume": round(ms_per_volume, 2),
+            "note": "moves exactly its algorithmic bytes (FETCH_SIZE / WRITE_SIZE); its time is the FFT arithmetic "
+                    "in registers and LDS, about 4 % of a volume's time"}
+
+
 def host_cpu_model() -> str:
     """The host CPU's model name (for the oracle baseline), or "unknown"."""
     try:
@@ -378,6 +395,11 @@ def main():
                      "traffic": traffic,
                      "launch_ms": round(r["bp_launch_ms"], 3),
                      "flop_per_launch": FLOP_PER_UPDATE * bp_updates},
+        # the fused normalise + filter kernel: HBM-class work (uint16 raw sample
+        # in, one filtered sample out in the storage type, per sample of the
+        # scan), from the HIP events around its launches
+        "filter_roofline": {st: filter_roofline(st, results[st]["stage_ms_per_step"]["norm_filter"], na, rows, n)
+                            for st in storages},
         "cpu_baseline": cpu,
         "differentiation": ls,
         "fourierrec": fourier,

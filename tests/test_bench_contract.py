@@ -58,3 +58,12 @@ def test_traffic_records_describe_their_launch(bench):
 def test_fourier_work_count(bench):
     # (L + 1) samples per angle and slice pair, each meeting (2h)^2 grid points at 6 flop
     assert bench.fourier_flop_per_pair(2048, 4096, 6) == 2048 * 4097 * 144 * 6
+
+
+def test_filter_roofline_bytes(bench):
+    # 2048^3 scan, FP16 storage: 2 B raw in + 2 B filtered out per sample
+    e = bench.filter_roofline("f16", 50.0, 2048, 2048, 2048)
+    assert e["bytes_per_volume"] == 2048 ** 3 * 4
+    assert abs(e["achieved"] - 2048 ** 3 * 4 / 0.05 / 1e9) < 0.1
+    assert e["frac"] == round(e["achieved"] / 8000.0, 4)
+    assert bench.filter_roofline("f32", 50.0, 2, 3, 4)["bytes_per_volume"] == 2 * 3 * 4 * 6
