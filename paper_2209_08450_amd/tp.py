@@ -144,6 +144,21 @@ def _dev(t, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _out(out, shape, dtype, like, name="out"):
+    """A caller's output tensor checked against what the kernels will write
+    (the C ABI receives a bare pointer), or a new one on ``like``'s device."""
+    torch = _torch()
+    shape = tuple(int(v) for v in shape)
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=like.device)
+    if out.dtype != dtype or tuple(out.shape) != shape or not out.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {list(shape)}, "
+                         f"got {out.dtype} {list(out.shape)}")
+    if not out.is_cuda or out.device != like.device:
+        raise ValueError(f"{name} must be on {like.device}")
+    return out
+
+
 def _raw_strides(t, name, n_det):
     """(pointer, outer stride) of a [outer][rows][n_det] uint16 view with packed rows."""
     torch = _torch()
@@ -257,8 +272,7 @@ def normalize(proj, dark, flat, out_dtype="f32", out=None, workspace=None, strea
     if dark.shape[1] != n_rows or flat.shape[1] != n_rows:
         raise ValueError("dark/flat rows must match proj rows")
     code = dtype_code(out_dtype)
-    if out is None:
-        out = torch.empty((n_rows, n_angles, n_det), dtype=torch_dtype(code), device=proj.device)
+    out = _out(out, (n_rows, n_angles, n_det), torch_dtype(code), proj)
     ws_need = int(_normalize_ws(n_rows, n_det))
     if workspace is None:
         workspace = _workspace(ws_need, proj.device)
@@ -278,8 +292,7 @@ def filter(sino, out_dtype=None, out=None, pad_len: int = 0, kind="ramp", stream
     out_code = in_code if out_dtype is None else dtype_code(out_dtype)
     n_det = int(sino.shape[-1])
     n_lines = int(sino.numel() // n_det)
-    if out is None:
-        out = torch.empty(sino.shape, dtype=torch_dtype(out_code), device=sino.device)
+    out = _out(out, sino.shape, torch_dtype(out_code), sino)
     _check(_filter(_dev(sino, "sino"), in_code, _dev(out, "out"), out_code, n_lines, n_det, int(pad_len),
                    filter_code(kind), _stream_ptr(stream)))
     return out
@@ -315,8 +328,7 @@ def radon(plan: Plan, vol, out=None, workspace=None, stream=None):
             or not vol.is_contiguous():
         raise ValueError(f"vol must be contiguous float32 [rows][{plan.n_vox}][{plan.n_vox}]")
     n_rows = int(vol.shape[0])
-    if out is None:
-        out = torch.empty((n_rows, plan.n_angles, plan.n_det), dtype=torch.float32, device=vol.device)
+    out = _out(out, (n_rows, plan.n_angles, plan.n_det), torch.float32, vol)
     need = plan.radon_workspace_bytes(n_rows)
     if workspace is None and need > 0:
         workspace = _workspace(need, vol.device)
@@ -352,8 +364,7 @@ def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=N
     need = plan.fbp_workspace_bytes(n_rows, code)
     if workspace is None:
         workspace = _workspace(need, proj.device)
-    if out is None:
-        out = torch.empty((n_rows, plan.n_vox, plan.n_vox), dtype=torch.float32, device=proj.device)
+    out = _out(out, (n_rows, plan.n_vox, plan.n_vox), torch.float32, proj)
     if events is None:
         _check(_fbp_chunk(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode,
                           code, _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
@@ -399,8 +410,7 @@ def fourier_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, st
     kcode = filter_code(kind)
     if workspace is None:
         workspace = _workspace(plan.fourier_workspace_bytes(n_rows), proj.device)
-    if out is None:
-        out = torch.empty((n_rows, plan.n_vox, plan.n_vox), dtype=torch.float32, device=proj.device)
+    out = _out(out, (n_rows, plan.n_vox, plan.n_vox), torch.float32, proj)
     args = (plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode, int(half_width),
             _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(), _dev(out, "out"),
             _stream_ptr(stream))
@@ -434,8 +444,7 @@ def lamino_backproject(plan: Plan, filt, tilt: float, center_v: float, n_slices:
     if filt.dim() != 3 or filt.shape[0] != plan.n_angles or filt.shape[2] != plan.n_det or not filt.is_contiguous():
         raise ValueError("filt must be a contiguous [n_angles][det_rows][n_det] device tensor")
     nz = int(n_slices) - int(z0) if nz is None else int(nz)
-    if out is None:
-        out = torch.empty((nz, plan.n_vox, plan.n_vox), dtype=torch.float32, device=filt.device)
+    out = _out(out, (nz, plan.n_vox, plan.n_vox), torch.float32, filt)
     scale = math.pi / plan.n_angles if scale is None else float(scale)
     _check(_lamino(plan.handle, _dev(filt, "filt"), dtype_code(filt.dtype), int(filt.shape[1]), float(tilt),
                    float(center_v), int(n_slices), int(z0), nz, scale, _dev(out, "out"), _stream_ptr(stream)))

@@ -154,3 +154,20 @@ def test_lamino_validation_without_plan(tp):
     p = ctypes.c_void_p(0x100000)
     assert tp._lamino_prepare(nul, 0.5, 0.0, 8) == tp.TP_EINVAL and "plan" in tp.last_error()
     assert tp._lamino(nul, p, tp.TP_F32, 8, 0.5, 0.0, 8, 0, 8, 1.0, p, nul) == tp.TP_EINVAL
+
+
+def test_output_tensors_checked_before_the_call(tp):
+    # the C ABI gets a bare pointer, so the binding checks a caller's output
+    # tensor against what the kernels would write (here on the host: shape,
+    # dtype and layout are refused before the device is looked at)
+    import torch
+    like = torch.empty(1)
+    assert tuple(tp._out(None, (2, 3), torch.float32, like).shape) == (2, 3)
+    with pytest.raises(ValueError, match="shape"):
+        tp._out(torch.empty(2, 4), (2, 3), torch.float32, like)
+    with pytest.raises(ValueError, match="shape"):
+        tp._out(torch.empty(2, 3, dtype=torch.float16), (2, 3), torch.float32, like)
+    with pytest.raises(ValueError, match="shape"):
+        tp._out(torch.empty(3, 2).t(), (2, 3), torch.float32, like)  # not contiguous
+    with pytest.raises(ValueError, match="must be on"):
+        tp._out(torch.empty(2, 3), (2, 3), torch.float32, like)  # a host tensor

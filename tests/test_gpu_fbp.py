@@ -217,3 +217,28 @@ def test_fbp_widest_detector(tp):
         want = oracle.fbp_points(s.proj[:, z], s.dark[:, z], s.flat[:, z], s.angles, s.center, 8192, ix, iy)
         got = to_host(out[z])[iy, ix].astype(np.float64)
         assert rel_l2(got, want) < 1e-5, z
+
+
+def test_wrong_output_tensors_refused(tp, scan16):
+    # a caller's output tensor that does not match what the kernels write is
+    # refused before any launch (the C ABI sees only its pointer)
+    import torch
+    s = scan16
+    plan = tp.Plan(s.angles, 256, s.center)
+    proj, dark, flat = to_dev(s.proj), to_dev(s.dark), to_dev(s.flat)
+    bad = [torch.empty((16, 256, 255), device="cuda"),                      # too small
+           torch.empty((16, 256, 256), dtype=torch.float16, device="cuda"),  # wrong type
+           torch.empty((256, 256, 16), device="cuda").permute(2, 0, 1)]     # not contiguous
+    for out in bad:
+        with pytest.raises(ValueError):
+            tp.fbp_chunk(plan, proj, dark, flat, "f32", out=out)
+        with pytest.raises(ValueError):
+            tp.fourier_fbp_chunk(plan, proj, dark, flat, out=out)
+    with pytest.raises(ValueError):
+        tp.normalize(proj, dark, flat, out=torch.empty((16, 180, 255), device="cuda"))
+    with pytest.raises(ValueError):
+        tp.radon(plan, torch.zeros((2, 256, 256), device="cuda"), out=torch.empty((2, 180, 200), device="cuda"))
+    with pytest.raises(ValueError):
+        tp.lamino_backproject(plan, torch.zeros((180, 8, 256), device="cuda"), 1.0, 4.0, 4,
+                              out=torch.empty((3, 256, 256), device="cuda"))
+    plan.close()
