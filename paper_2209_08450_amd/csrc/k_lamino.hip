@@ -27,6 +27,8 @@
 // and each slice's coordinates are the same however the volume is split into
 // calls.  Every LDS index is clamped into the staged window, which the window
 // bounds (from the tile's corners, with one sample of margin) make a no-op.
+#include <type_traits>
+
 #include "tp_internal.h"
 
 namespace tp {
@@ -94,7 +96,13 @@ template <typename TI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int nz, float scale,
          float* __restrict__ vol, int wrows, int nzb) {
-    // [kLamA][wrows][kLamCols] float2: windows of wrows rows (sized from the tilt by the launcher)
+    // [kLamA][wrows][kLamCols] elements: windows of wrows rows (sized from the
+    // tilt by the launcher).  An element is the pair (sample at column c,
+    // sample at c + 1): for FP16 projections the two raw FP16 values (4 bytes,
+    // interpolated by mixed-precision FMAs), otherwise the FP32 sample and the
+    // difference to the next (8 bytes).
+    constexpr bool kH = std::is_same<TI, __half>::value;
+    using WinT = typename std::conditional<kH, uint32_t, float2>::type;
     extern __shared__ float win_mem[];
     // per-angle window parameters, double-buffered by block parity: the next
     // block's are written while the current block's are read
@@ -217,6 +225,17 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
     // one row of the window: masked values v[m] at columns lc + 16 m; the
     // next column's value comes from the neighbouring lane (lane 15 of a row
     // group takes lane 0's next chunk; column kLamCols, never read, gets 0)
+    auto put_row_h = [&](uint32_t* wrow, const uint32_t v[3], bool store) {
+        const uint32_t s0 = __shfl(static_cast<int>(v[0]), nbr_lane), s1 = __shfl(static_cast<int>(v[1]), nbr_lane),
+                       s2 = __shfl(static_cast<int>(v[2]), nbr_lane);
+        const bool wrap = lc == 15;
+        const uint32_t n0 = wrap ? s1 : s0, n1 = wrap ? s2 : s1, n2 = wrap ? v[2] : s2;
+        if (store) {
+            wrow[0] = v[0] | (n0 << 16);
+            wrow[16] = v[1] | (n1 << 16);
+            wrow[32] = v[2] | (n2 << 16);
+        }
+    };
     auto put_row = [&](float2* wrow, const float v[3], bool store) {
         const float s0 = __shfl(v[0], nbr_lane), s1 = __shfl(v[1], nbr_lane), s2 = __shfl(v[2], nbr_lane);
         const bool wrap = lc == 15;
@@ -234,18 +253,28 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
             int col[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) col[m] = col_of(c0, m, &cin[m]);
-            float2* wj = reinterpret_cast<float2*>(win_mem) + sj * wrows * kLamCols + lc;
+            WinT* wj = reinterpret_cast<WinT*>(win_mem) + sj * wrows * kLamCols + lc;
 #pragma unroll
             for (int p = 0; p < kLamPre; ++p) {
                 const int rr = lr + 4 * p, row = r0 + rr;
                 const bool rin = rr < nr && row >= 0 && row < t.rows;
-                float v[3];
+                if constexpr (kH) {
+                    uint32_t v[3];  // raw FP16 bits, zero (+0.0) off the detector
 #pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    asm volatile("" : "+v"(X[p][m]));
-                    v[m] = (rin && cin[m]) ? lam_value<TI>(X[p][m]) : 0.0f;
+                    for (int m = 0; m < 3; ++m) {
+                        asm volatile("" : "+v"(X[p][m]));
+                        v[m] = (rin && cin[m]) ? X[p][m] : 0u;
+                    }
+                    put_row_h(wj + rr * kLamCols, v, rr < nr);
+                } else {
+                    float v[3];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        asm volatile("" : "+v"(X[p][m]));
+                        v[m] = (rin && cin[m]) ? lam_value<TI>(X[p][m]) : 0.0f;
+                    }
+                    put_row(wj + rr * kLamCols, v, rr < nr);
                 }
-                put_row(wj + rr * kLamCols, v, rr < nr);
             }
             if (nr > 4 * kLamPre) {  // wave-uniform
                 const TI* img = filt + static_cast<int64_t>(b0 + sj) * t.rows * n;
@@ -253,13 +282,23 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
                     const int row = r0 + rr;
                     const bool rin = rr < nr && row >= 0 && row < t.rows;
                     const unsigned base = rin ? static_cast<unsigned>(row * n) : 0u;
-                    float v[3];
+                    if constexpr (kH) {
+                        uint32_t v[3];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) {
-                        const float x = load_as_float(img + (base + static_cast<unsigned>(col[m])), 0);
-                        v[m] = (rin && cin[m]) ? x : 0.0f;
+                        for (int m = 0; m < 3; ++m) {
+                            const uint32_t x = lam_raw(img + (base + static_cast<unsigned>(col[m])));
+                            v[m] = (rin && cin[m]) ? x : 0u;
+                        }
+                        put_row_h(wj + rr * kLamCols, v, rr < nr);
+                    } else {
+                        float v[3];
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) {
+                            const float x = load_as_float(img + (base + static_cast<unsigned>(col[m])), 0);
+                            v[m] = (rin && cin[m]) ? x : 0.0f;
+                        }
+                        put_row(wj + rr * kLamCols, v, rr < nr);
                     }
-                    put_row(wj + rr * kLamCols, v, rr < nr);
                 }
             }
         }
@@ -298,25 +337,34 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
                 const float wu = coord_frac(u);
                 const float va = __builtin_fmaf(dx, dvx, dy * dvy);  // the voxel's in-tile row offset
                 // byte offset of (angle j, row 0, column c) in the windows
-                const unsigned cb = static_cast<unsigned>((j * wrows * kLamCols + c) * sizeof(float2));
+                const unsigned cb = static_cast<unsigned>((j * wrows * kLamCols + c) * sizeof(WinT));
                 // all slices' reads first, then the arithmetic, so the LDS
                 // reads of a voxel column are in flight together
-                float2 e0[kLamK], e1[kLamK];
+                WinT e0[kLamK], e1[kLamK];
                 float wv[kLamK];
 #pragma unroll
                 for (int k = 0; k < kLamK; ++k) {
                     const float v = va + cz[k];  // row in the window
                     const unsigned r = min(static_cast<unsigned>(coord_floor(v)), rmax);
                     wv[k] = coord_frac(v);
-                    const float2* p = reinterpret_cast<const float2*>(
-                        reinterpret_cast<const char*>(win_mem) + (__umul24(r, kLamCols * sizeof(float2)) + cb));
+                    const WinT* p = reinterpret_cast<const WinT*>(
+                        reinterpret_cast<const char*>(win_mem) + (__umul24(r, kLamCols * sizeof(WinT)) + cb));
                     e0[k] = p[0];
                     e1[k] = p[kLamCols];
                 }
 #pragma unroll
                 for (int k = 0; k < kLamK; ++k) {
-                    const float top = __builtin_fmaf(wu, e0[k].y, e0[k].x);
-                    const float bot = __builtin_fmaf(wu, e1[k].y, e1[k].x);
+                    float top, bot;
+                    if constexpr (kH) {
+                        // (1 - wu) q0 + wu q1 from the raw FP16 pair, in FP32
+                        const __half2 h0 = *reinterpret_cast<const __half2*>(&e0[k]);
+                        const __half2 h1 = *reinterpret_cast<const __half2*>(&e1[k]);
+                        top = __builtin_fmaf(wu, __high2float(h0), __builtin_fmaf(-wu, __low2float(h0), __low2float(h0)));
+                        bot = __builtin_fmaf(wu, __high2float(h1), __builtin_fmaf(-wu, __low2float(h1), __low2float(h1)));
+                    } else {
+                        top = __builtin_fmaf(wu, e0[k].y, e0[k].x);
+                        bot = __builtin_fmaf(wu, e1[k].y, e1[k].x);
+                    }
                     acc[i][k] += __builtin_fmaf(wv[k], bot - top, top);
                 }
             }
@@ -349,7 +397,8 @@ hipError_t launch_lamino_t(const GeoTables& g, const LaminoTables& t, const void
     // the one-row margins on both sides and FP32 slack
     const float span = 31.0f * 1.41421356f * fabsf(t.dvdcos) + (kLamK - 1) * t.dvdz;
     const int wrows = min(kLamRows, static_cast<int>(span) + 6);
-    const size_t lds = sizeof(float2) * kLamA * wrows * kLamCols;
+    const size_t elem = std::is_same<TI, __half>::value ? sizeof(uint32_t) : sizeof(float2);  // window element
+    const size_t lds = elem * kLamA * wrows * kLamCols;
     if (lds > 65536) {  // small tilts: windows above the default dynamic LDS limit (at most 96 KiB)
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_lamino<TI>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
