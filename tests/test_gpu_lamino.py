@@ -59,8 +59,12 @@ def test_lamino_ragged_angle_blocks(tp, na):
     assert np.max(np.abs(got - want)) < 1e-5 * np.max(np.abs(want))
 
 
+@pytest.mark.parametrize("tilt", [0.05, 0.8, 2.4])
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_lamino_reduced_precision_inputs(tp, storage):
+def test_lamino_reduced_precision_inputs(tp, storage, tilt):
+    # FP16 projections are staged as raw FP16 pairs, BF16 as FP32 pairs; tilt
+    # 0.05 needs windows of more than 32 rows (the rows past the ones loaded a
+    # block ahead are staged after the barrier)
     import torch
     q, ang = _case(2, 24, 20, 40)
     N, Nz, cu, cv = 36, 8, 19.5, 9.5
@@ -68,9 +72,10 @@ def test_lamino_reduced_precision_inputs(tp, storage):
     dt = torch.float16 if storage == "f16" else torch.bfloat16
     qd = to_dev(q).to(dt)
     qr = to_host(qd).astype(np.float64)  # the rounded values the kernel reads
-    got = to_host(tp.lamino_backproject(plan, qd, 0.8, cv, Nz)).astype(np.float64)
-    want = oracle.lamino_backproject(qr, ang, cu, cv, 0.8, N, Nz)
+    got = to_host(tp.lamino_backproject(plan, qd, tilt, cv, Nz)).astype(np.float64)
+    want = oracle.lamino_backproject(qr, ang, cu, cv, tilt, N, Nz)
     assert rel_l2(got, want) < 1e-5
+    assert np.max(np.abs(got - want)) < 1e-5 * np.max(np.abs(want))
 
 
 def test_lamino_tomography_tilt_matches_linear_backprojection(tp):
@@ -86,11 +91,13 @@ def test_lamino_tomography_tilt_matches_linear_backprojection(tp):
     assert rel_l2(got, lin) < 1e-6
 
 
-def test_lamino_slice_ranges_bitwise(tp):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_lamino_slice_ranges_bitwise(tp, storage):
+    import torch
     q, ang = _case(4, 20, 16, 32)
     N, Nz, cu, cv = 32, 11, 15.5, 7.3
     plan = tp.Plan(ang, 32, cu, N)
-    qd = to_dev(q)
+    qd = to_dev(q) if storage == "f32" else to_dev(q).to(torch.float16)
     full = to_host(tp.lamino_backproject(plan, qd, 0.7, cv, Nz))
     for z0, nz in [(0, 3), (3, 5), (8, 3)]:
         part = to_host(tp.lamino_backproject(plan, qd, 0.7, cv, Nz, z0=z0, nz=nz))
