@@ -55,7 +55,7 @@ __device__ __forceinline__ int lamino_work_item(int b, int total) {
 // A stored sample as loaded (its bits, zero-extended to 32), and its value:
 // the conversion is deferred so loads issued a block ahead are not waited for.
 __device__ __forceinline__ uint32_t lam_raw(const float* p) { return __float_as_uint(*p); }
-__device__ __forceinline__ uint32_t lam_raw(const __half* p) { return *reinterpret_cast<const uint16_t*>(p); }
+__device__ __forceinline__ uint32_t lam_raw(const __half* p) { return __half_as_ushort(*p); }
 __device__ __forceinline__ uint32_t lam_raw(const uint16_t* p) { return *p; }
 template <typename TI> __device__ __forceinline__ float lam_value(uint32_t r);
 template <> __device__ __forceinline__ float lam_value<float>(uint32_t r) { return __uint_as_float(r); }
@@ -357,8 +357,9 @@ k_lamino(GeoTables g, LaminoTables t, const TI* __restrict__ filt, int z0, int n
                     float top, bot;
                     if constexpr (kH) {
                         // (1 - wu) q0 + wu q1 from the raw FP16 pair, in FP32
-                        const __half2 h0 = *reinterpret_cast<const __half2*>(&e0[k]);
-                        const __half2 h1 = *reinterpret_cast<const __half2*>(&e1[k]);
+                        __half2 h0, h1;
+                        __builtin_memcpy(&h0, &e0[k], sizeof(h0));
+                        __builtin_memcpy(&h1, &e1[k], sizeof(h1));
                         top = __builtin_fmaf(wu, __high2float(h0), __builtin_fmaf(-wu, __low2float(h0), __low2float(h0)));
                         bot = __builtin_fmaf(wu, __high2float(h1), __builtin_fmaf(-wu, __low2float(h1), __low2float(h1)));
                     } else {
