@@ -77,7 +77,21 @@ typedef struct {
  * current when it is created: FP32 (cos, sin) per angle and, per 32-voxel
  * tile edge, the detector coordinate of the tile origin computed in FP64 and
  * split into an integer and an FP32 fraction, plus the ramp filter's tables
- * for pad length 2^ceil(log2(2 n_det)).  Use a plan only on that device. */
+ * for pad length 2^ceil(log2(2 n_det)).  Use a plan only on that device.
+ *
+ * Why a handle: the paper's reconstruction is configured once per scan (the
+ * angles, rotation axis and detector width of Section 2.4) and then run chunk
+ * after chunk (Section 2.3), with FFT plans built once and reused per chunk
+ * (Section 2.2).  The plan is that once-per-scan state: its tables are built
+ * here, outside any graph capture, and every chunk call reads them.
+ *
+ * tp_plan_create: g as above (angles read during the call only); *out
+ * receives the plan.  Errors: TP_EINVAL (null pointers, non-positive sizes,
+ * non-finite angles or centre, |center| > 1e6), TP_EUNSUPPORTED (pad length
+ * above 16384 or n_vox above 32768), TP_ENOMEM / TP_EHIP from the device.
+ * If tp_tune_load has loaded a table holding this device and shape, the
+ * plan starts from the recorded backprojection tilings (else the defaults
+ * below). */
 typedef struct tp_plan tp_plan;
 
 tp_status tp_plan_create(const tp_geometry* g, tp_plan** out);
@@ -102,10 +116,52 @@ tp_status tp_plan_get_tuning(const tp_plan* plan, tp_dtype storage, int32_t* sli
                              int32_t* angles_per_block);
 
 /* Build and cache the filter tables of one pad length and window on the
- * current device (for tp_filter / tp_fbp_chunk calls that will be
- * graph-captured; a plan prepares the ramp of its own pad length).  pad_len:
- * power of two in [2, 16384]. */
+ * current device (the paper builds its FFT plans once and runs them per
+ * chunk, Section 2.2; the windows are the filter choices of Section 2.4), for
+ * tp_filter / tp_fbp_chunk calls that will be graph-captured; a plan prepares
+ * the ramp of its own pad length.  pad_len: power of two in [2, 16384].
+ * Errors: TP_EINVAL (pad_len), TP_EUNSUPPORTED (kind), TP_ENOMEM / TP_EHIP. */
 tp_status tp_filter_prepare(int32_t pad_len, tp_filter_kind kind);
+
+/* Everything the hot calls of one plan need for one filter window and one
+ * storage type, built before the first chunk (FFT plans created once and
+ * executed per chunk, paper Section 2.2; the filter and 16-bit storage
+ * choices of Section 2.4): the window's tables at the plan's pad length and
+ * the dynamic-LDS limit of the backprojection kernel that the plan's current
+ * tiling for `storage` selects.  After it, tp_fbp_chunk and tp_backproject
+ * with that (kind, storage) allocate nothing and make no one-time runtime
+ * call, so they may be graph-captured.  Call it again after
+ * tp_plan_set_tuning.  The plan's device must be current.  Errors: TP_EINVAL
+ * (null plan, bad storage, another device current), TP_EUNSUPPORTED (kind),
+ * TP_ENOMEM / TP_EHIP from the device. */
+tp_status tp_prepare(const tp_plan* plan, tp_filter_kind kind, tp_dtype storage);
+
+/* Loads the autotuner's table of backprojection tilings (the tile parameters
+ * of the backprojection; the paper's per-chunk kernels take their sizes from
+ * the chunk and detector, Section 2.3) from a JSON file: an object mapping
+ * "<device name>|<f32|f16|bf16>|na=<angles>|n=<columns>|N=<voxels>|rows=<rows>"
+ * to objects whose "choice" member is [slices_per_block, angles_per_block]
+ * (other members are ignored; several row counts of one shape keep the
+ * largest).  Plans created afterwards on a matching device and shape start
+ * from these tilings.  Tilings never change results (every legal tiling gives
+ * bitwise-identical output), only speed.  json_path NULL clears the table.
+ * Host only (no device call).  Errors: TP_EINVAL for an unreadable file,
+ * malformed JSON, a malformed key or an illegal tiling; the previous table is
+ * then kept. */
+tp_status tp_tune_load(const char* json_path);
+/* Host only: the tiling the loaded table holds for (device_name, storage,
+ * n_angles, n_det, n_vox; n_vox 0 => n_det).  TP_EINVAL if none (or null
+ * arguments). */
+tp_status tp_tune_lookup(const char* device_name, tp_dtype storage, int32_t n_angles, int32_t n_det, int32_t n_vox,
+                         int32_t* slices_per_block, int32_t* angles_per_block);
+
+/* Releases what the library caches across plans: the filter tables of every
+ * (device, pad length, window) on every device, and the tuning table.  Plans
+ * point at those tables, so every plan must have been destroyed first
+ * (TP_EINVAL otherwise, nothing freed), and no enqueued work may still read
+ * them.  Later calls rebuild what they need.  Errors: TP_EINVAL (plans
+ * alive), TP_EHIP (a device call failed; the cache is emptied regardless). */
+tp_status tp_shutdown(void);
 
 /* Host only, no device needed: the FP64 filter response the device tables are
  * rounded from, H[k] = sum_{m=-L/2}^{L/2-1} h[m] exp(-2 pi i k m / L), where
@@ -166,7 +222,10 @@ tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtyp
                          void* stream);
 
 /* --------------------------------------------------------------------------
- * Forward projection, the exact transpose of tp_backproject with scale 1:
+ * Forward projection (the operator the paper's iterative reconstruction
+ * methods need alongside the backprojector, Sections 1 and 5; not defined in
+ * the paper, so it is read as the exact transpose of tp_backproject with
+ * scale 1):
  *   sino[r][a][j] = sum over voxels of vol[r][iy][ix] * ( (1-w)[j0 == j] + w[j0+1 == j] )
  * with (j0, w) computed by the same FP32 formula as tp_backproject, so
  * <R x, y> = <x, R^T y> holds up to FP32 summation rounding.  Gather form
@@ -185,7 +244,9 @@ tp_status tp_radon(const tp_plan* plan, const float* vol, int32_t n_rows, float*
                    void* workspace, size_t workspace_bytes, void* stream);
 
 /* --------------------------------------------------------------------------
- * One chunk of rows through the whole path: normalise -> filter -> backproject.
+ * One chunk of rows through the whole path (paper Section 2.2: dark/flat
+ * correction, -log, filtering, backprojection; Section 2.3: the path runs per
+ * chunk of detector rows): normalise -> filter -> backproject.
  *   vol = (pi / n_angles) R^T ( H * normalize(proj, dark, flat) )
  * The -log sinogram never leaves the chip: the filter kernel normalises raw
  * counts in registers, filters in FP32 and stores only the filtered rows, in
@@ -331,6 +392,23 @@ tp_status tp_io_write_slices(const char* path, int64_t header_bytes, int64_t fir
 tp_status tp_io_create(const char* path, int64_t bytes);
 /* Thread-local description of the last failing tp_io_* call on this thread. */
 const char* tp_io_last_error(void);
+
+/* --------------------------------------------------------------------------
+ * Measurement instruments for the roofline report (not part of the paper's
+ * method): the rates a kernel of this library can reach on this device, as
+ * the denominators beside the vendor peaks.
+ * tp_peak_copy: copies `bytes` (a positive multiple of 16; both buffers dev,
+ *   16-byte aligned, not overlapping) with 16-byte loads and stores on
+ *   `stream`; time it with events to get the copy rate (2 x bytes moved).
+ * tp_peak_fma: `blocks` work-groups of 256 threads each run 8 independent
+ *   FP32 FMA chains for 2 x iters steps (non-packed v_fma_f32, the build's
+ *   instruction selection) and store one float per thread to out (dev,
+ *   blocks x 256 floats); *flop receives the flop count (2 per FMA).
+ *   blocks in [1, 2^20], iters in [1, 2^24].
+ * Errors: TP_EINVAL for bad arguments (nothing enqueued), TP_EHIP.
+ * ------------------------------------------------------------------------ */
+tp_status tp_peak_copy(const void* src, void* dst, int64_t bytes, void* stream);
+tp_status tp_peak_fma(float* out, int32_t blocks, int32_t iters, int64_t* flop, void* stream);
 
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* tp_last_error(void);

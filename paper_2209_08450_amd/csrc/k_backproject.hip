@@ -228,6 +228,8 @@ size_t bp_lds_bytes(tp_dtype dt, int K, int A) {
     return static_cast<size_t>(bin_pitch(elem * K)) * A * kWin + static_cast<size_t>(A) * sizeof(float4);
 }
 
+// A null `vol` only sets the instance's dynamic-LDS limit (tp_prepare), so
+// that later launches, possibly graph-captured, make no attribute call.
 template <typename T, int K, int A>
 hipError_t launch_bp_t(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
                        int accumulate, size_t lds, hipStream_t st) {
@@ -236,6 +238,7 @@ hipError_t launch_bp_t(const GeoTables& g, const void* filt, int n_rows, float s
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
+    if (vol == nullptr) return hipSuccess;
     const dim3 grid(static_cast<unsigned>(g.nb * g.nb), static_cast<unsigned>((n_rows + K - 1) / K));
     hipLaunchKernelGGL((k_backproject<T, K, A>), grid, dim3(kBpThreads), lds, st, g, static_cast<const T*>(filt),
                        n_rows, scale, vol, accumulate);
@@ -271,6 +274,11 @@ hipError_t launch_bp_k(const GeoTables& g, const void* filt, int n_rows, float s
 
 size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_block) {
     return bp_lds_bytes(dt, slices_per_block, angles_per_block);
+}
+
+hipError_t prepare_backproject(tp_dtype dt, int slices_per_block, int angles_per_block) {
+    GeoTables g{};
+    return launch_backproject(g, nullptr, dt, 0, 0.0f, nullptr, 0, slices_per_block, angles_per_block, nullptr);
 }
 
 hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt, int n_rows, float scale,

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -89,6 +90,9 @@ struct FilterEntry {
 };
 std::mutex g_filter_mu;
 std::map<std::tuple<int, int, int>, FilterEntry> g_filter_cache;
+// plans created and not yet destroyed (tp_shutdown refuses while any exist:
+// every plan points at the cached ramp tables of its pad length)
+std::atomic<int> g_live_plans{0};
 
 // Exact integral of p(x) cos(pi m x) over [x0, x1] for a polynomial p with
 // coefficients c[0..deg] (p = sum c[i] x^i), using the antiderivative
@@ -676,6 +680,20 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
         delete p;
         return st;
     }
+    if (!tp::tune_table_empty()) {
+        // tilings recorded by the autotuner for this device and shape (tp_tune_load)
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+            for (int d = TP_F32; d <= TP_BF16; ++d) {
+                int k = 0, a = 0;
+                if (tp::tune_table_lookup(prop.name, d, na, g->n_det, N, &k, &a)) {
+                    p->bp_k[d] = k;
+                    p->bp_a[d] = a;
+                }
+            }
+        }
+    }
+    g_live_plans.fetch_add(1);
     *out = p;
     return TP_OK;
 }
@@ -696,7 +714,67 @@ tp_status tp_plan_destroy(tp_plan* plan) {
     }
     if (cur != plan->device) (void)hipSetDevice(cur);
     delete plan;
+    g_live_plans.fetch_sub(1);
     if (e != hipSuccess) return hip_fail(e, "hipFree(plan tables)");
+    return TP_OK;
+}
+
+tp_status tp_prepare(const tp_plan* plan, tp_filter_kind kind, tp_dtype storage) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
+    if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != plan->device)
+        return fail(TP_EINVAL, "plan belongs to device %d, current device is %d", plan->device, cur);
+    tp::FilterTables ft;
+    tp_status s = filter_tables(plan->filt.L, kind, &ft, nullptr);
+    if (s != TP_OK) return s;
+    e = tp::prepare_backproject(storage, plan->bp_k[storage], plan->bp_a[storage]);
+    if (e != hipSuccess) return hip_fail(e, "backprojection kernel attribute");
+    return TP_OK;
+}
+
+tp_status tp_tune_load(const char* json_path) {
+    std::string err;
+    if (tp::tune_table_load(json_path, &err) < 0) return fail(TP_EINVAL, "%s", err.c_str());
+    return TP_OK;
+}
+
+tp_status tp_tune_lookup(const char* device_name, tp_dtype storage, int32_t n_angles, int32_t n_det, int32_t n_vox,
+                         int32_t* slices_per_block, int32_t* angles_per_block) {
+    if (!device_name || !slices_per_block || !angles_per_block) return fail(TP_EINVAL, "null argument");
+    if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
+    const int N = n_vox ? n_vox : n_det;
+    int k = 0, a = 0;
+    if (!tp::tune_table_lookup(device_name, storage, n_angles, n_det, N, &k, &a))
+        return fail(TP_EINVAL, "no tiling recorded for %s storage %d, %d angles, %d columns, %d voxels", device_name,
+                    static_cast<int>(storage), n_angles, n_det, N);
+    *slices_per_block = k;
+    *angles_per_block = a;
+    return TP_OK;
+}
+
+tp_status tp_shutdown(void) {
+    const int live = g_live_plans.load();
+    if (live > 0) return fail(TP_EINVAL, "%d plan(s) still exist; destroy them before tp_shutdown", live);
+    std::string ignore;
+    (void)tp::tune_table_load(nullptr, &ignore);
+    std::lock_guard<std::mutex> lk(g_filter_mu);
+    if (g_filter_cache.empty()) return TP_OK;
+    int cur = 0;
+    hipError_t first = hipGetDevice(&cur);
+    for (auto& kv : g_filter_cache) {
+        const int dev = std::get<0>(kv.first);
+        hipError_t e = hipSetDevice(dev);
+        if (e == hipSuccess) e = hipFree(kv.second.tw);
+        const hipError_t e2 = hipFree(kv.second.H);
+        if (first == hipSuccess) first = e != hipSuccess ? e : e2;
+    }
+    g_filter_cache.clear();
+    (void)hipSetDevice(cur);
+    if (first != hipSuccess) return hip_fail(first, "freeing the filter tables");
     return TP_OK;
 }
 
@@ -1038,6 +1116,30 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj,
         if ((e = mark(5)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         first = false;
     }
+    return TP_OK;
+}
+
+tp_status tp_peak_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+    if (!src || !dst) return fail(TP_EINVAL, "null buffer");
+    if (bytes <= 0 || (bytes & 15)) return fail(TP_EINVAL, "bytes=%lld must be a positive multiple of 16",
+                                                static_cast<long long>(bytes));
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+        return fail(TP_EINVAL, "buffers must be 16-byte aligned");
+    const char* a = static_cast<const char*>(src);
+    const char* b = static_cast<const char*>(dst);
+    if (a < b + bytes && b < a + bytes) return fail(TP_EINVAL, "buffers overlap");
+    const hipError_t e = tp::launch_peak_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return TP_OK;
+}
+
+tp_status tp_peak_fma(float* out, int32_t blocks, int32_t iters, int64_t* flop, void* stream) {
+    if (!out || !flop) return fail(TP_EINVAL, "null argument");
+    if (blocks <= 0 || blocks > (1 << 20) || iters <= 0 || iters > (1 << 24))
+        return fail(TP_EINVAL, "blocks=%d iters=%d out of range", blocks, iters);
+    *flop = tp::peak_fma_flop(blocks, iters);
+    const hipError_t e = tp::launch_peak_fma(out, blocks, iters, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "FMA launch");
     return TP_OK;
 }
 

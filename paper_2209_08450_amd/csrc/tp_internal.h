@@ -5,6 +5,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/tp.h"
 
 namespace tp {
@@ -110,6 +112,8 @@ hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt,
                               float* vol, int accumulate, int slices_per_block, int angles_per_block,
                               hipStream_t st);
 size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_block);
+// Sets the dynamic-LDS limit of one backprojection kernel instance (no launch).
+hipError_t prepare_backproject(tp_dtype dt, int slices_per_block, int angles_per_block);
 size_t radon_workspace_bytes(const GeoTables& g, int n_rows);
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
                         hipStream_t st);
@@ -124,6 +128,19 @@ hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const
                                float* vol, hipStream_t st);
 
 int lamino_slices_per_block();
+
+// measurement instruments (k_peak.hip)
+hipError_t launch_peak_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
+int64_t peak_fma_flop(int blocks, int iters);
+hipError_t launch_peak_fma(float* out, int blocks, int iters, hipStream_t st);
+
+// ---- backprojection tilings read from the autotuner's JSON table (tp_tune.cpp) ----
+// Replaces the process-wide table with the file's entries (path null: clears
+// it).  Returns the number of shapes held, or -1 with *err set (the table is
+// then unchanged).
+int tune_table_load(const char* path, std::string* err);
+bool tune_table_lookup(const std::string& device, int storage, int na, int n, int N, int* k, int* a);
+bool tune_table_empty();
 hipError_t launch_lamino(const GeoTables& g, const LaminoTables& t, const void* filt, tp_dtype dt, int z0, int nz,
                          float scale, float* vol, hipStream_t st);
 

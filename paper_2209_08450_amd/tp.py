@@ -51,6 +51,11 @@ _plan_set_tuning = _proto("tp_plan_set_tuning", _c_i32, _c_vp, _c_i32, _c_i32, _
 _plan_get_tuning = _proto("tp_plan_get_tuning", _c_i32, _c_vp, _c_i32, ctypes.POINTER(_c_i32),
                           ctypes.POINTER(_c_i32))
 _filter_prepare = _proto("tp_filter_prepare", _c_i32, _c_i32, _c_i32)
+_prepare = _proto("tp_prepare", _c_i32, _c_vp, _c_i32, _c_i32)
+_tune_load = _proto("tp_tune_load", _c_i32, ctypes.c_char_p)
+_tune_lookup = _proto("tp_tune_lookup", _c_i32, ctypes.c_char_p, _c_i32, _c_i32, _c_i32, _c_i32,
+                      ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32))
+_shutdown = _proto("tp_shutdown", _c_i32)
 _filter_response = _proto("tp_filter_response", _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_d))
 _normalize_ws = _proto("tp_normalize_workspace_bytes", _c_sz, _c_i32, _c_i32)
 _normalize = _proto("tp_normalize", _c_i32, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32,
@@ -80,6 +85,8 @@ _io_write_slices = _proto("tp_io_write_slices", _c_i32, ctypes.c_char_p, _c_i64,
                           _c_i32)
 _io_create = _proto("tp_io_create", _c_i32, ctypes.c_char_p, _c_i64)
 _io_last_error = _proto("tp_io_last_error", ctypes.c_char_p)
+_peak_copy = _proto("tp_peak_copy", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp)
+_peak_fma = _proto("tp_peak_fma", _c_i32, _c_vp, _c_i32, _c_i32, ctypes.POINTER(_c_i64), _c_vp)
 _last_error = _proto("tp_last_error", ctypes.c_char_p)
 _version = _proto("tp_version", ctypes.c_char_p)
 
@@ -228,9 +235,35 @@ class Plan:
         """Workspace for the Fourier-domain FBP of n_rows rows in one pass."""
         return int(_fourier_ws(self._h, int(n_rows)))
 
+    def prepare(self, kind="ramp", storage="f16"):
+        """Build what the hot calls need for (kind, storage) before graph capture (tp_prepare)."""
+        _check(_prepare(self._h, filter_code(kind), dtype_code(storage)))
+
     def fourier_prepare(self, kind="ramp", half_width: int = 0):
         """Build the Fourier-domain path's tables (before graph capture)."""
         _check(_fourier_prepare(self._h, filter_code(kind), int(half_width)))
+
+
+def tune_load(path) -> None:
+    """Load the autotuner's JSON table of backprojection tilings (None clears it); plans
+    created afterwards start from the recorded tilings of their device and shape."""
+    _check(_tune_load(None if path is None else os.fsencode(path)))
+
+
+def tune_lookup(device_name: str, storage, n_angles: int, n_det: int, n_vox: int = 0):
+    """(slices_per_block, angles_per_block) the loaded table holds for a shape, or None."""
+    k, a = _c_i32(), _c_i32()
+    st = _tune_lookup(device_name.encode(), dtype_code(storage), int(n_angles), int(n_det), int(n_vox),
+                      ctypes.byref(k), ctypes.byref(a))
+    if st != TP_OK:
+        return None
+    return int(k.value), int(a.value)
+
+
+def shutdown() -> None:
+    """Free the library's cached filter tables on every device and clear the tuning
+    table (every plan must have been closed)."""
+    _check(_shutdown())
 
 
 def filter_code(kind) -> int:
@@ -495,3 +528,23 @@ def io_write_slices(path, first_slice: int, src, slice_bytes: int, threads: int 
 def io_create(path, nbytes: int):
     """Create (or truncate) a file of nbytes bytes (tp_io_create)."""
     _io_check(_io_create(os.fsencode(str(path)), int(nbytes)))
+
+
+# ---------------------------------------------------------------------------
+# Measurement instruments (roofline denominators)
+# ---------------------------------------------------------------------------
+def peak_copy(src, dst, stream=None):
+    """Enqueue a device copy of src into dst (same byte size, a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same size in bytes")
+    _check(_peak_copy(_dev(src, "src"), _dev(dst, "dst"), nbytes, _stream_ptr(stream)))
+    return nbytes
+
+
+def peak_fma(out, iters: int, stream=None) -> int:
+    """Enqueue the FMA-chain kernel over out.numel() // 256 work-groups; returns its flop count."""
+    blocks = out.numel() // 256
+    flop = _c_i64()
+    _check(_peak_fma(_dev(out, "out"), int(blocks), int(iters), ctypes.byref(flop), _stream_ptr(stream)))
+    return int(flop.value)

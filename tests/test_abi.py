@@ -171,3 +171,92 @@ def test_output_tensors_checked_before_the_call(tp):
         tp._out(torch.empty(3, 2).t(), (2, 3), torch.float32, like)  # not contiguous
     with pytest.raises(ValueError, match="must be on"):
         tp._out(torch.empty(2, 3), (2, 3), torch.float32, like)  # a host tensor
+
+
+# ---------------------------------------------------------------------------
+# Lifecycle calls: tp_prepare, tp_tune_load / tp_tune_lookup, tp_shutdown.
+# ---------------------------------------------------------------------------
+def test_prepare_rejects_bad_arguments(tp):
+    nul = ctypes.c_void_p()
+    assert tp._prepare(nul, tp.TP_RAMP, tp.TP_F16) == tp.TP_EINVAL
+    assert "plan" in tp.last_error()
+
+
+def _write_table(path, entries):
+    import json
+    with open(path, "w") as f:
+        json.dump(entries, f)
+
+
+def test_tune_load_reads_the_tuners_cache(tp, tmp_path):
+    from paper_2209_08450_amd import tune
+    dev = "AMD Instinct MI355X"
+    p = str(tmp_path / "tune.json")
+    cache = {
+        tune.cache_key(dev, "f16", 2048, 2048, 2048, 16): {"choice": [16, 32], "seconds": {"16,32": 0.1,
+                                                                                       "8,64": 0.2}},
+        tune.cache_key(dev, "f16", 2048, 2048, 2048, 64): {"seconds": {"16,16": 0.1}, "choice": [8, 16]},
+        tune.cache_key(dev, "f32", 900, 1024, 1024, 16): {"choice": [16, 8]},
+        tune.cache_key("other|gpu", "bf16", 12, 34, 56, 8): {"choice": [4, 64]},
+    }
+    tune.save_cache(cache, p)  # the tuner's own writer
+    tp.tune_load(p)
+    # several chunk heights of one shape keep the tallest
+    assert tp.tune_lookup(dev, "f16", 2048, 2048, 2048) == (8, 16)
+    assert tp.tune_lookup(dev, "f32", 900, 1024, 1024) == (16, 8)
+    assert tp.tune_lookup(dev, "f32", 900, 1024, 0) == (16, 8)  # n_vox 0 => n_det
+    assert tp.tune_lookup("other|gpu", "bf16", 12, 34, 56) == (4, 64)  # '|' inside the device name
+    assert tp.tune_lookup(dev, "bf16", 2048, 2048, 2048) is None
+    assert tp.tune_lookup(dev, "f16", 2048, 2048, 1024) is None
+    tp.tune_load(None)
+    assert tp.tune_lookup(dev, "f32", 900, 1024, 1024) is None
+
+
+@pytest.mark.parametrize("text,needle", [
+    ("[1, 2]", "object"),
+    ('{"AMD|f16|na=4|n=8|N=8|rows=2": {"choice": [16, 16]', "expected"),
+    ('{"AMD|f16|na=4|n=8|N=8|rows=2": {"choice": [3, 16]}}', "illegal"),
+    ('{"AMD|f16|na=4|n=8|N=8|rows=2": {"choice": [16, 16.5]}}', "illegal"),
+    ('{"AMD|f32|na=4|n=8|N=8|rows=2": {"choice": [16, 64]}}', "illegal"),  # exceeds LDS
+    ('{"AMD|f64|na=4|n=8|N=8|rows=2": {"choice": [16, 16]}}', "key"),
+    ('{"AMD|f16|na=0|n=8|N=8|rows=2": {"choice": [16, 16]}}', "key"),
+    ('{"f16|na=4|n=8|N=8": {"choice": [16, 16]}}', "key"),
+    ('{"AMD|f16|na=4|n=8|N=8|rows=2": {"seconds": {}}}', "choice"),
+    ('{"AMD|f16|na=4|n=8|N=8|rows=2": {"choice": [16, 16]}} x', "trailing"),
+])
+def test_tune_load_rejects_malformed_tables_and_keeps_the_old_one(tp, tmp_path, text, needle):
+    good = str(tmp_path / "good.json")
+    _write_table(good, {"GPU|f16|na=4|n=8|N=8|rows=2": {"choice": [4, 8]}})
+    tp.tune_load(good)
+    bad = str(tmp_path / "bad.json")
+    with open(bad, "w") as f:
+        f.write(text)
+    with pytest.raises(tp.TpError) as ei:
+        tp.tune_load(bad)
+    assert ei.value.status == tp.TP_EINVAL and needle in str(ei.value)
+    assert tp.tune_lookup("GPU", "f16", 4, 8, 8) == (4, 8)
+    tp.tune_load(None)
+
+
+def test_tune_load_missing_file(tp, tmp_path):
+    with pytest.raises(tp.TpError) as ei:
+        tp.tune_load(str(tmp_path / "absent.json"))
+    assert "cannot open" in str(ei.value)
+
+
+def test_tune_load_empty_object_clears(tp, tmp_path):
+    p = str(tmp_path / "t.json")
+    _write_table(p, {"GPU|f16|na=4|n=8|N=8|rows=2": {"choice": [4, 8]}})
+    tp.tune_load(p)
+    _write_table(p, {})
+    tp.tune_load(p)
+    assert tp.tune_lookup("GPU", "f16", 4, 8, 8) is None
+
+
+def test_shutdown_without_device_state_is_ok(tp):
+    # nothing cached on a machine without a GPU: shutdown frees nothing and succeeds
+    # (on a GPU machine the lifecycle is tested in a fresh process, test_gpu_lifecycle.py)
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("device state may exist in this process")
+    tp.shutdown()

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_2209_08450_amd import synth
-from tests._util import note, rel_l2, to_dev, to_host
+from tests._util import assert_parity, note, rel_l2, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +40,7 @@ def test_fbp_f32_16_slices(tp, scan16, ref16):
     note("fbp f32 180x16x256")
     got = _run(tp, scan16, "f32")
     want = ref16[None]
-    assert rel_l2(got, want) < 1e-5
+    assert_parity(got, want, "f32", label="fbp 16 slices")
     for z in range(16):
         assert rel_l2(got[z], want[z]) < 1e-5
 
@@ -48,8 +48,7 @@ def test_fbp_f32_16_slices(tp, scan16, ref16):
 def test_fbp_f16_storage(tp, scan16, ref16):
     note("fbp f16 180x16x256")
     got = _run(tp, scan16, "f16")
-    e = rel_l2(got, ref16[None])
-    assert e < 3e-3
+    e, _ = assert_parity(got, ref16[None], "f16", label="fbp 16 slices")
     # against the oracle with the same storage rounding: FP32-level agreement
     # except where an FP32/FP64 difference flips an FP16 rounding
     assert rel_l2(got, ref16["f16"]) < 0.25 * e + 1e-5
@@ -58,8 +57,7 @@ def test_fbp_f16_storage(tp, scan16, ref16):
 def test_fbp_bf16_storage(tp, scan16, ref16):
     note("fbp bf16 180x16x256")
     got = _run(tp, scan16, "bf16")
-    e = rel_l2(got, ref16[None])
-    assert e < 2e-2
+    e, _ = assert_parity(got, ref16[None], "bf16", label="fbp 16 slices")
     assert rel_l2(got, ref16["bf16"]) < 0.25 * e + 1e-5
 
 
@@ -72,7 +70,7 @@ def test_fbp_ragged_geometry(tp):
     out = tp.fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), "f32")
     got = to_host(out).astype(np.float64)
     want = oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center, N=80)
-    assert rel_l2(got, want) < 1e-5
+    assert_parity(got, want, "f32", label="fbp ragged")
 
 
 def test_fbp_equals_separate_calls(tp, scan16):
@@ -108,6 +106,8 @@ def test_fbp_paper_scale_sampled(tp):
         want = oracle.fbp_points(s.proj[:, i], s.dark[:, i], s.flat[:, i], s.angles, s.center, 2048, ix, iy)
         e32.append(rel_l2(got32[i][iy, ix], want))
         e16.append(rel_l2(got16[i][iy, ix], want))
+        assert_parity(got32[i][iy, ix], want, "f32", label=f"paper-scale row {rows[i]}")
+        assert_parity(got16[i][iy, ix], want, "f16", label=f"paper-scale row {rows[i]}")
     note(f"paper-scale rel-L2 f32 {e32} f16 {e16}")
     assert max(e32) < 1e-5
     assert max(e16) < 3e-3
@@ -117,7 +117,9 @@ def test_fbp_bench_launch_shape_sampled(tp):
     """The launch the 2048^3 benchmark times: one 256-row chunk of 2048 angles
     x 2048 columns (default tuning, all three storage types) of a 12-bit
     ellipsoid scan generated on the GPU; three rows spread over the chunk (its
-    first and last slice blocks included) checked at 512 sampled voxels each."""
+    first and last slice blocks included) checked at 512 sampled voxels each,
+    and the chunk's first and last slices checked whole (2048^2 voxels each)
+    against the oracle's full-slice FBP."""
     import torch
     s = synth.ellipsoid_scan_torch(seed=5, n_angles=2048, n_rows=256, n_det=2048, device="cuda", center=1024.0)
     rows = [0, 129, 255]
@@ -127,6 +129,9 @@ def test_fbp_bench_launch_shape_sampled(tp):
     pts = [(rng.integers(0, 2048, 512), rng.integers(0, 2048, 512)) for _ in rows]
     want = [oracle.fbp_points(host["proj"][:, i], host["dark"][:, i], host["flat"][:, i], s.angles, s.center, 2048,
                               ix, iy) for i, (ix, iy) in enumerate(pts)]
+    whole = [0, 2]  # positions in `rows` of the chunk's first and last slices
+    want_full = oracle.fbp(host["proj"][:, whole], host["dark"][:, whole], host["flat"][:, whole], s.angles,
+                           s.center)
     for storage, tol in (("f32", 1e-5), ("f16", 3e-3), ("bf16", 3e-3)):
         note(f"fbp 2048 x 256 x 2048 {storage}")
         vol = tp.fbp_chunk(plan, s.proj, s.dark, s.flat, storage)
@@ -136,6 +141,9 @@ def test_fbp_bench_launch_shape_sampled(tp):
         errs = [rel_l2(got[i][iy, ix], want[i]) for i, (ix, iy) in enumerate(pts)]
         note(f"{storage} rel-L2 {errs}")
         assert max(errs) < tol
+        for i, (ix, iy) in enumerate(pts):
+            assert_parity(got[i][iy, ix], want[i], storage, rel=tol, label=f"bench chunk row {rows[i]} sampled")
+        assert_parity(got[whole], want_full, storage, rel=tol, label="bench chunk first and last slices whole")
     plan.close()
 
 
@@ -149,11 +157,10 @@ def test_fbp_windowed_filters(tp, scan16, kind):
     plan = tp.Plan(s.angles, 256, s.center)
     run = lambda st: to_host(tp.fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), st,  # noqa: E731
                                           kind=kind)).astype(np.float64)
-    assert rel_l2(run("f32"), want) < 1e-5
-    e = rel_l2(run("f16"), want)
-    assert e < 3e-3
+    assert_parity(run("f32"), want, "f32", label=f"fbp {kind}")
+    e, _ = assert_parity(run("f16"), want, "f16", label=f"fbp {kind}")
     assert rel_l2(run("f16"), want16) < 0.25 * e + 1e-5
-    assert rel_l2(run("bf16"), want) < 2e-2
+    assert_parity(run("bf16"), want, "bf16", label=f"fbp {kind}")
     # the window changes the reconstruction
     assert rel_l2(want, oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center)) > 1e-2
 
@@ -216,7 +223,7 @@ def test_fbp_widest_detector(tp):
     for z in range(2):
         want = oracle.fbp_points(s.proj[:, z], s.dark[:, z], s.flat[:, z], s.angles, s.center, 8192, ix, iy)
         got = to_host(out[z])[iy, ix].astype(np.float64)
-        assert rel_l2(got, want) < 1e-5, z
+        assert_parity(got, want, "f32", label=f"widest detector row {z}")
 
 
 def test_wrong_output_tensors_refused(tp, scan16):

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2209_08450_amd import synth
-from tests._util import note, rel_l2, to_dev, to_host
+from tests._util import assert_parity, note, rel_l2, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +53,7 @@ def test_fourier_matches_oracle_full_slices(tp, scan64):
     errs = [rel_l2(got[z], want[z]) for z in range(7)]  # odd count: the last slice has a zero partner
     note(f"rel-L2 per slice {errs}")
     assert max(errs) < 1e-5
+    assert_parity(got, want, "f32", label="fourier 90x7x64")
 
 
 @pytest.mark.parametrize("kind", ["shepp", "parzen"])
@@ -60,8 +61,7 @@ def test_fourier_windows(tp, scan64, kind):
     note(f"fourier {kind} 90x7x64")
     got = _run(tp, scan64, kind=kind)
     want = _oracle(scan64, slice(0, 7), kind=kind)
-    note(f"rel-L2 {rel_l2(got, want)}")
-    assert rel_l2(got, want) < 1e-5
+    assert_parity(got, want, "f32", label=f"fourier {kind}")
 
 
 def test_fourier_angles_over_full_circle_and_negative(tp, scan64):
@@ -73,7 +73,7 @@ def test_fourier_angles_over_full_circle_and_negative(tp, scan64):
     note("fourier 90 random angles in [-pi, 2pi)")
     got = _run(tp, scan64, angles=ang)
     want = _oracle(scan64, slice(0, 7), angles=ang)
-    assert rel_l2(got, want) < 1e-5
+    assert_parity(got, want, "f32", label="fourier random angles")
 
 
 @pytest.mark.parametrize("n_vox", [48, 100])
@@ -84,8 +84,7 @@ def test_fourier_voxel_grid_sizes(tp, scan64, n_vox):
     got = _run(tp, scan64, n_vox=n_vox)
     want = _oracle(scan64, slice(0, 7), N=n_vox)
     assert got.shape == (7, n_vox, n_vox)
-    note(f"rel-L2 {rel_l2(got, want)}")
-    assert rel_l2(got, want) < 1e-5
+    assert_parity(got, want, "f32", label=f"fourier n_vox {n_vox}")
 
 
 @pytest.mark.parametrize("n,rows,center", [(63, 3, 30.0), (100, 1, 61.7), (64, 2, 20.25)])
@@ -97,9 +96,7 @@ def test_fourier_detector_widths_and_axes(tp, n, rows, center):
     note(f"fourier n={n} rows={rows} centre={center}")
     got = _run(tp, s)
     want = _oracle(s, slice(0, rows))
-    e = rel_l2(got, want)
-    note(f"rel-L2 {e}")
-    assert e < 1e-5
+    assert_parity(got, want, "f32", label=f"fourier n={n} rows={rows}")
 
 
 def test_fourier_passes_bitwise(tp, scan64):
@@ -147,6 +144,7 @@ def test_fourier_paper_geometry_sampled(tp):
         want = oracle.fourier_fbp_points(s.proj[:, i], s.dark[:, i], s.flat[:, i], s.angles, s.center, 2048,
                                          ix, iy)
         errs.append(rel_l2(got[i, iy, ix], want))
+        assert_parity(got[i, iy, ix], want, "f32", label=f"fourier paper geometry row {rows[i]}")
     note(f"rel-L2 at sampled voxels {errs}")
     assert max(errs) < 1e-5, errs
     torch.cuda.empty_cache()
@@ -174,6 +172,7 @@ def test_fourier_bench_launch_shape_sampled(tp):
         want = oracle.fourier_fbp_points(host["proj"][:, i], host["dark"][:, i], host["flat"][:, i], s.angles,
                                          s.center, 2048, ix, iy)
         errs.append(rel_l2(got[i, iy, ix], want))
+        assert_parity(got[i, iy, ix], want, "f32", label=f"fourier bench chunk row {rows[i]}")
     note(f"rel-L2 at sampled voxels {errs}")
     assert max(errs) < 1e-5, errs
     plan.close()
@@ -194,6 +193,7 @@ def test_fourier_register_transform_sizes(tp, n):
     for i in range(2):
         want = oracle.fourier_fbp_points(s.proj[:, i], s.dark[:, i], s.flat[:, i], s.angles, s.center, n, ix, iy)
         errs.append(rel_l2(got[i, iy, ix], want))
+        assert_parity(got[i, iy, ix], want, "f32", label=f"fourier n={n} row {i}")
     note(f"rel-L2 at sampled voxels {errs}")
     assert max(errs) < 1e-5, errs
     torch.cuda.empty_cache()
@@ -210,9 +210,7 @@ def test_fourier_widest_detector(tp):
     ix = rng.integers(0, 8192, 48)
     iy = rng.integers(0, 8192, 48)
     want = oracle.fourier_fbp_points(s.proj[:, 0], s.dark[:, 0], s.flat[:, 0], s.angles, s.center, 8192, ix, iy)
-    e = rel_l2(got[0, iy, ix], want)
-    note(f"rel-L2 at sampled voxels {e}")
-    assert e < 1e-5
+    assert_parity(got[0, iy, ix], want, "f32", label="fourier widest detector")
     torch.cuda.empty_cache()
 
 

@@ -2,8 +2,9 @@
 import numpy as np
 import pytest
 
+import oracle
 from paper_2209_08450_amd import synth
-from tests._util import note, to_dev, to_host
+from tests._util import assert_parity, note, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +57,41 @@ def test_pipeline_bitwise_equals_monolithic(env, graphs, poison, storage):
     if graphs:
         assert st.graph_replays == len(chunks)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_pipeline_matches_oracle(env, storage):
+    # the pipelined volume, uneven chunks 7/13/32 through three streams with
+    # graphs, against the FP64 oracle's FBP of the same scan: every slice,
+    # chunk-boundary slices included, element by element
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    chunks = pipeline.uneven_chunks(100, (7, 13, 32))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, storage=storage, use_graphs=True)
+    got = np.full((100, 128, 128), np.nan, np.float32)
+    note(f"pipeline vs oracle {storage}")
+    pl.run(chunks, _source(s), _sink(got))
+    want = oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center)
+    assert_parity(got, want, storage, label="pipeline 90 x 100 x 128, chunks 7/13/32")
+    edges = sorted({z for z0, z1 in chunks for z in (z0, z1 - 1)})
+    assert_parity(got[edges], want[edges], storage, label="pipeline chunk-boundary slices")
+
+
+def test_pipeline_fourier_matches_oracle_at_chunk_boundaries(env):
+    # the Fourier-domain path through the pipeline: the first and last slice of
+    # every chunk at sampled voxels against the oracle's direct sum
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    chunks = pipeline.uneven_chunks(100, (32, 16))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, method="fourier")
+    got = np.full((100, 128, 128), np.nan, np.float32)
+    note("pipeline fourier vs oracle")
+    pl.run(chunks, _source(s), _sink(got))
+    rng = np.random.default_rng(21)
+    ix, iy = rng.integers(0, 128, 96), rng.integers(0, 128, 96)
+    for z in sorted({z for z0, z1 in chunks for z in (z0, z1 - 1)}):
+        want = oracle.fourier_fbp_points(s.proj[:, z], s.dark[:, z], s.flat[:, z], s.angles, s.center, 128, ix, iy)
+        assert_parity(got[z][iy, ix], want, "f32", label=f"pipeline fourier slice {z}")
 
 
 def test_pipeline_parzen_bitwise_equals_monolithic(env):
