@@ -32,6 +32,10 @@ Functions follow the paper (arXiv 2209.08450):
   geometry (tilted rotation axis, bilinear interpolation; Section 2.2 names
   this use of the direct method).
 * ``power_lambda_max`` / ``ls_solve`` -- gradient least squares with the pair.
+* ``lprec.lprec_backproject`` / ``lprec.lprec_fbp`` -- the log-polar-based
+  backprojection ("LpRec", Sections 2.2 and 3): per span of angles, a
+  convolution in log-polar coordinates by FFTs between B-spline
+  interpolations to and from the log-polar grid (module ``oracle.lprec``).
 
 Parity status: every function here is pinned by closed forms, invariants or
 brute force in ``tests/test_oracle_*.py`` except where noted in a function's
@@ -71,3 +75,4 @@ from .fbp import (  # noqa: F401
     num_threads,
     set_num_threads,
 )
+from . import lprec  # noqa: F401,E402
