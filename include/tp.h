@@ -193,6 +193,28 @@ tp_status tp_normalize(const uint16_t* proj, int64_t proj_stride,
                        void* workspace, size_t workspace_bytes, void* stream);
 
 /* --------------------------------------------------------------------------
+ * tp_normalize without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, arguments, layouts and results as
+ * tp_normalize; D and 1/max(F - D, 1) live instead in a file-scope device
+ * array of 2 x TP_NOALLOC_MAX_PIXELS floats (64 MiB), one per GPU, kept until
+ * the process ends.  Its address is looked up on the first call on each
+ * device (that device must be current); the call allocates nothing.
+ * Limit: n_rows * n_det <= TP_NOALLOC_MAX_PIXELS (e.g. 2048 rows of a
+ * 4096-column detector); larger calls return TP_EINVAL, enqueue nothing.
+ * Every call on one GPU shares that array: calls that can overlap on one
+ * device (different streams, or host threads without ordering) race and may
+ * produce wrong sinograms.  Nothing in the array needs clearing: each call
+ * writes every entry it reads.
+ * ------------------------------------------------------------------------ */
+#define TP_NOALLOC_MAX_PIXELS (8388608LL)
+tp_status tp_normalize_noalloc(const uint16_t* proj, int64_t proj_stride,
+                               const uint16_t* dark, int32_t n_dark,
+                               const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                               int32_t n_angles, int32_t n_rows, int32_t n_det,
+                               tp_dtype out_dtype, void* sino, void* stream);
+
+/* --------------------------------------------------------------------------
  * Filter of detector rows by FFT (paper Section 2.2, padding per Section 3):
  * each row p[0..n) is padded to L by replicating its end values, with the data
  * at offset floor((L - n)/2); y = IFFT(H . FFT(u)), H = tp_filter_response of

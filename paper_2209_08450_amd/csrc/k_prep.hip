@@ -8,10 +8,25 @@
 //   One work-group per (projection a, row r): it moves a whole detector row,
 //   so both the projection-major read and the sinogram-major write are
 //   contiguous; 8 counts per thread per 16-byte load where the row allows.
+//
+// The allocation-free variant keeps D and rden in `scratch`, a file-scope
+// device array (one copy per GPU, held until the process ends); host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device.
+#include <mutex>
+
 #include "tp_internal.h"
 
 namespace tp {
+
+// D at [0, kNoAllocPixels), rden at [kNoAllocPixels, 2 kNoAllocPixels).
+static __device__ __align__(256) float scratch[2 * kNoAllocPixels];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_addr[kMaxScratchDevices] = {};
 
 __global__ void __launch_bounds__(256)
 k_darkflat(RawInput in, int n_rows, int n_det, float* __restrict__ dmean, float* __restrict__ rden) {
@@ -61,6 +76,24 @@ k_normalize(RawInput in, const float* __restrict__ dmean, const float* __restric
 }
 
 }  // namespace
+
+hipError_t normalize_scratch(float** dmean, float** den) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = static_cast<float*>(p);
+    }
+    *dmean = g_scratch_addr[dev];
+    *den = g_scratch_addr[dev] + kNoAllocPixels;
+    return hipSuccess;
+}
 
 hipError_t launch_darkflat(const RawInput& in, int n_rows, int n_det, float* dmean, float* den,
                            hipStream_t st) {

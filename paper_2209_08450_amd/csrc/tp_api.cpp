@@ -17,6 +17,8 @@
 
 #include "tp_internal.h"
 
+static_assert(TP_NOALLOC_MAX_PIXELS == tp::kNoAllocPixels, "header limit and scratch size disagree");
+
 struct FourierEntry {
     void* block = nullptr;  // one allocation holding the tables
     tp::FourierTables t{};
@@ -845,6 +847,31 @@ tp_status tp_normalize(const uint16_t* proj, int64_t proj_stride, const uint16_t
     float* den = reinterpret_cast<float*>(static_cast<char*>(workspace) + need / 2);
     tp::RawInput in{proj, proj_stride, dark, flat, frame_stride, n_dark, n_flat};
     hipError_t e = tp::launch_darkflat(in, n_rows, n_det, dmean, den, st);
+    if (e != hipSuccess) return hip_fail(e, "darkflat launch");
+    e = tp::launch_normalize(in, dmean, den, n_angles, n_rows, n_det, out_dtype, sino, st);
+    if (e != hipSuccess) return hip_fail(e, "normalize launch");
+    return TP_OK;
+}
+
+tp_status tp_normalize_noalloc(const uint16_t* proj, int64_t proj_stride, const uint16_t* dark, int32_t n_dark,
+                               const uint16_t* flat, int32_t n_flat, int64_t frame_stride, int32_t n_angles,
+                               int32_t n_rows, int32_t n_det, tp_dtype out_dtype, void* sino, void* stream) {
+    tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, n_angles, n_rows,
+                            n_det);
+    if (s != TP_OK) return s;
+    if (!valid_dtype(out_dtype)) return fail(TP_EINVAL, "bad out_dtype %d", out_dtype);
+    if (!sino) return fail(TP_EINVAL, "sino is null");
+    const int64_t pixels = static_cast<int64_t>(n_rows) * n_det;
+    if (pixels > TP_NOALLOC_MAX_PIXELS)
+        return fail(TP_EINVAL, "n_rows*n_det=%lld exceeds the allocation-free limit of %lld pixels",
+                    static_cast<long long>(pixels), static_cast<long long>(TP_NOALLOC_MAX_PIXELS));
+    float* dmean = nullptr;
+    float* den = nullptr;
+    hipError_t e = tp::normalize_scratch(&dmean, &den);
+    if (e != hipSuccess) return hip_fail(e, "scratch address of the allocation-free normaliser");
+    auto st = static_cast<hipStream_t>(stream);
+    tp::RawInput in{proj, proj_stride, dark, flat, frame_stride, n_dark, n_flat};
+    e = tp::launch_darkflat(in, n_rows, n_det, dmean, den, st);
     if (e != hipSuccess) return hip_fail(e, "darkflat launch");
     e = tp::launch_normalize(in, dmean, den, n_angles, n_rows, n_det, out_dtype, sino, st);
     if (e != hipSuccess) return hip_fail(e, "normalize launch");

@@ -98,6 +98,14 @@ struct LaminoTables {
     int rows;          // detector rows of the projections (per call)
 };
 
+// ---- allocation-free normalisation ----
+// Pixels (n_rows * n_det) whose D and 1/max(F - D, 1) fit the file-scope
+// scratch array of the allocation-free normaliser (2 x 32 MiB of FP32).
+constexpr int64_t kNoAllocPixels = int64_t(1) << 23;
+// Addresses of that array's two halves on the current device, looked up once
+// per device with hipGetSymbolAddress.
+hipError_t normalize_scratch(float** dmean, float** den);
+
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_darkflat(const RawInput& in, int n_rows, int n_det, float* dmean, float* den,
                            hipStream_t st);

@@ -60,6 +60,8 @@ _filter_response = _proto("tp_filter_response", _c_i32, _c_i32, _c_i32, ctypes.P
 _normalize_ws = _proto("tp_normalize_workspace_bytes", _c_sz, _c_i32, _c_i32)
 _normalize = _proto("tp_normalize", _c_i32, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32,
                     _c_i32, _c_i32, _c_vp, _c_vp, _c_sz, _c_vp)
+_normalize_noalloc = _proto("tp_normalize_noalloc", _c_i32, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
+                            _c_i32, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp)
 _filter = _proto("tp_filter", _c_i32, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp)
 _backproject = _proto("tp_backproject", _c_i32, _c_vp, _c_vp, _c_i32, _c_i32, _c_f, _c_vp, _c_i32, _c_vp)
 _radon = _proto("tp_radon", _c_i32, _c_vp, _c_vp, _c_i32, _c_vp, _c_vp, _c_sz, _c_vp)
@@ -312,6 +314,31 @@ def normalize(proj, dark, flat, out_dtype="f32", out=None, workspace=None, strea
     _check(_normalize(pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_angles, n_rows, n_det, code,
                       _dev(out, "out"), _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
                       _stream_ptr(stream)))
+    return out
+
+
+NOALLOC_MAX_PIXELS = 1 << 23
+
+
+def normalize_noalloc(proj, dark, flat, out, stream=None):
+    """``normalize`` through the allocation-free entry point: the caller passes
+    the output sinogram (``out``, [rows][n_angles][n_det] of F32/F16/BF16); the
+    library's per-device scratch array holds the dark/flat tables, so the call
+    allocates nothing.  Calls that overlap on one device race."""
+    n_angles, n_rows, n_det = (int(s) for s in proj.shape)
+    pp, ps = _raw_strides(proj, "proj", n_det)
+    dp, fs = _raw_strides(dark, "dark", n_det)
+    fp, fs2 = _raw_strides(flat, "flat", n_det)
+    if fs != fs2:
+        raise ValueError("dark and flat must share one frame stride")
+    if dark.shape[1] != n_rows or flat.shape[1] != n_rows:
+        raise ValueError("dark/flat rows must match proj rows")
+    if out is None:
+        raise ValueError("normalize_noalloc needs a caller-supplied output")
+    code = dtype_code(out.dtype)
+    _out(out, (n_rows, n_angles, n_det), torch_dtype(code), proj)
+    _check(_normalize_noalloc(pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_angles, n_rows, n_det,
+                              code, _dev(out, "out"), _stream_ptr(stream)))
     return out
 
 

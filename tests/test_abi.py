@@ -137,6 +137,23 @@ def test_normalize_validation(tp):
     assert tp._normalize_ws(0, 8) == 0
 
 
+def test_normalize_noalloc_validation(tp):
+    """Host checks of the allocation-free normaliser, before any device call:
+    the raw-data checks of tp_normalize, and sizes beyond its scratch array."""
+    nul = ctypes.c_void_p()
+    p = ctypes.c_void_p(0x100000)
+    f = tp._normalize_noalloc
+    assert f(nul, 0, p, 1, p, 1, 0, 4, 2, 8, 0, p, nul) == tp.TP_EINVAL
+    assert f(p, 0, p, 0, p, 1, 0, 4, 2, 8, 0, p, nul) == tp.TP_EINVAL
+    assert f(p, 0, p, 1, p, 1, 0, 4, 2, 8, 9, p, nul) == tp.TP_EINVAL and "dtype" in tp.last_error()
+    assert f(p, 0, p, 1, p, 1, 0, 4, 2, 8, 0, nul, nul) == tp.TP_EINVAL and "sino" in tp.last_error()
+    # one row past the limit of n_rows * n_det pixels (2048 x 4096)
+    assert f(p, 0, p, 1, p, 1, 0, 4, 2049, 4096, 0, p, nul) == tp.TP_EINVAL
+    assert "allocation-free limit" in tp.last_error()
+    assert f(p, 0, p, 1, p, 1, 0, 4, 1, 8388609, 0, p, nul) == tp.TP_EINVAL
+    assert tp.NOALLOC_MAX_PIXELS == 2048 * 4096
+
+
 def test_fourier_validation_without_plan(tp):
     nul = ctypes.c_void_p()
     p = ctypes.c_void_p(0x100000)
