@@ -90,6 +90,15 @@ def parse():
     ap.add_argument("--fourier-half-width", type=int, default=0, help="Gaussian truncation radius (0 = 6)")
     ap.add_argument("--fourier-slices", type=int, default=3, help="slices checked against the oracle's direct sum")
     ap.add_argument("--fourier-points", type=int, default=96, help="sampled voxels per checked slice")
+    ap.add_argument("--no-lprec", action="store_true",
+                    help="skip the log-polar FBP section (tp_lprec_fbp_chunk on the same scan)")
+    ap.add_argument("--lprec-rows", type=int, default=32,
+                    help="rows per pass of the log-polar FBP (its workspace: about 1.1 GB per row at 2048^2)")
+    ap.add_argument("--lprec-slices", type=int, default=3, help="slices checked against the oracle's direct sum")
+    ap.add_argument("--lprec-points", type=int, default=96, help="sampled voxels per checked slice")
+    ap.add_argument("--single-lprec", action="store_true",
+                    help="instead: one tp_lprec_fbp_chunk of 32 rows of the timed scan shape (a short program for "
+                         "hardware-counter passes)")
     ap.add_argument("--no-lamino", action="store_true",
                     help="skip the laminography section (2048^2 x 256 slab from 2048 angles, axis tilted 63 degrees)")
     ap.add_argument("--single-lamino", action="store_true",
@@ -279,6 +288,8 @@ def main():
         return main_single_radon(args)
     if args.single_fourier:
         return main_single_fourier(args)
+    if args.single_lprec:
+        return main_single_lprec(args)
     if args.single_lamino:
         return main_single_lamino(args)
 
@@ -445,6 +456,11 @@ def main():
     if not args.no_fourier:
         fourier = bench_fourier(args, scan, plan, vol, chunks, stream, updates, log)
 
+    # ---------------- log-polar FBP on the same scan ----------------
+    lprec = None
+    if not args.no_lprec:
+        lprec = bench_lprec(args, scan, plan, vol, stream, updates, log)
+
     # ---------------- laminography (tilted axis) ----------------
     lamino = None
     if not args.no_lamino:
@@ -527,6 +543,7 @@ def main():
         "cpu_baseline": cpu,
         "differentiation": ls,
         "fourierrec": fourier,
+        "lprec": lprec,
         "laminography": lamino,
         "pipeline": pipe,
         "paper_context": {"linerec_fp32_2048cubed_total_s_A100_incl_io": 80.0},
@@ -676,6 +693,139 @@ def bench_fourier(args, scan, plan, vol, chunks, stream, updates, log):
                        "unit": "Gvoxel-angle updates/s", "cores": oracle.num_threads(),
                        "sample": f"direct sum at {cpu_pts} voxels ({L + 1} terms per voxel-angle), {cpu_t:.1f} s"},
     }
+
+
+def lprec_conv_flop_per_pair(g: dict) -> float:
+    """Algorithmic work of the log-polar convolution kernel per pair of slices:
+    for every span and sigma frequency, the angle column's FFT (length NA/M),
+    the product with the kernel's transform (NA complex multiplies) and the
+    inverse FFT (length NA); 5 n log2 n real flop per complex FFT of length n,
+    6 per complex multiply."""
+    na_c = g["NA"] // g["M"]
+    fft = lambda n: 5.0 * n * math.log2(n)
+    return float(g["spans"]) * g["Ns"] * (fft(na_c) + 6.0 * g["NA"] + fft(g["NA"]))
+
+
+def lprec_conv_bytes_per_pair(g: dict) -> float:
+    """Algorithmic bytes of the convolution kernel per pair: the angle columns
+    read (spans x Ns x n_span complex FP32) and the kept rows written
+    (spans x rows x Ns complex FP32)."""
+    return 8.0 * g["spans"] * g["Ns"] * (g["n_span"] + g["rows"])
+
+
+def bench_lprec(args, scan, plan, vol, stream, updates, log):
+    """Log-polar FBP (tp_lprec_fbp_chunk) of the resident scan, in passes of
+    --lprec-rows rows: time per volume, per-stage times of one pass, the
+    convolution kernel's roofline and parity at sampled voxels against the
+    oracle's direct sum of trigonometric interpolants (the sum it
+    approximates)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2209_08450_amd import tp
+
+    n, na, rows = plan.n_det, plan.n_angles, vol.shape[0]
+    chunk = args.lprec_rows
+    plan.lprec_prepare(args.filter)
+    g = tp.lprec_grid(na, plan.n_vox)
+    ws = torch.empty(plan.lprec_workspace_bytes(chunk), dtype=torch.uint8, device=vol.device)
+    chunks = [(z0, min(rows, z0 + chunk)) for z0 in range(0, rows, chunk)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    for e in evs:
+        e.record(stream)
+
+    def step(record):
+        for ci, (z0, z1) in enumerate(chunks):
+            tp.lprec_fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], out=vol[z0:z1],
+                               workspace=ws, events=evs if (record and ci == 0) else None, kind=args.filter)
+
+    # a few steps only: one volume takes seconds
+    steps, warmup = max(1, min(args.steps, 3)), min(args.warmup, 1)
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log(f"[lprec] warmup done; timing {steps} steps")
+    stage = np.zeros(6)
+    t0 = time.perf_counter()
+    for s_i in range(steps):
+        step(True)
+        torch.cuda.synchronize()
+        stage += [evs[i].elapsed_time(evs[i + 1]) for i in range(6)]
+        log(f"[lprec] step {s_i + 1}/{steps} done")
+    sec = (time.perf_counter() - t0) / steps
+    stage /= steps
+    pairs = (chunk + 1) // 2
+    conv_ms = float(stage[3])
+    flop = lprec_conv_flop_per_pair(g) * pairs
+    achieved = flop / (conv_ms * 1e-3) / 1e12
+    gbs = lprec_conv_bytes_per_pair(g) * pairs / (conv_ms * 1e-3) / 1e9
+    log(f"[lprec] {sec:.3f} s per volume; convolution {conv_ms:.2f} ms per {chunk}-row pass "
+        f"({achieved:.1f} TFLOP/s, {gbs:.0f} GB/s algorithmic)")
+    ns = min(args.lprec_slices, rows)
+    zs = [int((k + 0.5) * rows / ns) for k in range(ns)] if ns > 0 else []
+    rng = np.random.default_rng(8192)
+    errs, num, den, cpu_t, cpu_pts = [], 0.0, 0.0, 0.0, 0
+    for z in zs:
+        ix = rng.integers(0, n, args.lprec_points)
+        iy = rng.integers(0, n, args.lprec_points)
+        got = vol[z][torch.from_numpy(iy).to(vol.device), torch.from_numpy(ix).to(vol.device)].cpu().numpy()
+        p = scan.proj[:, z, :].cpu().numpy().view(np.uint16)
+        d = scan.dark[:, z, :].cpu().numpy().view(np.uint16)
+        f = scan.flat[:, z, :].cpu().numpy().view(np.uint16)
+        log(f"[lprec] oracle direct sum at {args.lprec_points} voxels of slice {z}")
+        t1 = time.perf_counter()
+        want = oracle.fourier_fbp_points(p, d, f, scan.angles, plan.center, n, ix, iy, kind=args.filter)
+        cpu_t += time.perf_counter() - t1
+        cpu_pts += len(ix)
+        e = got.astype(np.float64) - want
+        num += float(np.sum(e ** 2))
+        den += float(np.sum(want ** 2))
+        errs.append(float(np.max(np.abs(e)) / np.max(np.abs(want))))
+    rel = math.sqrt(num / den) if den > 0 else None
+    if rel is not None:
+        log(f"[lprec] rel-L2 vs FP64 direct sum at sampled voxels: {rel:.3e}")
+    return {
+        "method": "log-polar backprojection: half-sample quintic row splines, per span of angles a convolution in "
+                  "(angle, log-radius) by FFTs, quintic spline evaluation at the voxels",
+        "grid": {k: g[k] for k in ("spans", "n_span", "Ns", "NA", "M", "rows", "nj", "os", "eps")},
+        "s_per_volume": round(sec, 4),
+        "gups_equivalent": round(updates / sec / 1e9, 2),
+        "rows_per_pass": chunk,
+        "steps": steps,
+        "stage_ms_first_pass": {k: round(float(v), 2) for k, v in
+                                zip(("darkflat", "row_splines", "logradial_fft", "conv", "sigma_ifft", "interp"),
+                                    stage)},
+        "rel_l2_vs_fp64_direct_sum_sampled": rel,
+        "max_abs_over_max_ref_per_slice": errs,
+        "parity_sample": f"{args.lprec_points} voxels of each of slices {zs}",
+        "roofline_conv": {"bound": "alu", "kernel": "k_lp_conv", "achieved": round(achieved, 2),
+                          "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                          "hbm_GBs_algorithmic": round(gbs, 1), "launch_ms": round(conv_ms, 3),
+                          "flop_per_launch": flop},
+        "cpu_oracle_direct_sum": {"value": round(cpu_pts * na / cpu_t / 1e9, 6) if cpu_t > 0 else None,
+                                  "unit": "Gvoxel-angle updates/s", "cores": oracle.num_threads(),
+                                  "sample": f"direct sum at {cpu_pts} voxels, {cpu_t:.1f} s"},
+    }
+
+
+def main_single_lprec(args):
+    import torch
+
+    from paper_2209_08450_amd import synth, tp
+
+    n, na, rows = args.n, args.angles, 32
+    scan = synth.ellipsoid_scan_torch(seed=2, n_angles=na, n_rows=rows, n_det=n, device="cuda", center=n / 2.0)
+    plan = tp.Plan(scan.angles, n, n / 2.0)
+    plan.lprec_prepare(args.filter)
+    vol = torch.empty((rows, n, n), dtype=torch.float32, device="cuda")
+    ws = torch.empty(plan.lprec_workspace_bytes(rows), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    tp.lprec_fbp_chunk(plan, scan.proj, scan.dark, scan.flat, out=vol, workspace=ws, kind=args.filter)
+    torch.cuda.synchronize()
+    print(json.dumps({"single_lprec": {"rows": rows, "n": n, "angles": na, "grid": tp.lprec_grid(na, n)}}),
+          flush=True)
+    plan.close()
 
 
 LAMINO = dict(n=2048, rows=2048, angles=2048, slices=256, tilt=1.1, center_v=1023.5)

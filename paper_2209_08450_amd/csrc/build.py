@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libtp.so")
-SOURCES = ["tp_api.cpp", "k_prep.hip", "k_filter.hip", "k_backproject.hip", "k_radon.hip", "k_fourier.hip", "k_lamino.hip", "tp_io.cpp", "tp_tune.cpp", "k_peak.hip"]
+SOURCES = ["tp_api.cpp", "k_prep.hip", "k_filter.hip", "k_backproject.hip", "k_radon.hip", "k_fourier.hip", "k_lamino.hip", "tp_io.cpp", "tp_tune.cpp", "k_peak.hip", "k_lprec.hip"]
 ARCH = os.environ.get("TP_OFFLOAD_ARCH", "gfx950")
 
 

@@ -29,6 +29,11 @@ struct LaminoEntry {
     tp::LaminoTables t{};
 };
 
+struct LprecEntry {
+    void* block = nullptr;
+    tp::LprecTables t{};
+};
+
 struct tp_plan {
     int device = -1;
     int na = 0, n = 0, N = 0, nb = 0;
@@ -45,6 +50,8 @@ struct tp_plan {
     mutable std::map<std::pair<int, int>, FourierEntry> fr;
     // laminographic backprojection tables per (tilt, row centre, slice count)
     mutable std::map<std::tuple<double, double, int>, LaminoEntry> lam;
+    // log-polar backprojection tables per (filter window, spans, oversampling, origin margin)
+    mutable std::map<std::tuple<int, int, double, double>, LprecEntry> lp;
 };
 
 namespace {
@@ -543,6 +550,245 @@ tp_status fourier_half_width(int32_t half_width, int* msp) {
     return TP_OK;
 }
 
+// ---- log-polar backprojection: grid sizing, tables, workspace ----
+constexpr int kLpSigmaMargin = 12;   // sigma points of taper beyond the data range
+constexpr int kLpAngleMargin = 16;   // psi rows beyond the image sector
+constexpr int kLpWindowMargin = 4;   // sigma points kept beyond the image's rho range
+constexpr int kLpMinFft = 1024;
+constexpr int kLpMaxFft = 16384;
+constexpr int kLpMaxSpans = 4;       // the evaluation kernel holds every span's weights in registers
+constexpr int kLpDefaultSpans = 3;
+constexpr double kLpDefaultOs = 1.2;
+constexpr double kLpDefaultEps = 0.5;
+
+int pow2_at_least(int64_t v) {
+    int r = 0;
+    while ((int64_t{1} << r) < v) ++r;
+    return 1 << r;
+}
+
+// Sizing rule of the log-polar grids (see tp.h, tp_lprec_grid_query).
+tp_status lp_grid(int na, int N, int spans, double os, double eps, tp_lprec_grid* g) {
+    if (spans == 0) spans = kLpDefaultSpans;
+    if (os == 0.0) os = kLpDefaultOs;
+    if (eps == 0.0) eps = kLpDefaultEps;
+    if (spans < 2 || spans > kLpMaxSpans) return fail(TP_EINVAL, "spans=%d not in 2..%d", spans, kLpMaxSpans);
+    if (!(os >= 0.25 && os <= 8.0)) return fail(TP_EINVAL, "oversampling %g not in [0.25, 8]", os);
+    if (!(eps >= 0.05 && eps <= 4.0)) return fail(TP_EINVAL, "origin margin %g not in [0.05, 4]", eps);
+    if (na < 2 * spans) return fail(TP_EUNSUPPORTED, "%d angles for %d spans", na, spans);
+    if (N < 2) return fail(TP_EUNSUPPORTED, "slice side %d", N);
+    tp_lprec_grid r{};
+    r.spans = spans;
+    r.os = os;
+    r.eps = eps;
+    r.dtheta = M_PI / na;
+    const int half = N / 2;
+    r.R = std::sqrt(2.0) * half + 2.0;
+    r.n_span = (na + spans - 1) / spans;
+    const double phi_max = 0.5 * (r.n_span - 1) * r.dtheta;
+    r.phi0 = -phi_max;
+    r.a0 = (1.0 + eps) * r.R / std::cos(phi_max);
+    r.s_min = r.a0 * std::cos(phi_max) - r.R;
+    r.s_max = r.a0 + r.R;
+    const double lo = std::log(r.s_min), hi = std::log(r.s_max);
+    const int64_t n_need = static_cast<int64_t>(std::ceil((hi - lo) * os * r.s_max)) + 2 * kLpSigmaMargin + 1;
+    r.Ns = std::max(kLpMinFft, pow2_at_least(n_need));
+    if (r.Ns > kLpMaxFft)
+        return fail(TP_EUNSUPPORTED, "log-polar grid needs %lld sigma points (> %d); lower the oversampling",
+                    static_cast<long long>(n_need), kLpMaxFft);
+    r.delta = (hi - lo) / (r.Ns - 1 - 2 * kLpSigmaMargin);
+    r.sigma0 = lo - kLpSigmaMargin * r.delta;
+    r.M = pow2_at_least(static_cast<int64_t>(std::ceil(os * r.dtheta * r.s_max)));
+    r.dpsi = r.dtheta / r.M;
+    const double psi_max = std::asin(r.R / r.a0);
+    r.m_lo = static_cast<int32_t>(std::floor((-psi_max - r.phi0) / r.dpsi)) - kLpAngleMargin;
+    const int m_hi = static_cast<int32_t>(std::ceil((psi_max - r.phi0) / r.dpsi)) + kLpAngleMargin;
+    r.rows = m_hi - r.m_lo + 1;
+    r.D = r.rows + r.M * (r.n_span - 1);
+    r.NA = std::max(kLpMinFft, pow2_at_least(r.D));
+    if (r.NA > kLpMaxFft)
+        return fail(TP_EUNSUPPORTED, "log-polar grid needs %d angle points (> %d); lower the oversampling", r.D,
+                    kLpMaxFft);
+    r.d_lo = r.m_lo - r.M * (r.n_span - 1);
+    if (!(std::fabs(r.d_lo * r.dpsi) < M_PI / 2) || !(std::fabs((r.d_lo + r.D - 1) * r.dpsi) < M_PI / 2))
+        return fail(TP_EUNSUPPORTED, "angular margin reaches 90 degrees; increase the origin margin");
+    r.j_lo = static_cast<int32_t>(std::floor((std::log(r.a0 - r.R) - r.sigma0) / r.delta)) - kLpWindowMargin;
+    const int j_hi = static_cast<int32_t>(std::ceil((std::log(r.a0 + r.R) - r.sigma0) / r.delta)) + kLpWindowMargin;
+    r.nj = j_hi - r.j_lo + 1;
+    *g = r;
+    return TP_OK;
+}
+
+double bspline5_hat(double nu) {  // sampled transform of the centred quintic B-spline, nu in cycles per sample
+    const double w = 2.0 * M_PI * nu;
+    return (66.0 + 52.0 * std::cos(w) + 2.0 * std::cos(2.0 * w)) / 120.0;
+}
+
+bool lp_angles_uniform(const tp_plan* plan) {
+    const double d = M_PI / plan->na;
+    for (int a = 0; a < plan->na; ++a)
+        if (std::fabs(plan->angles[a] - (plan->angles[0] + a * d)) > 1e-9) return false;
+    return true;
+}
+
+struct LpSizes {
+    size_t rows, ghat, fhat, F;  // bytes per pair of slices
+};
+
+LpSizes lp_sizes(const tp_plan* plan, const tp_lprec_grid& g) {
+    const int L = plan->filt.L;
+    const size_t nmb = static_cast<size_t>((g.rows + 15) / 16);
+    LpSizes z;
+    z.rows = sizeof(float2) * static_cast<size_t>(plan->na) * 2 * L;
+    z.ghat = sizeof(float2) * static_cast<size_t>(g.spans) * g.Ns * g.n_span;
+    z.fhat = sizeof(float2) * static_cast<size_t>(g.spans) * nmb * g.Ns * 16;
+    z.F = sizeof(float2) * static_cast<size_t>(g.spans) * g.rows * g.nj;
+    return z;
+}
+
+size_t lp_workspace(const tp_plan* plan, const tp_lprec_grid& g, int32_t n_rows, int64_t P) {
+    const LpSizes z = lp_sizes(plan, g);
+    return tp_normalize_workspace_bytes(n_rows, plan->n) + align256(static_cast<size_t>(P) * std::max(z.rows, z.fhat)) +
+           align256(static_cast<size_t>(P) * std::max(z.ghat, z.F));
+}
+
+tp_status lprec_tables(const tp_plan* plan, tp_filter_kind kind, const tp_lprec_grid& g, tp::LprecTables* out,
+                       hipStream_t st_for_capture_check) {
+    std::lock_guard<std::mutex> lk(plan->fr_mu);
+    const auto key = std::make_tuple(static_cast<int>(kind), g.spans, g.os, g.eps);
+    auto it = plan->lp.find(key);
+    if (it != plan->lp.end()) {
+        *out = it->second.t;
+        return TP_OK;
+    }
+    if (st_for_capture_check != nullptr) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st_for_capture_check, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+            return fail(TP_EUNSUPPORTED, "log-polar tables not built; call tp_lprec_prepare before capture");
+    }
+    const int na = plan->na, n = plan->n, L = plan->filt.L, Ns = g.Ns, NA = g.NA, NAc = g.NA / g.M;
+    const double pos0 = plan->center + (L - n) / 2;
+    std::vector<double> H;
+    filter_response_fp64(L, kind, H);
+    std::vector<float> T0(L), taper(Ns), preA(NA), colscale(Ns);
+    std::vector<float2> T1(L);
+    for (int k = 0; k < L; ++k) {
+        const int ks = k < L / 2 ? k : k - L;
+        const double t0 = H[k] / (L * bspline5_hat(static_cast<double>(ks) / (2.0 * L)));
+        T0[k] = static_cast<float>(t0);
+        const double ph = M_PI * ks / L;
+        T1[k] = k == L / 2 ? make_float2(0.0f, 0.0f)
+                           : make_float2(static_cast<float>(t0 * std::cos(ph)), static_cast<float>(t0 * std::sin(ph)));
+    }
+    std::vector<double> E(Ns), A(g.n_span), cd(g.D), cbp(g.spans), sbp(g.spans);
+    const double ramp = kLpSigmaMargin - 2;
+    for (int j = 0; j < Ns; ++j) {
+        E[j] = std::exp(g.sigma0 + g.delta * j);
+        const double tl = std::min(std::max((j - 2.0) / ramp, 0.0), 1.0);
+        const double th = std::min(std::max((Ns - 3.0 - j) / ramp, 0.0), 1.0);
+        taper[j] = static_cast<float>(std::min(0.5 - 0.5 * std::cos(M_PI * tl), 0.5 - 0.5 * std::cos(M_PI * th)));
+        colscale[j] = static_cast<float>(g.dtheta / (static_cast<double>(NA) * Ns * bspline5_hat(static_cast<double>(j) / Ns)));
+    }
+    for (int k = 0; k < g.n_span; ++k) A[k] = g.a0 * std::cos((k - 0.5 * (g.n_span - 1)) * g.dtheta) - pos0;
+    for (int d = 0; d < g.D; ++d) cd[d] = std::log(std::cos((g.d_lo + d) * g.dpsi)) / (g.delta * Ns);
+    for (int v = 0; v < NA; ++v) preA[v] = static_cast<float>(1.0 / bspline5_hat(static_cast<double>(v) / NA));
+    for (int p = 0; p < g.spans; ++p) {
+        const double beta = plan->angles[0] + (p * g.n_span + 0.5 * (g.n_span - 1)) * g.dtheta;
+        cbp[p] = std::cos(beta);
+        sbp[p] = std::sin(beta);
+    }
+    auto twiddles = [](int len) {
+        std::vector<float2> tw(len);
+        for (int k = 0; k < len; ++k) {
+            const double ang = -2.0 * M_PI * static_cast<double>(k) / len;
+            tw[k] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang)));
+        }
+        return tw;
+    };
+    const std::vector<float2> twL = twiddles(L), twNs = twiddles(Ns), twNA = twiddles(NA), twNAc = twiddles(NAc);
+    struct Part {
+        const void* src;
+        size_t bytes;
+        char* dst;
+    };
+    std::vector<Part> parts = {{T0.data(), sizeof(float) * L, nullptr},        {T1.data(), sizeof(float2) * L, nullptr},
+                               {E.data(), sizeof(double) * Ns, nullptr},        {taper.data(), sizeof(float) * Ns, nullptr},
+                               {A.data(), sizeof(double) * g.n_span, nullptr},  {cd.data(), sizeof(double) * g.D, nullptr},
+                               {preA.data(), sizeof(float) * NA, nullptr},      {colscale.data(), sizeof(float) * Ns, nullptr},
+                               {cbp.data(), sizeof(double) * g.spans, nullptr}, {sbp.data(), sizeof(double) * g.spans, nullptr},
+                               {twL.data(), sizeof(float2) * L, nullptr},       {twNs.data(), sizeof(float2) * Ns, nullptr},
+                               {twNA.data(), sizeof(float2) * NA, nullptr},     {twNAc.data(), sizeof(float2) * NAc, nullptr}};
+    size_t total = 0;
+    for (const Part& q : parts) total += align256(q.bytes);
+    LprecEntry le;
+    hipError_t e = hipMalloc(&le.block, total);
+    if (e != hipSuccess) return fail(TP_ENOMEM, "hipMalloc(log-polar tables, %zu bytes): %s", total, hipGetErrorString(e));
+    char* b = static_cast<char*>(le.block);
+    for (Part& q : parts) {
+        q.dst = b;
+        b += align256(q.bytes);
+        if (e == hipSuccess) e = hipMemcpy(q.dst, q.src, q.bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(le.block);
+        return hip_fail(e, "hipMemcpy(log-polar tables)");
+    }
+    tp::LprecTables& t = le.t;
+    t.T0 = reinterpret_cast<const float*>(parts[0].dst);
+    t.T1 = reinterpret_cast<const float2*>(parts[1].dst);
+    t.E = reinterpret_cast<const double*>(parts[2].dst);
+    t.taper = reinterpret_cast<const float*>(parts[3].dst);
+    t.A = reinterpret_cast<const double*>(parts[4].dst);
+    t.cd = reinterpret_cast<const double*>(parts[5].dst);
+    t.preA = reinterpret_cast<const float*>(parts[6].dst);
+    t.colscale = reinterpret_cast<const float*>(parts[7].dst);
+    t.cb = reinterpret_cast<const double*>(parts[8].dst);
+    t.sb = reinterpret_cast<const double*>(parts[9].dst);
+    t.twL = reinterpret_cast<const float2*>(parts[10].dst);
+    t.twNs = reinterpret_cast<const float2*>(parts[11].dst);
+    t.twNA = reinterpret_cast<const float2*>(parts[12].dst);
+    t.twNAc = reinterpret_cast<const float2*>(parts[13].dst);
+    t.na = na;
+    t.n = n;
+    t.N = plan->N;
+    t.L = L;
+    t.log2L = ilog2(L);
+    t.spans = g.spans;
+    t.n_span = g.n_span;
+    t.Ns = Ns;
+    t.NA = NA;
+    t.M = g.M;
+    t.NAc = NAc;
+    t.log2NAc = ilog2(NAc);
+    t.D = g.D;
+    t.rows = g.rows;
+    t.nmb = (g.rows + 15) / 16;
+    t.m_lo = g.m_lo;
+    t.j_lo = g.j_lo;
+    t.nj = g.nj;
+    t.a0 = g.a0;
+    t.sigma0 = g.sigma0;
+    t.delta = g.delta;
+    t.phi0 = g.phi0;
+    t.dpsi = g.dpsi;
+    e = tp::prepare_lprec(t);
+    if (e != hipSuccess) {
+        (void)hipFree(le.block);
+        return hip_fail(e, "log-polar kernel attributes");
+    }
+    plan->lp.emplace(key, le);
+    *out = t;
+    return TP_OK;
+}
+
+tp_status lp_plan_grid(const tp_plan* plan, int32_t spans, double os, double eps, tp_lprec_grid* g) {
+    if (!lp_angles_uniform(plan))
+        return fail(TP_EUNSUPPORTED, "the log-polar method needs angles theta_0 + a pi / n_angles (equally spaced "
+                    "over a half turn, increasing)");
+    if (plan->filt.L > 8192) return fail(TP_EUNSUPPORTED, "pad length %d > 8192", plan->filt.L);
+    return lp_grid(plan->na, plan->N, spans, os, eps, g);
+}
+
 }  // namespace
 
 extern "C" {
@@ -711,6 +957,10 @@ tp_status tp_plan_destroy(tp_plan* plan) {
         if (e == hipSuccess) e = e2;
     }
     for (auto& kv : plan->lam) {
+        const hipError_t e2 = hipFree(kv.second.block);
+        if (e == hipSuccess) e = e2;
+    }
+    for (auto& kv : plan->lp) {
         const hipError_t e2 = hipFree(kv.second.block);
         if (e == hipSuccess) e = e2;
     }
@@ -1141,6 +1391,111 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj,
                                     st);
         if (e != hipSuccess) return hip_fail(e, "Fourier column-transform launch");
         if ((e = mark(5)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        first = false;
+    }
+    return TP_OK;
+}
+
+tp_status tp_lprec_grid_query(int32_t n_angles, int32_t n_vox, int32_t spans, double os, double eps,
+                              tp_lprec_grid* out) {
+    if (!out) return fail(TP_EINVAL, "out is null");
+    if (n_angles <= 0 || n_vox <= 0) return fail(TP_EINVAL, "n_angles=%d n_vox=%d must be positive", n_angles, n_vox);
+    return lp_grid(n_angles, n_vox, spans, os, eps, out);
+}
+
+size_t tp_lprec_workspace_bytes(const tp_plan* plan, int32_t n_rows, int32_t spans, double os, double eps) {
+    if (!plan || n_rows <= 0) return 0;
+    tp_lprec_grid g;
+    if (lp_plan_grid(plan, spans, os, eps, &g) != TP_OK) return 0;
+    return lp_workspace(plan, g, n_rows, (n_rows + 1) / 2);
+}
+
+tp_status tp_lprec_prepare(const tp_plan* plan, tp_filter_kind kind, int32_t spans, double os, double eps) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
+    tp_lprec_grid g;
+    tp_status s = lp_plan_grid(plan, spans, os, eps, &g);
+    if (s != TP_OK) return s;
+    tp::LprecTables t;
+    return lprec_tables(plan, kind, g, &t, nullptr);
+}
+
+tp_status tp_lprec_fbp_chunk(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride, const uint16_t* dark,
+                             int32_t n_dark, const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                             int32_t n_rows, tp_filter_kind kind, int32_t spans, double os, double eps,
+                             void* workspace, size_t workspace_bytes, float* vol, void* stream) {
+    return tp_lprec_fbp_chunk_events(plan, proj, proj_stride, dark, n_dark, flat, n_flat, frame_stride, n_rows, kind,
+                                     spans, os, eps, workspace, workspace_bytes, vol, stream, nullptr);
+}
+
+tp_status tp_lprec_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride,
+                                    const uint16_t* dark, int32_t n_dark, const uint16_t* flat, int32_t n_flat,
+                                    int64_t frame_stride, int32_t n_rows, tp_filter_kind kind, int32_t spans,
+                                    double os, double eps, void* workspace, size_t workspace_bytes, float* vol,
+                                    void* stream, void* const* events) {
+    if (!plan) return fail(TP_EINVAL, "plan is null");
+    tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, plan->na, n_rows,
+                            plan->n);
+    if (s != TP_OK) return s;
+    if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
+    if (!vol) return fail(TP_EINVAL, "vol is null");
+    if (!workspace) return fail(TP_EINVAL, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(TP_EINVAL, "workspace not 256-byte aligned");
+    tp_lprec_grid g;
+    if ((s = lp_plan_grid(plan, spans, os, eps, &g)) != TP_OK) return s;
+    const int pairs = (n_rows + 1) / 2;
+    const size_t df = tp_normalize_workspace_bytes(n_rows, plan->n);
+    if (workspace_bytes < lp_workspace(plan, g, n_rows, 1))
+        return fail(TP_EINVAL, "workspace %zu < %zu bytes (one pair of rows)", workspace_bytes,
+                    lp_workspace(plan, g, n_rows, 1));
+    const LpSizes z = lp_sizes(plan, g);
+    int64_t P = static_cast<int64_t>((workspace_bytes - df) / (std::max(z.rows, z.fhat) + std::max(z.ghat, z.F)));
+    P = std::min<int64_t>(std::max<int64_t>(P, 1), pairs);
+    P = std::min<int64_t>(P, 65535);
+    while (P > 1 && lp_workspace(plan, g, n_rows, P) > workspace_bytes) --P;
+    auto st = static_cast<hipStream_t>(stream);
+    tp::LprecTables t;
+    if ((s = lprec_tables(plan, kind, g, &t, st)) != TP_OK) return s;
+    float* dmean = static_cast<float*>(workspace);
+    float* den = reinterpret_cast<float*>(static_cast<char*>(workspace) + df / 2);
+    char* regA = static_cast<char*>(workspace) + df;
+    char* regB = regA + align256(static_cast<size_t>(P) * std::max(z.rows, z.fhat));
+    float2* rowsbuf = reinterpret_cast<float2*>(regA);
+    float2* fhat = reinterpret_cast<float2*>(regA);
+    float2* ghat = reinterpret_cast<float2*>(regB);
+    float2* F = reinterpret_cast<float2*>(regB);
+    tp::RawInput in{proj, proj_stride, dark, flat, frame_stride, n_dark, n_flat};
+    bool first = true;
+    auto mark = [&](int i) -> hipError_t {
+        if (!first || !events || !events[i]) return hipSuccess;
+        return hipEventRecord(static_cast<hipEvent_t>(events[i]), st);
+    };
+    hipError_t e = mark(0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    e = tp::launch_darkflat(in, n_rows, plan->n, dmean, den, st);
+    if (e != hipSuccess) return hip_fail(e, "darkflat launch");
+    for (int r0 = 0; r0 < n_rows; r0 += static_cast<int>(2 * P)) {
+        const int rows = std::min(static_cast<int>(2 * P), n_rows - r0);
+        const int pp = (rows + 1) / 2;
+        tp::RawInput ip = in;
+        ip.proj = proj + static_cast<int64_t>(r0) * plan->n;
+        const int64_t roff = static_cast<int64_t>(r0) * plan->n;
+        if ((e = mark(1)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_lprec_rows(ip, rows, dmean + roff, den + roff, t, rowsbuf, st);
+        if (e != hipSuccess) return hip_fail(e, "log-polar row-spline launch");
+        if ((e = mark(2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_lprec_logradial(t, rowsbuf, pp, ghat, st);
+        if (e != hipSuccess) return hip_fail(e, "log-polar resampling launch");
+        if ((e = mark(3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_lprec_conv(t, ghat, pp, fhat, st);
+        if (e != hipSuccess) return hip_fail(e, "log-polar convolution launch");
+        if ((e = mark(4)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_lprec_sigma(t, fhat, pp, F, st);
+        if (e != hipSuccess) return hip_fail(e, "log-polar sigma-transform launch");
+        if ((e = mark(5)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        e = tp::launch_lprec_interp(t, F, pp, rows, vol + static_cast<int64_t>(r0) * plan->N * plan->N, st);
+        if (e != hipSuccess) return hip_fail(e, "log-polar evaluation launch");
+        if ((e = mark(6)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         first = false;
     }
     return TP_OK;

@@ -98,6 +98,32 @@ struct LaminoTables {
     int rows;          // detector rows of the projections (per call)
 };
 
+// Tables of the log-polar backprojection (one set per plan, filter window,
+// span count, oversampling and origin margin).  Spans p < spans hold n_span
+// angle slots each (slot k of span p is angle p * n_span + k, empty past the
+// last angle), rotated by beta_p so that slot k sits at phi_k = phi0 + k dtheta.
+// Grids: sigma_j = sigma0 + j delta (j < Ns), psi_m = phi0 + m dpsi,
+// dpsi = dtheta / M, stored rows m_lo .. m_lo + rows - 1, stored sigma
+// window j_lo .. j_lo + nj - 1.
+struct LprecTables {
+    const float* T0;        // [L]   H[k] / (L B(k~ / 2L)): row spline multiplier, even half-samples
+    const float2* T1;       // [L]   T0[k] exp(i pi k~ / L), zero at L/2: odd half-samples
+    const double* E;        // [Ns]  exp(sigma_j)
+    const float* taper;     // [Ns]  raised-cosine window of the log-radial samples
+    const double* A;        // [n_span] a0 cos(phi_k) - pos0
+    const double* cd;       // [D]   log(cos((d_lo + d) dpsi)) / (delta Ns)
+    const float* preA;      // [NA]  1 / B(nu / NA)
+    const float* colscale;  // [Ns]  dtheta / (NA Ns B(eta / Ns))
+    const double* cb;       // [spans] cos(beta_p), FP64
+    const double* sb;       // [spans] sin(beta_p)
+    const float2* twL;      // [L]   exp(-2 pi i k / L)
+    const float2* twNs;     // [Ns]
+    const float2* twNA;     // [NA]
+    const float2* twNAc;    // [NAc]
+    int na, n, N, L, log2L, spans, n_span, Ns, NA, M, NAc, log2NAc, D, rows, nmb, m_lo, j_lo, nj;
+    double a0, sigma0, delta, phi0, dpsi;
+};
+
 // ---- allocation-free normalisation ----
 // Pixels (n_rows * n_det) whose D and 1/max(F - D, 1) fit the file-scope
 // scratch array of the allocation-free normaliser (2 x 32 MiB of FP32).
@@ -136,6 +162,17 @@ hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const
                                float* vol, hipStream_t st);
 
 int lamino_slices_per_block();
+
+// log-polar backprojection (k_lprec.hip); `pairs` slice pairs per launch
+hipError_t launch_lprec_rows(const RawInput& in, int rows, const float* dmean, const float* rden,
+                             const LprecTables& t, float2* out, hipStream_t st);
+hipError_t launch_lprec_logradial(const LprecTables& t, const float2* rows, int pairs, float2* ghat, hipStream_t st);
+hipError_t launch_lprec_conv(const LprecTables& t, const float2* ghat, int pairs, float2* fhat, hipStream_t st);
+hipError_t launch_lprec_sigma(const LprecTables& t, const float2* fhat, int pairs, float2* F, hipStream_t st);
+hipError_t launch_lprec_interp(const LprecTables& t, const float2* F, int pairs, int rows, float* vol,
+                               hipStream_t st);
+// Sets the dynamic-LDS limits of the instances a table set uses (no launch).
+hipError_t prepare_lprec(const LprecTables& t);
 
 // measurement instruments (k_peak.hip)
 hipError_t launch_peak_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);

@@ -78,6 +78,27 @@ _fourier_chunk = _proto("tp_fourier_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c
 _fourier_chunk_events = _proto("tp_fourier_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
                                _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp,
                                ctypes.POINTER(_c_vp))
+
+
+class LprecGrid(ctypes.Structure):
+    """tp_lprec_grid: sizes and geometry of the log-polar grids."""
+    _fields_ = [(k, ctypes.c_int32) for k in ("spans", "n_span", "Ns", "M", "NA", "D", "rows", "m_lo", "d_lo",
+                                             "j_lo", "nj")] + \
+               [(k, ctypes.c_double) for k in ("os", "eps", "dtheta", "R", "phi0", "a0", "s_min", "s_max", "delta",
+                                              "sigma0", "dpsi")]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lprec_grid = _proto("tp_lprec_grid_query", _c_i32, _c_i32, _c_i32, _c_i32, _c_d, _c_d, ctypes.POINTER(LprecGrid))
+_lprec_ws = _proto("tp_lprec_workspace_bytes", _c_sz, _c_vp, _c_i32, _c_i32, _c_d, _c_d)
+_lprec_prepare = _proto("tp_lprec_prepare", _c_i32, _c_vp, _c_i32, _c_i32, _c_d, _c_d)
+_lprec_chunk = _proto("tp_lprec_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
+                      _c_i32, _c_i32, _c_i32, _c_d, _c_d, _c_vp, _c_sz, _c_vp, _c_vp)
+_lprec_chunk_events = _proto("tp_lprec_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
+                             _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_d, _c_d, _c_vp, _c_sz, _c_vp, _c_vp,
+                             ctypes.POINTER(_c_vp))
 _lamino_prepare = _proto("tp_lamino_prepare", _c_i32, _c_vp, _c_d, _c_d, _c_i32)
 _lamino = _proto("tp_lamino_backproject", _c_i32, _c_vp, _c_vp, _c_i32, _c_i32, _c_d, _c_d, _c_i32, _c_i32, _c_i32,
                  _c_f, _c_vp, _c_vp)
@@ -244,6 +265,14 @@ class Plan:
     def fourier_prepare(self, kind="ramp", half_width: int = 0):
         """Build the Fourier-domain path's tables (before graph capture)."""
         _check(_fourier_prepare(self._h, filter_code(kind), int(half_width)))
+
+    def lprec_workspace_bytes(self, n_rows: int, spans: int = 0, os: float = 0.0, eps: float = 0.0) -> int:
+        """Workspace for the log-polar FBP of n_rows rows in one pass (0: unsupported plan)."""
+        return int(_lprec_ws(self._h, int(n_rows), int(spans), float(os), float(eps)))
+
+    def lprec_prepare(self, kind="ramp", spans: int = 0, os: float = 0.0, eps: float = 0.0):
+        """Build the log-polar path's tables (before graph capture)."""
+        _check(_lprec_prepare(self._h, filter_code(kind), int(spans), float(os), float(eps)))
 
 
 def tune_load(path) -> None:
@@ -483,6 +512,55 @@ def fourier_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, st
             raise ValueError("record each event once before passing it (torch creates it lazily)")
         arr = (_c_vp * 6)(*[_c_vp(e.cuda_event) if e is not None else _c_vp() for e in events])
         _check(_fourier_chunk_events(*args, arr))
+    return out
+
+
+def lprec_grid(n_angles: int, n_vox: int, spans: int = 0, os: float = 0.0, eps: float = 0.0) -> dict:
+    """The log-polar grid the library picks (host only, tp_lprec_grid_query)."""
+    g = LprecGrid()
+    _check(_lprec_grid(int(n_angles), int(n_vox), int(spans), float(os), float(eps), ctypes.byref(g)))
+    return g.as_dict()
+
+
+def lprec_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, stream=None, events=None,
+                    kind="ramp", spans: int = 0, os: float = 0.0, eps: float = 0.0):
+    """Raw counts of a row chunk -> log-polar FBP slices [rows][N][N] (float32)
+    (tp_lprec_fbp_chunk).  Same inputs as ``fbp_chunk``; the plan's angles must
+    be theta_0 + a pi / n_angles.  ``spans``, ``os``, ``eps``: span count,
+    grid oversampling and origin margin (0: 3, 1.2, 0.5).  ``workspace``:
+    default ``plan.lprec_workspace_bytes(rows, ...)`` (one pass).  ``events``:
+    optional list of seven recorded-once ``torch.cuda.Event`` objects (or
+    None entries) marking the stages of the first pass."""
+    torch = _torch()
+    n_angles, n_rows, n_det = (int(s) for s in proj.shape)
+    if n_angles != plan.n_angles or n_det != plan.n_det:
+        raise ValueError("proj does not match the plan geometry")
+    pp, ps = _raw_strides(proj, "proj", n_det)
+    dp, fs = _raw_strides(dark, "dark", n_det)
+    fp, fs2 = _raw_strides(flat, "flat", n_det)
+    if fs != fs2:
+        raise ValueError("dark and flat must share one frame stride")
+    if dark.shape[1] != n_rows or flat.shape[1] != n_rows:
+        raise ValueError("dark/flat rows must match proj rows")
+    kcode = filter_code(kind)
+    if workspace is None:
+        need = plan.lprec_workspace_bytes(n_rows, spans, os, eps)
+        if need == 0:
+            _check(_lprec_prepare(plan.handle, kcode, int(spans), float(os), float(eps)))
+        workspace = _workspace(need, proj.device)
+    out = _out(out, (n_rows, plan.n_vox, plan.n_vox), torch.float32, proj)
+    args = (plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode, int(spans),
+            float(os), float(eps), _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+            _dev(out, "out"), _stream_ptr(stream))
+    if events is None:
+        _check(_lprec_chunk(*args))
+    else:
+        if len(events) != 7:
+            raise ValueError("events must hold seven entries")
+        if any(e is not None and not e.cuda_event for e in events):
+            raise ValueError("record each event once before passing it (torch creates it lazily)")
+        arr = (_c_vp * 7)(*[_c_vp(e.cuda_event) if e is not None else _c_vp() for e in events])
+        _check(_lprec_chunk_events(*args, arr))
     return out
 
 
