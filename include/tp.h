@@ -389,12 +389,14 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan,
  * (6) is evaluated at every voxel; the spans are summed.
  *
  * Accuracy: set by the grid resolution at the image's far side, os (grid
- * steps delta and dtheta / M at most 1 / (os (a0 + R))), and by the row
- * splines: about 1e-3 relative L2 at os = 1.2 on noisy phantom scans,
- * 2e-4 floor from the half-sample row splines; see tp_lprec_grid_query.
+ * steps delta and dtheta / M at most 1 / (os (a0 + R)); the power-of-two
+ * lengths usually give more), and by the row splines: at the defaults,
+ * relative L2 against the exact sum of 9e-4 on the 12-bit 2048 x 2048
+ * phantom scan (2048 angles) and 6e-4 on 256-column scans; see
+ * tp_lprec_grid_query for the grid a call uses.
  *
- * Parameters: spans in 2..4 (0: 3), os in [0.25, 8] (0: 1.2), eps in
- * [0.05, 4] (0: 0.5).  Ns and NA (the angle FFT length) are powers of two
+ * Parameters: spans in 2..4 (0: 3), os in [0.25, 8] (0: 1.0), eps in
+ * [0.05, 4] (0: 1.0).  Ns and NA (the angle FFT length) are powers of two
  * in [1024, 16384] and the pad length at most 8192, else TP_EUNSUPPORTED.
  * ------------------------------------------------------------------------ */
 typedef struct {

@@ -79,7 +79,7 @@ def _pow2_at_least(v: int) -> int:
     return 1 << max(0, int(math.ceil(math.log2(max(v, 1)))))
 
 
-def lprec_params(n_angles: int, N: int, spans: int = 3, os: float = 1.2, eps: float = 0.5) -> dict:
+def lprec_params(n_angles: int, N: int, spans: int = 3, os: float = 1.0, eps: float = 1.0) -> dict:
     """Grid sizes and geometry of the log-polar backprojection (steps 2-4 of the
     module docstring) for n_angles equally spaced angles over a half turn and
     an N x N slice."""
@@ -271,7 +271,7 @@ def span_points(C: np.ndarray, pr: dict, beta: float, ix, iy, deg: int = 5) -> n
 
 
 def lprec_backproject_points(y: np.ndarray, theta0: float, pos0: float, N: int, ix, iy, spans: int = 3,
-                             os: float = 1.2, eps: float = 0.5, deg: int = 5) -> np.ndarray:
+                             os: float = 1.0, eps: float = 1.0, deg: int = 5) -> np.ndarray:
     """Log-polar backprojection of one slice's padded filtered rows y [n_angles][L]
     (angles theta0 + a pi / n_angles) at voxels (ix, iy); pos0 = centre + pad
     offset.  Approximates ``fourier_backproject_points`` (scale pi / n_angles)."""

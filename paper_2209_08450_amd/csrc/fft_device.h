@@ -11,7 +11,6 @@ namespace tp {
 namespace {
 
 constexpr int kMaxPerThread4 = 4;  // radix-4 butterflies per thread (L / (4 B) with B = L / 16)
-constexpr int kMaxPerThread2 = 8;  // radix-2 butterflies per thread
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -21,23 +20,27 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 // multiply by -i
 __device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
-// In-place forward DFT X[k] = sum_m x[m] exp(-2 pi i k m / L) of buf[0..L).
-// Caller must have synchronised after writing buf; returns synchronised.
+// In-place forward DFT X[k] = sum_m x[m] exp(-2 pi i k m / L) of buf[0..L),
+// with at most PT4 radix-4 butterflies (2 PT4 radix-2 ones) per thread, so
+// blockDim.x >= L / (4 PT4).  Caller must have synchronised after writing buf;
+// returns synchronised.
+template <int PT4 = kMaxPerThread4>
 __device__ void fft_forward_lds(float2* buf, int L, int log2L, const float2* __restrict__ tw) {
+    constexpr int PT2 = 2 * PT4;
     const int tid = threadIdx.x;
     const int B = blockDim.x;
     int Ns = 1;
     if (log2L & 1) {
         const int h = L >> 1;
-        float2 v0[kMaxPerThread2], v1[kMaxPerThread2];
+        float2 v0[PT2], v1[PT2];
 #pragma unroll
-        for (int c = 0; c < kMaxPerThread2; ++c) {
+        for (int c = 0; c < PT2; ++c) {
             const int j = tid + c * B;
             if (j < h) { v0[c] = buf[j]; v1[c] = buf[j + h]; }
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < kMaxPerThread2; ++c) {
+        for (int c = 0; c < PT2; ++c) {
             const int j = tid + c * B;
             if (j < h) { buf[2 * j] = cadd(v0[c], v1[c]); buf[2 * j + 1] = csub(v0[c], v1[c]); }
         }
@@ -47,9 +50,9 @@ __device__ void fft_forward_lds(float2* buf, int L, int log2L, const float2* __r
     const int q = L >> 2;
     for (; Ns < L; Ns <<= 2) {
         const int tstride = L / (Ns << 2);
-        float2 v[kMaxPerThread4][4];
+        float2 v[PT4][4];
 #pragma unroll
-        for (int c = 0; c < kMaxPerThread4; ++c) {
+        for (int c = 0; c < PT4; ++c) {
             const int j = tid + c * B;
             if (j < q) {
                 const int k = j & (Ns - 1);
@@ -73,7 +76,7 @@ __device__ void fft_forward_lds(float2* buf, int L, int log2L, const float2* __r
         }
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < kMaxPerThread4; ++c) {
+        for (int c = 0; c < PT4; ++c) {
             const int j = tid + c * B;
             if (j < q) {
                 const int k = j & (Ns - 1);
@@ -235,6 +238,91 @@ __device__ __forceinline__ void reg_fft(float2 (&x)[kRegPts], float2* lds, const
         reg_pass<L, 16, false>(x, lds, 256, tw, t);
         reg_exchange<L>(x, lds, t);
         reg_pass<L, (L >> 12), true>(x, lds, 4096, tw, t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same register transform with every twiddle held in registers.  A
+// thread's twiddles depend only on its index, so a kernel that runs many
+// transforms loads them once (reg_tw_load) instead of reading the table in
+// every pass of every transform.  Identical values and operation order as
+// reg_fft, so the results are bitwise the same.  1024 <= L <= 8192.
+// ---------------------------------------------------------------------------
+template <int L>
+struct RegTw {
+    static constexpr int log2L = (L == 1024) ? 10 : (L == 2048) ? 11 : (L == 4096) ? 12 : 13;
+    static constexpr int R3 = log2L == 10 ? 4 : (log2L == 11 ? 8 : 16);  // radix of the third pass
+    static constexpr int N3 = (kRegPts / R3) * (R3 - 1);
+    static constexpr int R4 = log2L == 13 ? 2 : 1;                        // fourth pass (L = 8192 only)
+    static constexpr int N4 = log2L == 13 ? (kRegPts / 2) : 1;
+    float2 p2[15];  // second pass: Ns = 16, radix 16, one butterfly per thread
+    float2 p3[N3];  // third pass: Ns = 256
+    float2 p4[N4];  // fourth pass: Ns = 4096
+};
+
+template <int L>
+__device__ __forceinline__ void reg_tw_load(RegTw<L>& w, const float2* __restrict__ tw, int t) {
+    static_assert(L >= 1024 && L <= 8192, "register twiddles cover 1024..8192");
+    constexpr int B = L / kRegPts;
+    {
+        const int step = (t & 15) * (L / 256);
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w.p2[r - 1] = tw[step * r];
+    }
+    constexpr int R3 = RegTw<L>::R3;
+#pragma unroll
+    for (int c = 0; c < kRegPts / R3; ++c) {
+        const int step = ((t + B * c) & 255) * (L / (256 * R3));
+#pragma unroll
+        for (int r = 1; r < R3; ++r) w.p3[c * (R3 - 1) + r - 1] = tw[step * r];
+    }
+    if constexpr (RegTw<L>::R4 == 2) {
+#pragma unroll
+        for (int c = 0; c < kRegPts / 2; ++c) w.p4[c] = tw[((t + B * c) & 4095) * (L / 8192)];
+    }
+}
+
+// reg_pass with the pass's twiddles from registers: w[c * (R - 1) + r - 1].
+template <int L, int R, bool LAST>
+__device__ __forceinline__ void reg_pass_w(float2 (&x)[kRegPts], float2* lds, int Ns, const float2* w, int t) {
+    constexpr int B = L / kRegPts;
+    constexpr int NBF = kRegPts / R;
+#pragma unroll
+    for (int c = 0; c < NBF; ++c) {
+        float2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = x[c + NBF * r];
+        const int j = t + B * c;
+        const int k = j & (Ns - 1);
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[c * (R - 1) + r - 1]);
+        }
+        Dft<R>::run(v);
+        if (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[c + NBF * r] = v[r];
+        } else {
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_pad(base + Ns * r)] = v[r];
+        }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void reg_fft_w(float2 (&x)[kRegPts], float2* lds, const RegTw<L>& w, int t) {
+    constexpr int R3 = RegTw<L>::R3;
+    reg_pass_w<L, 16, false>(x, lds, 1, w.p2, t);
+    reg_exchange<L>(x, lds, t);
+    reg_pass_w<L, 16, false>(x, lds, 16, w.p2, t);
+    reg_exchange<L>(x, lds, t);
+    if constexpr (RegTw<L>::R4 == 2) {
+        reg_pass_w<L, R3, false>(x, lds, 256, w.p3, t);
+        reg_exchange<L>(x, lds, t);
+        reg_pass_w<L, 2, true>(x, lds, 4096, w.p4, t);
+    } else {
+        reg_pass_w<L, R3, true>(x, lds, 256, w.p3, t);
     }
 }
 

@@ -152,7 +152,12 @@ k_filter_reg(const TI* in, TO* out, int64_t n_lines, int n, int off, FilterTable
 // prefetched into registers while the previous pair is transformed.
 constexpr int kPairsPerGroup = 8;
 
-template <int L, typename TO>
+// HALF: the detector fills the middle half of the padded row (n = L/2, off =
+// L/4, every power-of-two detector), so slots 0-3 are left padding, 4-11 data
+// and 12-15 right padding at compile time: padding slots load nothing and
+// hold no registers.  Otherwise the same tests run on the runtime offsets
+// (each is uniform over the work-group).
+template <int L, typename TO, bool HALF>
 __global__ void __launch_bounds__(L / kRegPts)
 k_norm_filter_reg(RawInput in, const float* __restrict__ dmean, const float* __restrict__ rden, int n_angles, int n,
                   int off, FilterTables ft, TO* out) {
@@ -165,9 +170,15 @@ k_norm_filter_reg(RawInput in, const float* __restrict__ dmean, const float* __r
     const int g1 = min(pairs, g0 + kPairsPerGroup);
     const float* dm = dmean + static_cast<int64_t>(r) * n;
     const float* dn = rden + static_cast<int64_t>(r) * n;
-    // slot s holds padded position t + B s; loading at the column clamped onto
-    // the detector gives the edge-replicated padding directly.  Raw counts of a
-    // pair: row 2g in the low half, row 2g + 1 (or 0) in the high half.
+    // the thread's FFT twiddles, the same for every transform of the group
+    RegTw<L> w;
+    reg_tw_load<L>(w, ft.tw, threadIdx.x);
+    // slot s holds padded position t + B s; a slot whose B positions all lie
+    // left (right) of the detector holds the edge value in every thread
+    auto left_pad = [&](int s) { return HALF ? s < 4 : B * s + B - 1 - off < 0; };
+    auto right_pad = [&](int s) { return HALF ? s >= 12 : B * s - off > n - 1; };
+    auto column = [&](int t, int s) { return HALF ? t + B * s - off : min(max(t + B * s - off, 0), n - 1); };
+    // raw counts of a pair: row 2g in the low half, row 2g + 1 (or 0) in the high half
     auto load_pair = [&](int g, int t, uint32_t (&raw)[kRegPts]) {
         const int a0 = 2 * g;
         const uint16_t* p0 = in.proj + a0 * in.proj_stride + static_cast<int64_t>(r) * n;
@@ -175,38 +186,62 @@ k_norm_filter_reg(RawInput in, const float* __restrict__ dmean, const float* __r
         const uint16_t* p1 = has1 ? p0 + in.proj_stride : p0;
 #pragma unroll
         for (int s = 0; s < kRegPts; ++s) {
-            const int c = min(max(t + B * s - off, 0), n - 1);
+            if (left_pad(s) || right_pad(s)) continue;
+            const int c = column(t, s);
             const uint32_t hi = p1[c];
             raw[s] = p0[c] | (has1 ? hi << 16 : 0u);
         }
     };
     uint32_t cur[kRegPts], nxt[kRegPts];
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) cur[s] = nxt[s] = 0u;
     load_pair(g0, threadIdx.x, cur);
+    const float dL = dm[0], eL = dn[0], dR = dm[n - 1], eR = dn[n - 1];
 #pragma unroll 1
     for (int g = g0; g < g1; ++g) {
-        // an opaque thread index per pair: per-thread offsets (columns, FFT
-        // twiddles, LDS and output positions) are recomputed in the loop
-        // instead of being hoisted into registers held across it
+        // an opaque thread index per pair: per-thread offsets (columns, LDS and
+        // output positions) are recomputed in the loop instead of being
+        // hoisted into registers held across it
         int t = threadIdx.x;
         asm volatile("" : "+v"(t));
         if (g + 1 < g1) load_pair(g + 1, t, nxt);
         const int a0 = 2 * g;
         const bool has1 = a0 + 1 < n_angles;
+        const uint16_t* p0 = in.proj + a0 * in.proj_stride + static_cast<int64_t>(r) * n;
+        const uint16_t* p1 = has1 ? p0 + in.proj_stride : p0;
+        const float2 left = make_float2(neglog_counts(static_cast<float>(p0[0]), dL, eL),
+                                        has1 ? neglog_counts(static_cast<float>(p1[0]), dL, eL) : 0.0f);
+        const float2 right = make_float2(neglog_counts(static_cast<float>(p0[n - 1]), dR, eR),
+                                         has1 ? neglog_counts(static_cast<float>(p1[n - 1]), dR, eR) : 0.0f);
         float2 x[kRegPts];
 #pragma unroll
         for (int s = 0; s < kRegPts; ++s) {
-            const int c = min(max(t + B * s - off, 0), n - 1);
-            const float d = dm[c], e = dn[c];
-            x[s] = make_float2(neglog_counts(static_cast<float>(cur[s] & 0xffffu), d, e),
-                               has1 ? neglog_counts(static_cast<float>(cur[s] >> 16), d, e) : 0.0f);
+            if (left_pad(s)) {
+                x[s] = left;
+            } else if (right_pad(s)) {
+                x[s] = right;
+            } else {
+                const int c = column(t, s);
+                const float d = dm[c], e = dn[c];
+                x[s] = make_float2(neglog_counts(static_cast<float>(cur[s] & 0xffffu), d, e),
+                                   has1 ? neglog_counts(static_cast<float>(cur[s] >> 16), d, e) : 0.0f);
+            }
         }
-        reg_filter<L>(x, lds, ft, t);
+        // y = conj of IFFT(H . FFT(u)) (H real and even, 1/L folded in)
+        reg_fft_w<L>(x, lds, w, t);
+#pragma unroll
+        for (int s = 0; s < kRegPts; ++s) {
+            const float h = ft.H[t + B * s];
+            x[s] = make_float2(x[s].x * h, 0.0f - x[s].y * h);
+        }
+        reg_fft_w<L>(x, lds, w, t);
         TO* o0 = out + (static_cast<int64_t>(r) * n_angles + a0) * n;
         TO* o1 = o0 + n;
 #pragma unroll
         for (int s = 0; s < kRegPts; ++s) {
+            if (HALF && (s < 4 || s >= 12)) continue;
             const int j = t + B * s - off;
-            if (j >= 0 && j < n) {
+            if (HALF || (j >= 0 && j < n)) {
                 store_from_float(o0, j, x[s].x);
                 if (has1) store_from_float(o1, j, 0.0f - x[s].y);
             }
@@ -295,10 +330,17 @@ hipError_t launch_norm_filter_t(const RawInput& in, const float* dmean, const fl
     hipError_t e = hipSuccess;
 #define TP_REG_CASE(LL)                                                                                    \
     case LL:                                                                                              \
-        e = launch_reg<LL>(k_norm_filter_reg<LL, TO>, reg_grid, st, lds);                                 \
-        if (e != hipSuccess) return e;                                                                    \
-        hipLaunchKernelGGL((k_norm_filter_reg<LL, TO>), reg_grid, dim3(LL / kRegPts), lds, st, in, dmean, den, \
-                           n_angles, n, off, ft, pout);                                                   \
+        if (2 * n == LL) {                                                                                \
+            e = launch_reg<LL>(k_norm_filter_reg<LL, TO, true>, reg_grid, st, lds);                       \
+            if (e != hipSuccess) return e;                                                                \
+            hipLaunchKernelGGL((k_norm_filter_reg<LL, TO, true>), reg_grid, dim3(LL / kRegPts), lds, st, in, \
+                               dmean, den, n_angles, n, off, ft, pout);                                   \
+        } else {                                                                                          \
+            e = launch_reg<LL>(k_norm_filter_reg<LL, TO, false>, reg_grid, st, lds);                      \
+            if (e != hipSuccess) return e;                                                                \
+            hipLaunchKernelGGL((k_norm_filter_reg<LL, TO, false>), reg_grid, dim3(LL / kRegPts), lds, st, in, \
+                               dmean, den, n_angles, n, off, ft, pout);                                   \
+        }                                                                                                 \
         return hipGetLastError();
     switch (ft.L) {
         TP_REG_CASE(1024)

@@ -79,7 +79,7 @@ int rows_block(int L) { return L / 16 < 64 ? 64 : (L / 16 > 1024 ? 1024 : L / 16
 // ---------------------------------------------------------------------------
 constexpr int kRowSlots = 16;  // L / blockDim elements per thread (blockDim >= L / 16)
 
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
 k_lp_rows(RawInput in, int rows, const float* __restrict__ dmean, const float* __restrict__ rden, LprecTables t,
           float2* __restrict__ out) {
     extern __shared__ float2 buf[];
@@ -244,6 +244,90 @@ k_lp_conv(const float2* __restrict__ ghat, LprecTables t, int pairs, float2* __r
     }
 }
 
+// The same convolution for NA = 8192 and 16384.  Beside a kernel column held
+// in registers the register transform of these lengths spills, so the column
+// (transformed, prefilter and scale folded in) is built once per plan into a
+// table kt[eta][nu] (k_lp_ktable) and read per pair; the 3 spans share it.
+template <int NA>
+__global__ void __launch_bounds__(NA / kRegPts)
+k_lp_ktable(LprecTables t, float2* __restrict__ kt) {
+    extern __shared__ float2 lds[];
+    constexpr int B = NA / kRegPts;
+    const int tid = threadIdx.x;
+    const int NS = t.Ns;
+    const int eta = blockIdx.x;
+    const int eta_s = eta < NS / 2 ? eta : eta - NS;
+    const bool nyq = eta == NS / 2;
+    float2 x[kRegPts];
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const int d = tid + B * s;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (d < t.D) {
+            double ph = static_cast<double>(eta_s) * t.cd[d];
+            ph -= floor(ph);
+            float sn, cs;
+            sincospif(2.0f * static_cast<float>(ph), &sn, &cs);
+            v = nyq ? make_float2(cs, 0.0f) : make_float2(cs, sn);
+        }
+        x[s] = v;
+    }
+    reg_fft<NA>(x, lds, t.twNA, tid);
+    const float cscale = t.colscale[eta];
+    float2* dst = kt + static_cast<int64_t>(eta) * NA;
+#pragma unroll
+    for (int s = 0; s < kRegPts; ++s) {
+        const float f = t.preA[tid + B * s] * cscale;
+        dst[tid + B * s] = make_float2(x[s].x * f, x[s].y * f);
+    }
+}
+
+template <int NA>
+__global__ void __launch_bounds__(NA / kRegPts)
+k_lp_conv_tab(const float2* __restrict__ ghat, LprecTables t, int pairs, float2* __restrict__ fhat) {
+    extern __shared__ float2 lds[];
+    constexpr int B = NA / kRegPts;
+    const int tid = threadIdx.x;
+    const int NS = t.Ns;
+    const int id = blockIdx.x;
+    const int xcd = id & 7, r = id >> 3;
+    const int c = ((r >> 4) * 8 + xcd) * 16 + (r & 15);
+    const int span = c / NS, eta = c - span * NS;
+    const float2* kcol = t.kt + static_cast<int64_t>(eta) * NA;
+    const int first = t.M * (t.n_span - 1);
+    const int NAc = t.NAc;
+#pragma unroll 1
+    for (int p = 0; p < pairs; ++p) {
+        const float2* src = ghat + ((static_cast<int64_t>(p) * t.spans + span) * (NS / 16) + (eta >> 4)) *
+                                       t.n_span * 16 + (eta & 15);
+        __syncthreads();
+        for (int k = tid; k < NAc; k += B)
+            lds[k] = k < t.n_span ? src[static_cast<int64_t>(k) * 16] : make_float2(0.0f, 0.0f);
+        __syncthreads();
+        // an opaque thread index per pair: the transform's twiddle loads and
+        // the per-slot offsets are not hoisted out of the pair loop into
+        // registers held across it (they would spill)
+        int ti = tid;
+        asm volatile("" : "+v"(ti));
+        fft_forward_lds(lds, NAc, t.log2NAc, t.twNAc);
+        float2 x[kRegPts];
+#pragma unroll
+        for (int s = 0; s < kRegPts; ++s)
+            x[s] = cconj(cmul(lds[(ti + B * s) & (NAc - 1)], kcol[ti + B * s]));
+        __syncthreads();
+        reg_fft<NA>(x, lds, t.twNA, ti);
+        int to = tid;
+        asm volatile("" : "+v"(to));
+        float2* dst = fhat + (static_cast<int64_t>(p) * t.spans + span) * t.nmb * NS * 16;
+#pragma unroll
+        for (int s = 0; s < kRegPts; ++s) {
+            const int m = to + B * s - first;
+            if (m >= 0 && m < t.rows)
+                dst[(static_cast<int64_t>(m >> 4) * NS + eta) * 16 + (m & 15)] = cconj(x[s]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Inverse transform over sigma: one work-group per (pair, span, two rows);
 // the 8 work-groups of one 16-row line group run back to back on one XCD.
@@ -353,11 +437,29 @@ hipError_t launch_logradial_t(const LprecTables& t, const float2* rows, int pair
     return hipGetLastError();
 }
 
+size_t conv_lds_bytes(int NA, int NAc) {
+    return std::max(reg_lds_bytes(NA), static_cast<size_t>(NAc) * sizeof(float2));
+}
+
 template <int NA>
 hipError_t launch_conv_t(const LprecTables& t, const float2* ghat, int pairs, float2* fhat, hipStream_t st) {
-    const size_t lds = std::max(reg_lds_bytes(NA), static_cast<size_t>(t.NAc) * sizeof(float2));
-    hipLaunchKernelGGL(k_lp_conv<NA>, dim3(t.spans * t.Ns), dim3(NA / kRegPts), lds, st, ghat, t, pairs, fhat);
+    const size_t lds = conv_lds_bytes(NA, t.NAc);
+    if constexpr (NA >= 8192) {
+        hipLaunchKernelGGL(k_lp_conv_tab<NA>, dim3(t.spans * t.Ns), dim3(NA / kRegPts), lds, st, ghat, t, pairs, fhat);
+    } else {
+        hipLaunchKernelGGL(k_lp_conv<NA>, dim3(t.spans * t.Ns), dim3(NA / kRegPts), lds, st, ghat, t, pairs, fhat);
+    }
     return hipGetLastError();
+}
+
+template <int NA>
+hipError_t launch_ktable_t(const LprecTables& t, float2* kt, hipStream_t st) {
+    if constexpr (NA >= 8192) {
+        hipLaunchKernelGGL(k_lp_ktable<NA>, dim3(t.Ns), dim3(NA / kRegPts), reg_lds_bytes(NA), st, t, kt);
+        return hipGetLastError();
+    } else {
+        return hipSuccess;
+    }
 }
 
 template <int NS>
@@ -388,7 +490,13 @@ hipError_t prep_ns(const LprecTables& t) {
 
 template <int NA>
 hipError_t prep_na(const LprecTables& t) {
-    return lds_limit(k_lp_conv<NA>, std::max(reg_lds_bytes(NA), static_cast<size_t>(t.NAc) * 8));
+    if constexpr (NA >= 8192) {
+        hipError_t e = lds_limit(k_lp_ktable<NA>, reg_lds_bytes(NA));
+        if (e != hipSuccess) return e;
+        return lds_limit(k_lp_conv_tab<NA>, conv_lds_bytes(NA, t.NAc));
+    } else {
+        return lds_limit(k_lp_conv<NA>, conv_lds_bytes(NA, t.NAc));
+    }
 }
 
 }  // namespace
@@ -416,6 +524,14 @@ hipError_t launch_lprec_logradial(const LprecTables& t, const float2* rows, int 
 
 hipError_t launch_lprec_conv(const LprecTables& t, const float2* ghat, int pairs, float2* fhat, hipStream_t st) {
     TP_LP_DISPATCH(t.NA, launch_conv_t, t, ghat, pairs, fhat, st)
+}
+
+size_t lprec_ktable_bytes(int Ns, int NA) {
+    return NA >= 8192 ? static_cast<size_t>(Ns) * NA * sizeof(float2) : 0;
+}
+
+hipError_t launch_lprec_ktable(const LprecTables& t, float2* kt, hipStream_t st) {
+    TP_LP_DISPATCH(t.NA, launch_ktable_t, t, kt, st)
 }
 
 hipError_t launch_lprec_sigma(const LprecTables& t, const float2* fhat, int pairs, float2* F, hipStream_t st) {

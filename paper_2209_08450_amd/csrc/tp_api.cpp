@@ -558,8 +558,8 @@ constexpr int kLpMinFft = 1024;
 constexpr int kLpMaxFft = 16384;
 constexpr int kLpMaxSpans = 4;       // the evaluation kernel holds every span's weights in registers
 constexpr int kLpDefaultSpans = 3;
-constexpr double kLpDefaultOs = 1.2;
-constexpr double kLpDefaultEps = 0.5;
+constexpr double kLpDefaultOs = 1.0;
+constexpr double kLpDefaultEps = 1.0;
 
 int pow2_at_least(int64_t v) {
     int r = 0;
@@ -720,6 +720,8 @@ tp_status lprec_tables(const tp_plan* plan, tp_filter_kind kind, const tp_lprec_
                                {twNA.data(), sizeof(float2) * NA, nullptr},     {twNAc.data(), sizeof(float2) * NAc, nullptr}};
     size_t total = 0;
     for (const Part& q : parts) total += align256(q.bytes);
+    const size_t kt_bytes = tp::lprec_ktable_bytes(Ns, NA);
+    total += align256(kt_bytes);
     LprecEntry le;
     hipError_t e = hipMalloc(&le.block, total);
     if (e != hipSuccess) return fail(TP_ENOMEM, "hipMalloc(log-polar tables, %zu bytes): %s", total, hipGetErrorString(e));
@@ -748,6 +750,7 @@ tp_status lprec_tables(const tp_plan* plan, tp_filter_kind kind, const tp_lprec_
     t.twNs = reinterpret_cast<const float2*>(parts[11].dst);
     t.twNA = reinterpret_cast<const float2*>(parts[12].dst);
     t.twNAc = reinterpret_cast<const float2*>(parts[13].dst);
+    t.kt = kt_bytes ? reinterpret_cast<const float2*>(b) : nullptr;
     t.na = na;
     t.n = n;
     t.N = plan->N;
@@ -772,9 +775,13 @@ tp_status lprec_tables(const tp_plan* plan, tp_filter_kind kind, const tp_lprec_
     t.phi0 = g.phi0;
     t.dpsi = g.dpsi;
     e = tp::prepare_lprec(t);
+    if (e == hipSuccess && kt_bytes) {
+        e = tp::launch_lprec_ktable(t, reinterpret_cast<float2*>(b), nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    }
     if (e != hipSuccess) {
         (void)hipFree(le.block);
-        return hip_fail(e, "log-polar kernel attributes");
+        return hip_fail(e, "log-polar kernel attributes or kernel table");
     }
     plan->lp.emplace(key, le);
     *out = t;

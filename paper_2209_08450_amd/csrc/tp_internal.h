@@ -120,6 +120,7 @@ struct LprecTables {
     const float2* twNs;     // [Ns]
     const float2* twNA;     // [NA]
     const float2* twNAc;    // [NAc]
+    const float2* kt;       // [Ns][NA] transformed kernel columns, prefilter and scale folded in (NA >= 8192)
     int na, n, N, L, log2L, spans, n_span, Ns, NA, M, NAc, log2NAc, D, rows, nmb, m_lo, j_lo, nj;
     double a0, sigma0, delta, phi0, dpsi;
 };
@@ -173,6 +174,10 @@ hipError_t launch_lprec_interp(const LprecTables& t, const float2* F, int pairs,
                                hipStream_t st);
 // Sets the dynamic-LDS limits of the instances a table set uses (no launch).
 hipError_t prepare_lprec(const LprecTables& t);
+// The transformed kernel table of the long angle transforms: its size (0 when
+// the convolution holds the columns in registers) and the launch that fills it.
+size_t lprec_ktable_bytes(int Ns, int NA);
+hipError_t launch_lprec_ktable(const LprecTables& t, float2* kt, hipStream_t st);
 
 // measurement instruments (k_peak.hip)
 hipError_t launch_peak_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);

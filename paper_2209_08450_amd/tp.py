@@ -527,7 +527,7 @@ def lprec_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, stre
     """Raw counts of a row chunk -> log-polar FBP slices [rows][N][N] (float32)
     (tp_lprec_fbp_chunk).  Same inputs as ``fbp_chunk``; the plan's angles must
     be theta_0 + a pi / n_angles.  ``spans``, ``os``, ``eps``: span count,
-    grid oversampling and origin margin (0: 3, 1.2, 0.5).  ``workspace``:
+    grid oversampling and origin margin (0: 3, 1.0, 1.0).  ``workspace``:
     default ``plan.lprec_workspace_bytes(rows, ...)`` (one pass).  ``events``:
     optional list of seven recorded-once ``torch.cuda.Event`` objects (or
     None entries) marking the stages of the first pass."""

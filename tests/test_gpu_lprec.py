@@ -46,7 +46,7 @@ def _run(tp, s, angles, n_vox=0, kind="ramp", spans=0, os=0.0, eps=0.0, workspac
     return to_host(out).astype(np.float64)
 
 
-def _oracle(s, rows, theta0, N=None, kind="ramp", spans=3, os=1.2, eps=0.5):
+def _oracle(s, rows, theta0, N=None, kind="ramp", spans=3, os=1.0, eps=1.0):
     return olp.lprec_fbp(s.proj[:, rows], s.dark[:, rows], s.flat[:, rows], theta0, s.center, N, kind=kind,
                          spans=spans, os=os, eps=eps)
 
@@ -60,7 +60,7 @@ def test_grid_query_matches_oracle_sizing(tp):
                 assert v == o[k], (args, k, v, o[k])
 
 
-@pytest.mark.parametrize("spans,os,eps", [(3, 1.2, 0.5), (2, 1.0, 0.3), (4, 2.0, 1.0)])
+@pytest.mark.parametrize("spans,os,eps", [(3, 1.0, 1.0), (3, 1.2, 0.5), (2, 1.0, 0.3), (4, 2.0, 1.0)])
 def test_lprec_matches_oracle_full_slices(tp, scan96, spans, os, eps):
     ang = _angles(120, 0.3)
     note(f"lprec 120x5x96 centre 46.7, spans {spans} os {os} eps {eps}")
@@ -125,8 +125,8 @@ def test_lprec_near_direct_sum(tp):
 
 def test_lprec_paper_scale_sampled(tp):
     """2048 angles x 2048 columns (the 2048^3 workload's geometry), 4 rows of
-    the 12-bit ellipsoid scan: sampled voxels against the direct sum within the
-    FP16-regime bar, and against the grid's expected accuracy."""
+    the 12-bit ellipsoid scan: sampled voxels against the direct sum, within
+    half the FP16-regime bar (the default grid measures about 9e-4)."""
     import torch
     n, na = 2048, 2048
     rows = [1021, 1022, 1023, 1024]
@@ -139,13 +139,13 @@ def test_lprec_paper_scale_sampled(tp):
     rng = np.random.default_rng(9)
     e_all = []
     for z in (0, 3):
-        ix = rng.integers(0, n, 96)
-        iy = rng.integers(0, n, 96)
+        ix = rng.integers(0, n, 160)
+        iy = rng.integers(0, n, 160)
         want = oracle.fourier_fbp_points(s.proj[:, z], s.dark[:, z], s.flat[:, z], s.angles, s.center, n, ix, iy)
         e = rel_l2(got[z, iy, ix], want)
-        note(f"row {rows[z]}: rel-L2 vs direct sum at 96 voxels {e:.3e}")
+        note(f"row {rows[z]}: rel-L2 vs direct sum at 160 voxels {e:.3e}")
         e_all.append(e)
-    assert max(e_all) < 3e-3
+    assert max(e_all) < 1.5e-3
 
 
 def test_lprec_host_errors(tp, scan96):
