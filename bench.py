@@ -37,7 +37,6 @@ UNIT = "Gvoxel-angle updates/s"
 FLOP_PER_UPDATE = 7
 # MI355X fp32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz.
 PEAK_FP32_TFLOPS = 157.3
-PEAK_FP32_NONPACKED_TFLOPS = 78.6
 
 
 FILTER_NAMES = {"ramp": "ramp filter", "shepp": "Shepp-Logan-windowed ramp filter",
@@ -164,11 +163,14 @@ def host_cpu() -> dict:
     return info
 
 
-def measure_peaks(log, copy_bytes: int = 2 << 30, fma_blocks: int = 4096, fma_iters: int = 8192, reps: int = 5):
+def measure_peaks(log, copy_bytes: int = 2 << 30, fma_blocks: int = 4096, fma_iters: int = 4096,
+                  lds_iters: int = 2048, reps: int = 5):
     """The device rates this library's own kernels reach: a 16-byte-load copy
-    (HBM GB/s, read + written bytes) and independent non-packed FP32 FMA
-    chains (TFLOP/s; / 128 = VALU wave-instructions per second, 64 lanes x 2
-    flop per FMA).  Best of ``reps`` HIP-event-timed launches after a warm-up."""
+    (HBM GB/s, read + written bytes), independent multiply-add chains of four
+    instruction forms (v_fma_f32 with VGPR operands, the same reading a
+    scalar register, v_fma_mix_f32, v_dot2_f32_f16; TFLOP/s and wave64
+    instructions per second) and conflict-free 16-byte LDS reads (TB/s summed
+    over the CUs).  Best of ``reps`` HIP-event-timed launches after a warm-up."""
     import torch
 
     from paper_2209_08450_amd import tp
@@ -176,6 +178,7 @@ def measure_peaks(log, copy_bytes: int = 2 << 30, fma_blocks: int = 4096, fma_it
     a = torch.ones(copy_bytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     out = torch.empty(fma_blocks * 256, dtype=torch.float32, device="cuda")
+    out_i = torch.empty(fma_blocks * 256, dtype=torch.int32, device="cuda")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def best(fn):
@@ -191,24 +194,36 @@ def measure_peaks(log, copy_bytes: int = 2 << 30, fma_blocks: int = 4096, fma_it
         return min(ts), float(sorted(ts)[len(ts) // 2])
 
     t_copy, t_copy_med = best(lambda: tp.peak_copy(a, b, stream))
-    flop = [0]
+    work = {}
+    valu = {}
+    for form in tp.VALU_FORMS:
+        def run(form=form):
+            work[form] = tp.peak_valu(form, out, fma_iters, stream)
+        t, t_med = best(run)
+        flop_per_inst = 256.0 if form == "dot2_f16" else 128.0  # per wave64 instruction
+        valu[form] = {"TFLOPs": round(work[form] / t / 1e12, 2), "TFLOPs_median": round(work[form] / t_med / 1e12, 2),
+                      "wave_instructions_per_s": work[form] / t / flop_per_inst}
 
-    def fma():
-        flop[0] = tp.peak_fma(out, fma_iters, stream)
-    t_fma, t_fma_med = best(fma)
+    def lds():
+        work["lds"] = tp.peak_lds(out_i, lds_iters, stream)
+    t_lds, _ = best(lds)
     assert torch.equal(b[:1024], a[:1024])
-    del a, b, out
+    del a, b, out, out_i
     torch.cuda.empty_cache()
     gbs = 2.0 * copy_bytes / t_copy / 1e9
-    tfs = flop[0] / t_fma / 1e12
-    log(f"measured peaks: copy {gbs:.0f} GB/s, FP32 FMA {tfs:.1f} TFLOP/s")
+    lds_tbs = work["lds"] / t_lds / 1e12
+    log(f"measured peaks: copy {gbs:.0f} GB/s, " + ", ".join(f"{k} {v['TFLOPs']:.1f} TFLOP/s" for k, v in valu.items())
+        + f", LDS reads {lds_tbs:.1f} TB/s")
     return {"hbm_copy_GBs": round(gbs, 1), "hbm_copy_GBs_median": round(2.0 * copy_bytes / t_copy_med / 1e9, 1),
             "copy_bytes": copy_bytes,
-            "fp32_fma_nonpacked_TFLOPs": round(tfs, 2),
-            "fp32_fma_nonpacked_TFLOPs_median": round(flop[0] / t_fma_med / 1e12, 2),
-            "valu_wave_instructions_per_s": tfs * 1e12 / 128.0,
-            "note": "project-written kernels (tp_peak_copy, tp_peak_fma) built like every kernel here; best of "
-                    f"{reps} event-timed launches"}
+            "fp32_fma_nonpacked_TFLOPs": valu["fma_f32"]["TFLOPs"],
+            "fp32_fma_nonpacked_TFLOPs_median": valu["fma_f32"]["TFLOPs_median"],
+            "valu_wave_instructions_per_s": valu["fma_f32"]["wave_instructions_per_s"],
+            "dot2_wave_instructions_per_s": valu["dot2_f16"]["wave_instructions_per_s"],
+            "valu_forms": valu,
+            "lds_read_TBs": round(lds_tbs, 2),
+            "note": "project-written kernels (tp_peak_copy, tp_peak_valu, tp_peak_lds) built like every kernel "
+                    f"here; best of {reps} event-timed launches"}
 
 
 def load_valu_counters(storage: str, chunk: int, n: int, angles: int):
@@ -495,10 +510,22 @@ def main():
     valu = load_valu_counters(head, chunk, n, na)
     if valu is not None:
         insts = float(valu["valu_insts_per_launch"])
+        t_launch = r["bp_launch_ms"] * 1e-3
+        # FP16 rows: one v_dot2 per slice and voxel-angle (per wave: one per 64
+        # updates), issued at the dot2 rate; every other VALU instruction at the
+        # FP32 FMA rate.  LDS: the bytes the taps read per update (an FP16 pair,
+        # or two FP32 values).
+        dot2 = bp_updates / 64.0 if head == "f16" else 0.0
+        t_valu = dot2 / peaks["dot2_wave_instructions_per_s"] + (insts - dot2) / peaks["valu_wave_instructions_per_s"]
+        lds_bytes = bp_updates * (4.0 if head == "f16" else 8.0)
         valu = {"valu_insts_per_launch": insts, "valu_insts_per_update": round(insts * 64 / bp_updates, 3),
-                "valu_issue_frac_of_measured": round(insts / (r["bp_launch_ms"] * 1e-3)
-                                                     / peaks["valu_wave_instructions_per_s"], 4),
-                "source": "profiles/valu_backproject.json (rocprofv3 SQ_INSTS_VALU on this kernel source)"}
+                "dot2_insts_per_launch": dot2,
+                "valu_busy_frac": round(t_valu / t_launch, 4),
+                "lds_tap_bytes_per_launch": lds_bytes,
+                "lds_busy_frac": round(lds_bytes / t_launch / (peaks["lds_read_TBs"] * 1e12), 4),
+                "source": "profiles/valu_backproject.json (rocprofv3 SQ_INSTS_VALU on this kernel source); "
+                          "busy fractions: issue time at the measured dot2 and FP32 FMA rates, tap bytes at the "
+                          "measured LDS read rate, over the launch time"}
     out = {
         "metric": METRIC,
         "value": round(r["gups"], 3),
@@ -524,15 +551,15 @@ def main():
                               for st in storages},
         "roofline": {"bound": "alu", "kernel": "k_backproject", "achieved": round(achieved, 2),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "frac_of_nonpacked_peak": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
                      "frac_of_measured_fma_rate": round(achieved / peaks["fp32_fma_nonpacked_TFLOPs"], 4),
                      "traffic": traffic,
                      "launch_ms": round(r["bp_launch_ms"], 3),
                      "flop_per_launch": FLOP_PER_UPDATE * bp_updates,
                      "executed": valu,
                      "note": "achieved = 7 algorithmic flop per voxel-angle update / launch time; the kernel "
-                             "shares the coordinate, fraction and 1 - w of a voxel and angle over 16 slices, so "
-                             "it issues fewer VALU instructions than 7 flop per update (see executed)"},
+                             "shares the coordinate, fraction and weights of a voxel and angle over 16 slices and "
+                             "(FP16 rows) adds both taps of a slice with one v_dot2, so it issues fewer VALU "
+                             "instructions than 7 flop per update (see executed)"},
         "measured_peaks": peaks,
         # the fused normalise + filter kernel: HBM-class work (uint16 raw sample
         # in, one filtered sample out in the storage type, per sample of the

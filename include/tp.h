@@ -508,15 +508,28 @@ const char* tp_io_last_error(void);
  * tp_peak_copy: copies `bytes` (a positive multiple of 16; both buffers dev,
  *   16-byte aligned, not overlapping) with 16-byte loads and stores on
  *   `stream`; time it with events to get the copy rate (2 x bytes moved).
- * tp_peak_fma: `blocks` work-groups of 256 threads each run 8 independent
- *   FP32 FMA chains for 2 x iters steps (non-packed v_fma_f32, the build's
- *   instruction selection) and store one float per thread to out (dev,
- *   blocks x 256 floats); *flop receives the flop count (2 per FMA).
- *   blocks in [1, 2^20], iters in [1, 2^24].
+ * tp_peak_valu: `blocks` work-groups of 256 threads each run 16 independent
+ *   multiply-add chains of one instruction form for `iters` steps and store
+ *   one float per thread to out (dev, blocks x 256 floats); *flop receives
+ *   the flop count (2 per FMA, 4 per dot2).  Forms: TP_VALU_FMA_F32
+ *   (v_fma_f32, VGPR operands), TP_VALU_FMA_F32_SGPR (one operand from a
+ *   scalar register), TP_VALU_FMA_MIX_F16 (v_fma_mix_f32, an FP16 operand),
+ *   TP_VALU_DOT2_F16 (v_dot2_f32_f16: two FP16 products into an FP32 sum).
+ * tp_peak_fma: tp_peak_valu with TP_VALU_FMA_F32.
+ * tp_peak_lds: `blocks` work-groups of 256 threads each issue 16 x iters
+ *   conflict-free 16-byte LDS reads and store one word per thread to out
+ *   (dev, blocks x 256 words); *bytes receives the bytes read.
+ *   blocks in [1, 2^20], iters in [1, 2^24] for all of them.
  * Errors: TP_EINVAL for bad arguments (nothing enqueued), TP_EHIP.
  * ------------------------------------------------------------------------ */
+#define TP_VALU_FMA_F32 0
+#define TP_VALU_FMA_F32_SGPR 1
+#define TP_VALU_FMA_MIX_F16 2
+#define TP_VALU_DOT2_F16 3
 tp_status tp_peak_copy(const void* src, void* dst, int64_t bytes, void* stream);
+tp_status tp_peak_valu(int32_t form, float* out, int32_t blocks, int32_t iters, int64_t* flop, void* stream);
 tp_status tp_peak_fma(float* out, int32_t blocks, int32_t iters, int64_t* flop, void* stream);
+tp_status tp_peak_lds(uint32_t* out, int32_t blocks, int32_t iters, int64_t* bytes, void* stream);
 
 /* Thread-local description of the last non-OK status returned on this thread. */
 const char* tp_last_error(void);

@@ -55,6 +55,7 @@ from .fbp import (  # noqa: F401
     pad_rows,
     filter_rows,
     filter_rows_direct,
+    round_binary16,
     round_f16,
     round_bf16,
     backproject,

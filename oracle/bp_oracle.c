@@ -15,6 +15,11 @@
  *     j0 = floor(s),  w = s - j0
  *     Q(j) = q[z][a][j] for 0 <= j < n_det, else 0
  *
+ * In the 16-bit mode (paper, Section 2.1: 16-bit arithmetic, higher
+ * precision where accuracy needs it) the two weights are held as IEEE
+ * binary16 numbers: (1-w) and w are each rounded to the nearest binary16
+ * value (ties to even), products and sums stay exact/FP64 here.  Flag w16.
+ *
  * The forward projector is the transpose of that map with scale 1: every
  * voxel deposits (1-w) f into bin j0 and w f into bin j0+1 of each angle.
  * Both are written in double precision with libm sin/cos, in the plainest
@@ -44,10 +49,40 @@ void oracle_set_num_threads(int n) {
 #endif
 }
 
+
+/* Nearest IEEE binary16 value of a finite x with |x| < 65504, ties to even:
+ * binary16 keeps 11 significant bits, and below 2^-14 (subnormals) a fixed
+ * spacing of 2^-24.  x / ulp is exact (ulp is a power of two) and nearbyint
+ * rounds ties to even in the default rounding mode. */
+static double round_binary16(double x)
+{
+    if (x == 0.0) return x;
+    int e;
+    (void)frexp(fabs(x), &e);          /* |x| = m 2^e, m in [0.5, 1): leading bit 2^(e-1) */
+    int lead = e - 1;
+    if (lead < -14) lead = -14;
+    const double ulp = ldexp(1.0, lead - 10);
+    return nearbyint(x / ulp) * ulp;
+}
+
+double oracle_round_binary16(double x) { return round_binary16(x); }
+
+/* The two interpolation weights of one tap pair. */
+static void tap_weights(double w, int w16, double *wa, double *wb)
+{
+    if (w16) {
+        *wa = round_binary16(1.0 - w);
+        *wb = round_binary16(w);
+    } else {
+        *wa = 1.0 - w;
+        *wb = w;
+    }
+}
+
 /* q: [nz][na][n] filtered rows; f: [nz][N][N] output (overwritten). */
 void oracle_backproject(const double *q, int64_t nz, int64_t na, int64_t n,
                         const double *angles, double center, int64_t N,
-                        double scale, double *f)
+                        double scale, int w16, double *f)
 {
     const int64_t half = N / 2;
     double *ct = (double *)malloc((size_t)na * sizeof(double));
@@ -68,7 +103,9 @@ void oracle_backproject(const double *q, int64_t nz, int64_t na, int64_t n,
                     const double *row = q + (z * na + a) * n;
                     const double q0 = (j0 >= 0 && j0 < n) ? row[j0] : 0.0;
                     const double q1 = (j0 + 1 >= 0 && j0 + 1 < n) ? row[j0 + 1] : 0.0;
-                    acc += (1.0 - w) * q0 + w * q1;
+                    double wa, wb;
+                    tap_weights(w, w16, &wa, &wb);
+                    acc += wa * q0 + wb * q1;
                 }
                 f[(z * N + iy) * N + ix] = scale * acc;
             }
@@ -82,7 +119,7 @@ void oracle_backproject(const double *q, int64_t nz, int64_t na, int64_t n,
  * checks of large volumes).  q: [na][n]; out[k] is the value at (ix[k], iy[k]). */
 void oracle_backproject_points(const double *q, int64_t na, int64_t n,
                                const double *angles, double center, int64_t N,
-                               double scale, const int64_t *ix, const int64_t *iy,
+                               double scale, int w16, const int64_t *ix, const int64_t *iy,
                                int64_t npts, double *out)
 {
     const int64_t half = N / 2;
@@ -102,7 +139,9 @@ void oracle_backproject_points(const double *q, int64_t na, int64_t n,
             const double *row = q + a * n;
             const double q0 = (j0 >= 0 && j0 < n) ? row[j0] : 0.0;
             const double q1 = (j0 + 1 >= 0 && j0 + 1 < n) ? row[j0 + 1] : 0.0;
-            acc += (1.0 - w) * q0 + w * q1;
+            double wa, wb;
+            tap_weights(w, w16, &wa, &wb);
+            acc += wa * q0 + wb * q1;
         }
         out[k] = scale * acc;
     }

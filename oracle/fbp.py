@@ -36,9 +36,10 @@ def _load():
         i64 = ctypes.c_int64
         pd = ctypes.POINTER(ctypes.c_double)
         pi = ctypes.POINTER(ctypes.c_int64)
-        lib.oracle_backproject.argtypes = [pd, i64, i64, i64, pd, d, i64, d, pd]
+        i32 = ctypes.c_int
+        lib.oracle_backproject.argtypes = [pd, i64, i64, i64, pd, d, i64, d, i32, pd]
         lib.oracle_backproject.restype = None
-        lib.oracle_backproject_points.argtypes = [pd, i64, i64, pd, d, i64, d, pi, pi, i64, pd]
+        lib.oracle_backproject_points.argtypes = [pd, i64, i64, pd, d, i64, d, i32, pi, pi, i64, pd]
         lib.oracle_backproject_points.restype = None
         lib.oracle_radon.argtypes = [pd, i64, i64, pd, d, i64, i64, pd]
         lib.oracle_radon.restype = None
@@ -47,6 +48,8 @@ def _load():
         lib.oracle_lamino_backproject_points.argtypes = [pd, i64, i64, i64, pd, d, d, d, i64, i64, d, pi, pi, pi,
                                                           i64, pd]
         lib.oracle_lamino_backproject_points.restype = None
+        lib.oracle_round_binary16.argtypes = [d]
+        lib.oracle_round_binary16.restype = d
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -281,12 +284,29 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Step 3: backprojection with linear interpolation (LineRec) and its transpose.
 # --------------------------------------------------------------------------
-def backproject(q: np.ndarray, angles, center: float, N: int, scale: float | None = None) -> np.ndarray:
+def _w16(weights) -> int:
+    if weights in (None, "f64"):
+        return 0
+    if weights == "f16":
+        return 1
+    raise ValueError(weights)
+
+
+def round_binary16(x: float) -> float:
+    """Nearest IEEE binary16 value of x (ties to even), as the C oracle rounds
+    the interpolation weights of the 16-bit mode."""
+    return float(_load().oracle_round_binary16(float(x)))
+
+
+def backproject(q: np.ndarray, angles, center: float, N: int, scale: float | None = None,
+                weights: str | None = None) -> np.ndarray:
     """f[z][iy][ix] = scale * sum_a ((1-w) Q(j0) + w Q(j0+1)), FP64 (C loop).
 
     q: [nz][n_angles][n]; voxel centres x = ix - N//2, y = iy - N//2 (ix fast);
     s = x cos + y sin + center; taps off the detector read zero.
     scale defaults to pi / n_angles (uniform 180-degree scan).
+    ``weights='f16'``: the 16-bit mode (Section 2.1) -- (1-w) and w each
+    rounded to the nearest binary16 value before the FP64 products.
     """
     q = np.ascontiguousarray(q, dtype=np.float64)
     if q.ndim == 2:
@@ -297,13 +317,14 @@ def backproject(q: np.ndarray, angles, center: float, N: int, scale: float | Non
     if scale is None:
         scale = math.pi / na
     f = np.empty((nz, N, N), dtype=np.float64)
-    _load().oracle_backproject(_pd(q), nz, na, n, _pd(ang), float(center), N, float(scale), _pd(f))
+    _load().oracle_backproject(_pd(q), nz, na, n, _pd(ang), float(center), N, float(scale), _w16(weights), _pd(f))
     return f
 
 
 def backproject_points(q: np.ndarray, angles, center: float, N: int, ix, iy,
-                       scale: float | None = None) -> np.ndarray:
-    """Backprojection of one slice q: [n_angles][n] at voxels (ix[k], iy[k])."""
+                       scale: float | None = None, weights: str | None = None) -> np.ndarray:
+    """Backprojection of one slice q: [n_angles][n] at voxels (ix[k], iy[k]);
+    ``weights`` as for ``backproject``."""
     q = np.ascontiguousarray(q, dtype=np.float64)
     na, n = q.shape
     ang = np.ascontiguousarray(angles, dtype=np.float64)
@@ -312,7 +333,7 @@ def backproject_points(q: np.ndarray, angles, center: float, N: int, ix, iy,
     if scale is None:
         scale = math.pi / na
     out = np.empty(ix.shape[0], dtype=np.float64)
-    _load().oracle_backproject_points(_pd(q), na, n, _pd(ang), float(center), N, float(scale),
+    _load().oracle_backproject_points(_pd(q), na, n, _pd(ang), float(center), N, float(scale), _w16(weights),
                                       _pi(ix), _pi(iy), ix.shape[0], _pd(out))
     return out
 
@@ -340,6 +361,11 @@ def radon(f: np.ndarray, angles, center: float, n: int) -> np.ndarray:
 # --------------------------------------------------------------------------
 # The composition.
 # --------------------------------------------------------------------------
+def _storage_weights(storage):
+    """Interpolation weights of each storage mode: binary16 in the 16-bit mode."""
+    return "f16" if storage == "f16" else None
+
+
 def _round_storage(x, storage):
     if storage in (None, "f32"):
         return x
@@ -356,15 +382,16 @@ def fbp(proj, dark, flat, angles, center: float, N: int | None = None, storage: 
 
     ``storage`` in {None/'f32', 'f16', 'bf16'} rounds the filtered rows to that
     type before backprojection (emulates reduced-precision storage with
-    arithmetic kept in higher precision).  'f32' applies no rounding: the FP32
-    GPU path is compared against the unrounded FP64 result.  ``kind`` picks the
-    filter window (``FILTERS``).
+    arithmetic kept in higher precision); 'f16' is the 16-bit mode and also
+    holds the interpolation weights in binary16 (``backproject``).  'f32'
+    applies no rounding: the FP32 GPU path is compared against the unrounded
+    FP64 result.  ``kind`` picks the filter window (``FILTERS``).
     """
     p = normalize(proj, dark, flat)
     n = p.shape[-1]
     q = filter_rows(p, kind=kind)
     q = _round_storage(q, storage)
-    return backproject(q, angles, center, n if N is None else N)
+    return backproject(q, angles, center, n if N is None else N, weights=_storage_weights(storage))
 
 
 def fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, storage=None, kind="ramp"):
@@ -376,7 +403,7 @@ def fbp_points(proj_slice, dark_slice, flat_slice, angles, center, N, ix, iy, st
     p = normalize(np.asarray(proj_slice)[:, None, :], np.asarray(dark_slice)[:, None, :],
                   np.asarray(flat_slice)[:, None, :])[0]
     q = _round_storage(filter_rows(p, kind=kind), storage)
-    return backproject_points(q, angles, center, N, ix, iy)
+    return backproject_points(q, angles, center, N, ix, iy, weights=_storage_weights(storage))
 
 
 # --------------------------------------------------------------------------

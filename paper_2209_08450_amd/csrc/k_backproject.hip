@@ -24,9 +24,18 @@
 // FP32 offset); fma is monotone in each argument, so every voxel's floor
 // lies in [0, 45) of the 48-bin window and both taps are staged.  The inner
 // loop per voxel and angle: offset (1 FMA), fraction, floor, address, 1 - w,
-// reads of the two bins' K-slice groups (16-byte LDS reads), then two
-// FMAs per slice (v_fma_mix_f32 reads FP16 operands directly).  Every slice
-// sums its angles in order, so results do not depend on K or A.
+// reads of the two bins' K-slice groups (16-byte LDS reads), then two FP32
+// FMAs per slice.  Every slice sums its angles in order, so results do not
+// depend on K or A.
+//
+// FP16 rows (the paper's 16-bit mode, Section 2.1) take a kernel of their own,
+// k_backproject_h2: LDS holds for each (angle, bin j) the K slices' pairs
+// (Q[j], Q[j+1]) as packed halves, staged with one 4-byte load per slice, and
+// the weights (1 - w, w) are rounded to FP16 (nearest), so one v_dot2 per slice
+// and voxel adds (1 - w) Q[j] + w Q[j+1] to the FP32 sum: half the VALU issue
+// of two mixed-precision FMAs, the same LDS bytes.  The weights' rounding
+// (at most 2^-12 of a bin's value) is the FP16 mode's only change to the
+// arithmetic; every product is exact and every sum FP32.
 #include <type_traits>
 
 #include "tp_internal.h"
@@ -50,7 +59,6 @@ __device__ __forceinline__ U stage_load(const unsigned char* p) {
 }
 
 __device__ __forceinline__ float lds_val(const float* v, int i) { return v[i]; }
-__device__ __forceinline__ float lds_val(const __half* v, int i) { return __half2float(v[i]); }
 
 // Copy BYTES between LDS and registers in chunks of CHUNK bytes (the
 // alignment both addresses are known to have, at most 16).
@@ -223,9 +231,130 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
     }
 }
 
+
+// FP16 rows: pairs (Q[j], Q[j+1]) per slice in LDS, FP16 weights, v_dot2.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+template <int K, int A>
+__global__ void __launch_bounds__(kBpThreads)
+k_backproject_h2(GeoTables g, const __half* __restrict__ filt, int n_rows, float scale, float* __restrict__ vol,
+                 int accumulate) {
+    constexpr int BIN = K * 4;            // bytes of one (angle, bin) group: K packed pairs
+    constexpr int P = bin_pitch(BIN);     // LDS bytes between bins
+    extern __shared__ __align__(16) unsigned char smem[];
+    float4* sGeo = reinterpret_cast<float4*>(smem + A * kWin * P);  // [A] {bf, cos, sin, byte base}
+
+    const int na = g.na, n = g.n, nb = g.nb;
+    int bx, by;
+    tile_of(blockIdx.x, nb, bx, by);
+    const int z0 = blockIdx.y * K;
+    const int kz = min(K, n_rows - z0);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const float dy = static_cast<float>((lane >> 3) + 8 * wv);
+    const float dx0 = static_cast<float>(lane & 7);
+    const __half* rows0 = filt + static_cast<int64_t>(z0) * na * n;
+    const int64_t slice_bytes = static_cast<int64_t>(na) * n * 2;
+
+    float acc[4][K];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[i][k] = 0.0f;
+
+    for (int a0 = 0; a0 < na; a0 += A) {
+        const int nA = __builtin_amdgcn_readfirstlane(min(A, na - a0));
+        // stage: wave wv takes angles wv, wv+4, ...; lane b holds the pairs of bin ws + b
+        for (int a = wv; a < nA; a += kBpThreads / 64) {
+            const int ag = a0 + a;
+            const float cs = g.cs[ag], sn = g.sn[ag];
+            const int bi = g.xi[bx * na + ag] + g.yi[by * na + ag];
+            const float bf = g.xf[bx * na + ag] + g.yf[by * na + ag];
+            const float smin = tile_offset(cs >= 0.0f ? 0.0f : 31.0f, sn >= 0.0f ? 0.0f : 31.0f, cs, sn, bf);
+            const int fmin = coord_floor(smin);
+            if (lane == 0) sGeo[a] = make_float4(bf, cs, sn, __int_as_float((a * kWin - fmin) * P));
+            if (lane < kWin) {
+                const int ws = bi + fmin;  // wave-uniform
+                const int j = ws + lane;
+                const unsigned char* rowb = reinterpret_cast<const unsigned char*>(rows0) +
+                                            static_cast<int64_t>(ag) * n * 2;
+                uint32_t q[K];
+                // Slice k's row base is rowb + kk * slice_bytes with kk = min(k, kz - 1)
+                // made opaque (scalar, not K hoisted 64-bit constants); slices past the
+                // last row re-read it and their sums are never stored.
+                if (ws >= 0 && ws + kWin <= n - 1) {
+                    // window inside the detector: bins j and j + 1 in one 4-byte load
+                    // (2-byte aligned; the hardware serves unaligned global loads)
+                    const uint32_t voff = static_cast<uint32_t>(j) * 2u;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        int kk = min(k, kz - 1);
+                        asm volatile("" : "+s"(kk));
+                        __builtin_memcpy(&q[k], rowb + kk * slice_bytes + voff, 4);
+                    }
+                } else {
+                    // window at an edge: taps off the detector read zero
+                    const uint32_t v0 = static_cast<uint32_t>(min(max(j, 0), n - 1)) * 2u;
+                    const uint32_t v1 = static_cast<uint32_t>(min(max(j + 1, 0), n - 1)) * 2u;
+                    const uint32_t m0 = (j >= 0 && j < n) ? 0xffffu : 0u;
+                    const uint32_t m1 = (j + 1 >= 0 && j + 1 < n) ? 0xffffu : 0u;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        int kk = min(k, kz - 1);
+                        asm volatile("" : "+s"(kk));
+                        const unsigned char* rb = rowb + kk * slice_bytes;
+                        const uint32_t lo = *reinterpret_cast<const uint16_t*>(rb + v0) & m0;
+                        const uint32_t hi = *reinterpret_cast<const uint16_t*>(rb + v1) & m1;
+                        q[k] = lo | (hi << 16);
+                    }
+                }
+                copy_group<BIN, (BIN < 16 ? BIN : 16)>(smem + (a * kWin + lane) * P, q);
+            }
+        }
+        __syncthreads();
+        for (int a = 0; a < nA; ++a) {
+            const float4 ge = sGeo[a];
+            const int base = __float_as_int(ge.w);
+            uint32_t r[4][K];  // pairs (Q[j0], Q[j0+1]) of K slices per voxel
+            half2_t wt[4];     // (1 - w, w) rounded to FP16
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float s = tile_offset(dx0 + 8.0f * i, dy, ge.y, ge.z, ge.x);
+                const float w = coord_frac(s);
+                wt[i] = half2_t{static_cast<_Float16>(1.0f - w), static_cast<_Float16>(w)};
+                // |floor(s)| < 2^23 and P < 2^8: the 24-bit multiply is exact
+                const unsigned char* tap = smem + base + __mul24(coord_floor(s), P);
+                copy_group<BIN, (BIN < 16 ? BIN : 16)>(r[i], tap);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    acc[i][k] = __builtin_amdgcn_fdot2(__builtin_bit_cast(half2_t, r[i][k]), wt[i], acc[i][k], false);
+        }
+        __syncthreads();
+    }
+
+    const int N = g.N;
+    const int y = by * kGeoTile + (lane >> 3) + 8 * wv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int x = bx * kGeoTile + (lane & 7) + 8 * i;
+        if (x >= N || y >= N) continue;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k >= kz) continue;
+            const int64_t idx = (static_cast<int64_t>(z0 + k) * N + y) * N + x;
+            const float v = scale * acc[i][k];
+            vol[idx] = accumulate ? vol[idx] + v : v;
+        }
+    }
+}
+
 size_t bp_lds_bytes(tp_dtype dt, int K, int A) {
-    const int elem = (dt == TP_F16) ? 2 : 4;  // bf16 is widened to FP32 in LDS
-    return static_cast<size_t>(bin_pitch(elem * K)) * A * kWin + static_cast<size_t>(A) * sizeof(float4);
+    (void)dt;  // 4 bytes per slice and bin: FP32, bf16 widened to FP32, or an FP16 pair
+    return static_cast<size_t>(bin_pitch(4 * K)) * A * kWin + static_cast<size_t>(A) * sizeof(float4);
 }
 
 // A null `vol` only sets the instance's dynamic-LDS limit (tp_prepare), so
@@ -233,15 +362,25 @@ size_t bp_lds_bytes(tp_dtype dt, int K, int A) {
 template <typename T, int K, int A>
 hipError_t launch_bp_t(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
                        int accumulate, size_t lds, hipStream_t st) {
+    const void* fn;
+    if constexpr (std::is_same<T, __half>::value) {
+        fn = reinterpret_cast<const void*>(k_backproject_h2<K, A>);
+    } else {
+        fn = reinterpret_cast<const void*>(k_backproject<T, K, A>);
+    }
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_backproject<T, K, A>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
     if (vol == nullptr) return hipSuccess;
     const dim3 grid(static_cast<unsigned>(g.nb * g.nb), static_cast<unsigned>((n_rows + K - 1) / K));
-    hipLaunchKernelGGL((k_backproject<T, K, A>), grid, dim3(kBpThreads), lds, st, g, static_cast<const T*>(filt),
-                       n_rows, scale, vol, accumulate);
+    if constexpr (std::is_same<T, __half>::value) {
+        hipLaunchKernelGGL((k_backproject_h2<K, A>), grid, dim3(kBpThreads), lds, st, g,
+                           static_cast<const __half*>(filt), n_rows, scale, vol, accumulate);
+    } else {
+        hipLaunchKernelGGL((k_backproject<T, K, A>), grid, dim3(kBpThreads), lds, st, g, static_cast<const T*>(filt),
+                           n_rows, scale, vol, accumulate);
+    }
     return hipGetLastError();
 }
 

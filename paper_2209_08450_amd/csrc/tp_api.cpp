@@ -44,7 +44,7 @@ struct tp_plan {
     tp::FilterTables filt{};
     // backprojection tuning per storage type (F32, F16, BF16)
     int bp_k[3] = {16, 16, 16};
-    int bp_a[3] = {8, 16, 8};
+    int bp_a[3] = {8, 8, 8};
     // Fourier-domain backprojection tables per (filter window, truncation radius)
     mutable std::mutex fr_mu;
     mutable std::map<std::pair<int, int>, FourierEntry> fr;
@@ -1522,13 +1522,28 @@ tp_status tp_peak_copy(const void* src, void* dst, int64_t bytes, void* stream) 
     return TP_OK;
 }
 
-tp_status tp_peak_fma(float* out, int32_t blocks, int32_t iters, int64_t* flop, void* stream) {
+tp_status tp_peak_valu(int32_t form, float* out, int32_t blocks, int32_t iters, int64_t* flop, void* stream) {
     if (!out || !flop) return fail(TP_EINVAL, "null argument");
+    if (form < TP_VALU_FMA_F32 || form > TP_VALU_DOT2_F16) return fail(TP_EINVAL, "unknown VALU form %d", form);
     if (blocks <= 0 || blocks > (1 << 20) || iters <= 0 || iters > (1 << 24))
         return fail(TP_EINVAL, "blocks=%d iters=%d out of range", blocks, iters);
-    *flop = tp::peak_fma_flop(blocks, iters);
-    const hipError_t e = tp::launch_peak_fma(out, blocks, iters, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(e, "FMA launch");
+    *flop = tp::peak_valu_flop(form, blocks, iters);
+    const hipError_t e = tp::launch_peak_valu(form, out, blocks, iters, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "VALU launch");
+    return TP_OK;
+}
+
+tp_status tp_peak_fma(float* out, int32_t blocks, int32_t iters, int64_t* flop, void* stream) {
+    return tp_peak_valu(TP_VALU_FMA_F32, out, blocks, iters, flop, stream);
+}
+
+tp_status tp_peak_lds(uint32_t* out, int32_t blocks, int32_t iters, int64_t* bytes, void* stream) {
+    if (!out || !bytes) return fail(TP_EINVAL, "null argument");
+    if (blocks <= 0 || blocks > (1 << 20) || iters <= 0 || iters > (1 << 24))
+        return fail(TP_EINVAL, "blocks=%d iters=%d out of range", blocks, iters);
+    *bytes = tp::peak_lds_bytes(blocks, iters);
+    const hipError_t e = tp::launch_peak_lds(out, blocks, iters, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "LDS launch");
     return TP_OK;
 }
 

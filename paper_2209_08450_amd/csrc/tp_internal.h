@@ -181,8 +181,10 @@ hipError_t launch_lprec_ktable(const LprecTables& t, float2* kt, hipStream_t st)
 
 // measurement instruments (k_peak.hip)
 hipError_t launch_peak_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
-int64_t peak_fma_flop(int blocks, int iters);
-hipError_t launch_peak_fma(float* out, int blocks, int iters, hipStream_t st);
+int64_t peak_valu_flop(int form, int blocks, int iters);
+hipError_t launch_peak_valu(int form, float* out, int blocks, int iters, hipStream_t st);
+int64_t peak_lds_bytes(int blocks, int iters);
+hipError_t launch_peak_lds(uint32_t* out, int blocks, int iters, hipStream_t st);
 
 // ---- backprojection tilings read from the autotuner's JSON table (tp_tune.cpp) ----
 // Replaces the process-wide table with the file's entries (path null: clears

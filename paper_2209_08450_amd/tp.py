@@ -110,6 +110,8 @@ _io_create = _proto("tp_io_create", _c_i32, ctypes.c_char_p, _c_i64)
 _io_last_error = _proto("tp_io_last_error", ctypes.c_char_p)
 _peak_copy = _proto("tp_peak_copy", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp)
 _peak_fma = _proto("tp_peak_fma", _c_i32, _c_vp, _c_i32, _c_i32, ctypes.POINTER(_c_i64), _c_vp)
+_peak_valu = _proto("tp_peak_valu", _c_i32, _c_i32, _c_vp, _c_i32, _c_i32, ctypes.POINTER(_c_i64), _c_vp)
+_peak_lds = _proto("tp_peak_lds", _c_i32, _c_vp, _c_i32, _c_i32, ctypes.POINTER(_c_i64), _c_vp)
 _last_error = _proto("tp_last_error", ctypes.c_char_p)
 _version = _proto("tp_version", ctypes.c_char_p)
 
@@ -653,3 +655,24 @@ def peak_fma(out, iters: int, stream=None) -> int:
     flop = _c_i64()
     _check(_peak_fma(_dev(out, "out"), int(blocks), int(iters), ctypes.byref(flop), _stream_ptr(stream)))
     return int(flop.value)
+
+
+VALU_FORMS = {"fma_f32": 0, "fma_f32_sgpr": 1, "fma_mix_f16": 2, "dot2_f16": 3}
+
+
+def peak_valu(form: str, out, iters: int, stream=None) -> int:
+    """Enqueue the multiply-add chain kernel of one instruction form (``VALU_FORMS``) over
+    out.numel() // 256 work-groups (float32 out); returns its flop count."""
+    blocks = out.numel() // 256
+    flop = _c_i64()
+    _check(_peak_valu(VALU_FORMS[form], _dev(out, "out"), int(blocks), int(iters), ctypes.byref(flop),
+                      _stream_ptr(stream)))
+    return int(flop.value)
+
+
+def peak_lds(out, iters: int, stream=None) -> int:
+    """Enqueue the LDS read kernel (32-bit out, out.numel() // 256 work-groups); returns the bytes read."""
+    blocks = out.numel() // 256
+    nbytes = _c_i64()
+    _check(_peak_lds(_dev(out, "out"), int(blocks), int(iters), ctypes.byref(nbytes), _stream_ptr(stream)))
+    return int(nbytes.value)

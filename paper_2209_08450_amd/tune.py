@@ -26,8 +26,10 @@ def bin_pitch(group_bytes: int) -> int:
 
 
 def legal(storage: str, k: int, a: int) -> bool:
-    elem = 2 if storage == "f16" else 4
-    return bin_pitch(k * elem) * a * WINDOW + a * 16 <= LDS_BYTES
+    # 4 bytes per slice and staged bin for every storage type: FP32, bf16
+    # widened to FP32, or an FP16 pair (Q[j], Q[j+1])
+    del storage
+    return bin_pitch(k * 4) * a * WINDOW + a * 16 <= LDS_BYTES
 
 
 def candidates(storage: str, slices=SLICES, angles=ANGLES):

@@ -28,20 +28,20 @@ def tp():
 
 def test_prepare_then_capture_without_an_eager_run(tp):
     # A tiling whose staged block needs more than 64 KiB of LDS (F16, 16
-    # slices x 64 angles: 98 KiB) and a windowed filter: after tp_prepare the
+    # slices x 32 angles: 120.5 KiB) and a windowed filter: after tp_prepare the
     # very first call may be a graph capture.  Replays, with eager work and
     # synchronisation between them, equal an eager call bitwise and the oracle
     # within the FP16 bounds.
     import torch
     s = synth.ellipsoid_scan_np(seed=12, n_angles=64, n_rows=20, n_det=96, center=47.6, n_dark=2, n_flat=2)
     plan = tp.Plan(s.angles, 96, s.center)
-    plan.set_tuning("f16", 16, 64)
+    plan.set_tuning("f16", 16, 32)
     plan.prepare("parzen", "f16")
     P, D, F = to_dev(s.proj), to_dev(s.dark), to_dev(s.flat)
     out = torch.empty((20, 96, 96), device="cuda")
     ws = torch.empty(plan.fbp_workspace_bytes(20, "f16"), dtype=torch.uint8, device="cuda")
     st = torch.cuda.Stream()
-    note("capture fbp parzen f16 (K=16, A=64) without an eager run")
+    note("capture fbp parzen f16 (K=16, A=32) without an eager run")
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=st, capture_error_mode="thread_local"):
         tp.fbp_chunk(plan, P, D, F, "f16", out=out, workspace=ws, kind="parzen")
@@ -76,7 +76,7 @@ def test_tuning_table_sets_new_plans(tp, tmp_path):
         assert plan.get_tuning("f32") == (2, 64)
         assert plan.get_tuning("bf16") == (16, 8)  # no entry: the default
         other = tp.Plan(ang, 64, 31.5, 48)  # another shape: defaults
-        assert other.get_tuning("f16") == (16, 16)
+        assert other.get_tuning("f16") == (16, 8)
         q = to_dev(np.random.default_rng(2).standard_normal((5, 40, 64)).astype(np.float32)).half()
         got = tp.backproject(plan, q)
         plan.set_tuning("f16", 16, 16)

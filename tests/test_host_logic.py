@@ -29,8 +29,9 @@ def test_tuner_legal_candidates():
     # groups of 64 bytes or more get one 16-byte bank group of padding
     assert tune.bin_pitch(16) == 16 and tune.bin_pitch(32) == 32 and tune.bin_pitch(64) == 80
     assert all(tune.legal("f32", k, a) for k, a in c32)
-    assert len(c16) == 20 and (16, 64) in c16 and (16, 64) not in c32
-    assert (16, 32) in c32  # f32: 80 B x 48 x 32 + 512 = 120.5 KiB
+    # f16 stages pairs (Q[j], Q[j+1]): 4 bytes per slice and bin, as f32
+    assert c16 == c32 and (16, 64) not in c16
+    assert (16, 32) in c32  # 80 B x 48 x 32 + 512 = 120.5 KiB
 
 
 class FakePlan:
