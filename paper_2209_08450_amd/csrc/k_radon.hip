@@ -98,6 +98,12 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
     const int e = e0 + wv;
     // padding entries (-1) and entries past the class are inactive waves
     const bool active = e < e_end && g.order[e] >= 0;
+    // which of the work-group's W angle slots hold an angle, read once (the
+    // per-block strip bounds would otherwise wait on these loads every block)
+    unsigned live = 0;
+    for (int w = 0; w < W; ++w)
+        if (e0 + w < e_end && g.order[e0 + w] >= 0) live |= 1u << w;
+    live = __builtin_amdgcn_readfirstlane(live);
     const int a = active ? g.order[e] : g.order[e0];
     const int j = jb + lane;
     const int z0 = blockIdx.y * K;
@@ -137,7 +143,7 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
         __syncthreads();
         int xmin = 1 << 30, xmax = -(1 << 30);
         for (int w = 0; w < W; ++w) {
-            if (e0 + w >= e_end || g.order[e0 + w] < 0) continue;
+            if (!((live >> w) & 1u)) continue;
             for (int c = 0; c < 4; ++c) {
                 xmin = min(xmin, s_lo[w][c]);
                 xmax = max(xmax, s_lo[w][c] + kCand - 1);
