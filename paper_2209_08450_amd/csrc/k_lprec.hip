@@ -282,6 +282,11 @@ k_lp_ktable(LprecTables t, float2* __restrict__ kt) {
     }
 }
 
+// One (span, eta, pair) per work-group (a 16-wave work-group fills a CU, so
+// nothing is gained by looping over pairs inside it).  On each XCD the 16 eta
+// of one 128-byte line of the input run for every (span, pair) in turn:
+// the line is fetched once, and the 16 kernel columns (2 MB) are read from
+// that XCD's L2 after their first use.
 template <int NA>
 __global__ void __launch_bounds__(NA / kRegPts)
 k_lp_conv_tab(const float2* __restrict__ ghat, LprecTables t, int pairs, float2* __restrict__ fhat) {
@@ -291,40 +296,30 @@ k_lp_conv_tab(const float2* __restrict__ ghat, LprecTables t, int pairs, float2*
     const int NS = t.Ns;
     const int id = blockIdx.x;
     const int xcd = id & 7, r = id >> 3;
-    const int c = ((r >> 4) * 8 + xcd) * 16 + (r & 15);
-    const int span = c / NS, eta = c - span * NS;
+    const int per = t.spans * pairs * 16;  // work-groups per 16-eta group on one XCD
+    const int G = r / per, rem = r - G * per;
+    const int sp = rem >> 4;
+    const int span = sp / pairs, p = sp - span * pairs;
+    const int eta = (G * 8 + xcd) * 16 + (rem & 15);
     const float2* kcol = t.kt + static_cast<int64_t>(eta) * NA;
     const int first = t.M * (t.n_span - 1);
     const int NAc = t.NAc;
-#pragma unroll 1
-    for (int p = 0; p < pairs; ++p) {
-        const float2* src = ghat + ((static_cast<int64_t>(p) * t.spans + span) * (NS / 16) + (eta >> 4)) *
-                                       t.n_span * 16 + (eta & 15);
-        __syncthreads();
-        for (int k = tid; k < NAc; k += B)
-            lds[k] = k < t.n_span ? src[static_cast<int64_t>(k) * 16] : make_float2(0.0f, 0.0f);
-        __syncthreads();
-        // an opaque thread index per pair: the transform's twiddle loads and
-        // the per-slot offsets are not hoisted out of the pair loop into
-        // registers held across it (they would spill)
-        int ti = tid;
-        asm volatile("" : "+v"(ti));
-        fft_forward_lds(lds, NAc, t.log2NAc, t.twNAc);
-        float2 x[kRegPts];
+    const float2* src = ghat + ((static_cast<int64_t>(p) * t.spans + span) * (NS / 16) + (eta >> 4)) *
+                                   t.n_span * 16 + (eta & 15);
+    for (int k = tid; k < NAc; k += B)
+        lds[k] = k < t.n_span ? src[static_cast<int64_t>(k) * 16] : make_float2(0.0f, 0.0f);
+    __syncthreads();
+    fft_forward_lds(lds, NAc, t.log2NAc, t.twNAc);
+    float2 x[kRegPts];
 #pragma unroll
-        for (int s = 0; s < kRegPts; ++s)
-            x[s] = cconj(cmul(lds[(ti + B * s) & (NAc - 1)], kcol[ti + B * s]));
-        __syncthreads();
-        reg_fft<NA>(x, lds, t.twNA, ti);
-        int to = tid;
-        asm volatile("" : "+v"(to));
-        float2* dst = fhat + (static_cast<int64_t>(p) * t.spans + span) * t.nmb * NS * 16;
+    for (int s = 0; s < kRegPts; ++s) x[s] = cconj(cmul(lds[(tid + B * s) & (NAc - 1)], kcol[tid + B * s]));
+    __syncthreads();
+    reg_fft<NA>(x, lds, t.twNA, tid);
+    float2* dst = fhat + (static_cast<int64_t>(p) * t.spans + span) * t.nmb * NS * 16;
 #pragma unroll
-        for (int s = 0; s < kRegPts; ++s) {
-            const int m = to + B * s - first;
-            if (m >= 0 && m < t.rows)
-                dst[(static_cast<int64_t>(m >> 4) * NS + eta) * 16 + (m & 15)] = cconj(x[s]);
-        }
+    for (int s = 0; s < kRegPts; ++s) {
+        const int m = tid + B * s - first;
+        if (m >= 0 && m < t.rows) dst[(static_cast<int64_t>(m >> 4) * NS + eta) * 16 + (m & 15)] = cconj(x[s]);
     }
 }
 
@@ -445,7 +440,11 @@ template <int NA>
 hipError_t launch_conv_t(const LprecTables& t, const float2* ghat, int pairs, float2* fhat, hipStream_t st) {
     const size_t lds = conv_lds_bytes(NA, t.NAc);
     if constexpr (NA >= 8192) {
-        hipLaunchKernelGGL(k_lp_conv_tab<NA>, dim3(t.spans * t.Ns), dim3(NA / kRegPts), lds, st, ghat, t, pairs, fhat);
+        // one work-group per (span, eta, pair); the eta-group order needs Ns / 16 divisible by 8
+        if (static_cast<int64_t>(t.spans) * t.Ns * pairs > 0x7fffffff || (t.Ns / 16) % 8 != 0)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_lp_conv_tab<NA>, dim3(t.spans * t.Ns * pairs), dim3(NA / kRegPts), lds, st, ghat, t,
+                           pairs, fhat);
     } else {
         hipLaunchKernelGGL(k_lp_conv<NA>, dim3(t.spans * t.Ns), dim3(NA / kRegPts), lds, st, ghat, t, pairs, fhat);
     }
