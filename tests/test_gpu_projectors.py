@@ -48,6 +48,28 @@ def test_backproject_matches_oracle(tp, g):
         assert_parity(got, want, "f32", label=f"backproject {g}")
 
 
+@pytest.mark.parametrize("g", GEOMS)
+def test_backproject_f16_rows_match_oracle_16bit_mode(tp, g):
+    """FP16 rows (the v_dot2 kernel, pair staging with its detector-edge path)
+    against the oracle's 16-bit mode on the same stored rows."""
+    na, n, N, c, rows = g
+    rng = np.random.default_rng(na * 5 + n)
+    ang = synth.uniform_angles(na) + 0.021
+    q = to_dev(rng.standard_normal((rows, na, n)).astype(np.float32)).half()
+    stored = to_host(q).astype(np.float64)
+    plan = tp.Plan(ang, n, c, N)
+    note(f"backproject f16 {g}")
+    got = to_host(tp.backproject(plan, q))
+    want = oracle.backproject(stored, ang, c, N, weights="f16")
+    # one angle: a voxel is a single term, so a weight that rounds to the
+    # neighbouring FP16 value moves it by up to 2^-11 of a tap (no averaging)
+    mx = F16_MODE_MAX_REL if na > 1 else 2.0 ** -9
+    if np.linalg.norm(want) == 0:  # every ray misses the detector
+        assert np.all(got == 0)
+    else:
+        assert_parity(got, want, "f32", rel=F16_MODE_REL_L2, mx=mx, label=f"backproject f16 {g}")
+
+
 def test_backproject_constant_rows_give_pi(tp):
     na, n = 90, 128
     ang = synth.uniform_angles(na)
