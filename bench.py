@@ -70,6 +70,8 @@ def parse():
                     help="instead: the host-to-host three-stream pipeline over uneven chunks "
                          "(defaults become 3000 angles x 2048 rows x 4096 columns, FP16 storage)")
     ap.add_argument("--pattern", default="32,64,128", help="chunk sizes of the pipeline mode")
+    ap.add_argument("--out-dtype", default="f32", choices=("f32", "f16"),
+                    help="pipeline mode: precision of the output slices (f16: the 16-bit mode, FP16 storage only)")
     ap.add_argument("--io-dir", default="",
                     help="pipeline mode: read the scan from and write the volume to raw files in this directory "
                          "(native reader/writer threads; the files are written first and deleted afterwards)")
@@ -1123,14 +1125,16 @@ def cfg5_check_rows(chunks, rows: int, n_even: int = 10):
     return sorted(set(zs))
 
 
-def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, points=256):
+def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, points=256, out_dtype="f32"):
     """Host-pinned to host-pinned reconstruction through the three-stream
     pipeline (copy-in, compute, copy-out) over uneven chunks, with per-chunk
     graphs and the autotuned backprojection tiling; the same chunks are also
     timed with inputs resident on the device to show how much of the copy
     time the overlap hides.  Checked against the FP64 oracle at ``points``
     voxels of each check slice, and bitwise against the resident computation
-    on the check slices of the first three chunks.  Returns the record."""
+    on the check slices of the first three chunks.  ``out_dtype`` 'f16': FP16
+    slices (the 16-bit mode's output; half the copy-out and write bytes).
+    Returns the record."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -1162,10 +1166,12 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
                                  workspace=ws, kind=kind)
         else:
             tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st, out=out,
-                         workspace=ws, kind=kind)
+                         workspace=ws, kind=kind, out_dtype=out_dtype)
 
+    odt = torch.float16 if out_dtype == "f16" else torch.float32
+    out_bytes = 2 if out_dtype == "f16" else 4
     # compute only, inputs resident on the device, same chunks
-    vol_c = torch.empty((max(pattern), n, n), dtype=torch.float32, device=dev)
+    vol_c = torch.empty((max(pattern), n, n), dtype=odt, device=dev)
     ws_bytes = plan.fourier_workspace_bytes(max(pattern)) if fourier else plan.fbp_workspace_bytes(max(pattern), st)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     resident = {}
@@ -1230,7 +1236,7 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         log(f"scan written to {io_dir} in {time.perf_counter() - t1:.1f} s")
         source = pipeline.FileSource(paths["proj"], paths["dark"], paths["flat"], na, rows, n, dark_h.shape[0],
                                      flat_h.shape[0], threads=16)
-        file_sink = pipeline.FileSink(paths["vol"], rows, n, threads=16)
+        file_sink = pipeline.FileSink(paths["vol"], rows, n, threads=16, elem_bytes=out_bytes)
 
         def sink(z0, z1, vol):  # noqa: F811 (the file variant)
             file_sink(z0, z1, vol)
@@ -1240,7 +1246,7 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         io = paths
 
     pl = pipeline.ChunkPipeline(plan, max_rows=max(pattern), n_dark=dark_h.shape[0], n_flat=flat_h.shape[0],
-                                storage=st, use_graphs=True, kind=kind, method=method)
+                                storage=st, use_graphs=True, kind=kind, method=method, out_dtype=out_dtype)
     pl.prepare(chunks)
     log(f"pipeline: {len(chunks)} chunks, {pl.stats.graphs_captured} graphs; running")
     t_run = time.perf_counter()
@@ -1250,7 +1256,8 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         stats.seconds = time.perf_counter() - t_run
     log(f"pipeline: {stats.seconds:.2f} s " + ("file to file" if io else "host to host"))
     if io:
-        vol_file = np.memmap(io["vol"], dtype=np.float32, mode="r", shape=(rows, n, n))
+        vol_file = np.memmap(io["vol"], dtype=np.float16 if out_dtype == "f16" else np.float32, mode="r",
+                             shape=(rows, n, n))
         for z in check_z:
             kept[z] = np.array(vol_file[z])
         del vol_file
@@ -1271,7 +1278,7 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         w_all.append(want)
     g_all, w_all = np.concatenate(g_all), np.concatenate(w_all)
     h2d = (proj_h.nbytes + dark_h.nbytes + flat_h.nbytes) / 1e9
-    d2h = rows * n * n * 4 / 1e9
+    d2h = rows * n * n * out_bytes / 1e9
     out = {
         "metric": "Gvoxel-angle updates/s host-pinned to host-pinned (three-stream pipeline, uneven chunks)",
         "value": round(updates / stats.seconds / 1e9, 2),
@@ -1283,7 +1290,8 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         "config": {"workload": f"fbp {n}x{n}x{rows} from {na} angles x {rows} rows x {n} cols 12-bit ellipsoid scan, "
                                f"{FILTER_NAMES[kind]}, "
                                + ("Fourier-domain backprojection" if fourier else "linear-interpolation backprojection"),
-                   "storage": None if fourier else st, "chunks": list(pattern), "n_chunks": len(chunks),
+                   "storage": None if fourier else st, "slices_out": out_dtype,
+                   "chunks": list(pattern), "n_chunks": len(chunks),
                    "graphs": stats.graphs_captured, "bp_tuning": None if fourier else [k, a]},
         "s_host_to_host" if not io else "s_file_to_file": round(stats.seconds, 3),
         "s_compute_only_resident": round(t_compute, 3),
@@ -1319,7 +1327,8 @@ def main_pipeline(args):
     na = args.angles if (args.angles != 2048 or args.io_dir) else 3000
     st = args.storage.split(",")[0] if args.storage != "f16,f32,bf16" else "f16"
     pattern = tuple(int(v) for v in args.pattern.split(","))
-    out = pipeline_run(dev, n, na, args.rows, st, pattern, args.method, args.filter, args.io_dir, log)
+    out = pipeline_run(dev, n, na, args.rows, st, pattern, args.method, args.filter, args.io_dir, log,
+                       out_dtype=args.out_dtype)
     print(json.dumps(out), flush=True)
 
 

@@ -301,6 +301,21 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan,
                               void* workspace, size_t workspace_bytes,
                               float* vol, void* stream, void* const* events);
 
+/* As tp_fbp_chunk_events with a choice of output precision (paper, Section 3:
+ * in the 16-bit mode the reconstructed volumes are stored in 16 bits, half
+ * the memory and storage traffic).  vol_dtype TP_F32: vol is dev float
+ * [n_rows][N][N], exactly tp_fbp_chunk_events.  TP_F16: vol is dev IEEE half
+ * [n_rows][N][N], each voxel the FP32 result rounded once to nearest; needs
+ * storage TP_F16 (TP_EUNSUPPORTED otherwise, nothing enqueued).  Other
+ * vol_dtype values return TP_EINVAL. */
+tp_status tp_fbp_chunk_out(const tp_plan* plan,
+                           const uint16_t* proj, int64_t proj_stride,
+                           const uint16_t* dark, int32_t n_dark,
+                           const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                           int32_t n_rows, tp_filter_kind kind, tp_dtype storage,
+                           void* workspace, size_t workspace_bytes,
+                           tp_dtype vol_dtype, void* vol, void* stream, void* const* events);
+
 /* --------------------------------------------------------------------------
  * Fourier-domain filtered backprojection ("FourierRec"; paper, Section 2.2:
  * the backprojection evaluated with exponential interpolation kernels in the

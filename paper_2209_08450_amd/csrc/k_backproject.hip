@@ -235,9 +235,9 @@ k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, 
 // FP16 rows: pairs (Q[j], Q[j+1]) per slice in LDS, FP16 weights, v_dot2.
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
-template <int K, int A>
+template <int K, int A, typename OutT>
 __global__ void __launch_bounds__(kBpThreads)
-k_backproject_h2(GeoTables g, const __half* __restrict__ filt, int n_rows, float scale, float* __restrict__ vol,
+k_backproject_h2(GeoTables g, const __half* __restrict__ filt, int n_rows, float scale, OutT* __restrict__ vol,
                  int accumulate) {
     constexpr int BIN = K * 4;            // bytes of one (angle, bin) group: K packed pairs
     constexpr int P = bin_pitch(BIN);     // LDS bytes between bins
@@ -347,7 +347,12 @@ k_backproject_h2(GeoTables g, const __half* __restrict__ filt, int n_rows, float
             if (k >= kz) continue;
             const int64_t idx = (static_cast<int64_t>(z0 + k) * N + y) * N + x;
             const float v = scale * acc[i][k];
-            vol[idx] = accumulate ? vol[idx] + v : v;
+            if constexpr (std::is_same<OutT, __half>::value) {
+                // FP16 slices: the FP32 sum rounded once to nearest
+                vol[idx] = __float2half(accumulate ? __half2float(vol[idx]) + v : v);
+            } else {
+                vol[idx] = accumulate ? vol[idx] + v : v;
+            }
         }
     }
 }
@@ -359,52 +364,64 @@ size_t bp_lds_bytes(tp_dtype dt, int K, int A) {
 
 // A null `vol` only sets the instance's dynamic-LDS limit (tp_prepare), so
 // that later launches, possibly graph-captured, make no attribute call.
+// `half_out`: FP16 output slices (FP16 rows only).
 template <typename T, int K, int A>
-hipError_t launch_bp_t(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
+hipError_t launch_bp_t(const GeoTables& g, const void* filt, int n_rows, float scale, void* vol, bool half_out,
                        int accumulate, size_t lds, hipStream_t st) {
-    const void* fn;
-    if constexpr (std::is_same<T, __half>::value) {
-        fn = reinterpret_cast<const void*>(k_backproject_h2<K, A>);
-    } else {
-        fn = reinterpret_cast<const void*>(k_backproject<T, K, A>);
+    if constexpr (!std::is_same<T, __half>::value) {
+        if (half_out) return hipErrorInvalidValue;
     }
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        if (e != hipSuccess) return e;
+        const void* fns[2] = {nullptr, nullptr};
+        if constexpr (std::is_same<T, __half>::value) {
+            fns[0] = reinterpret_cast<const void*>(k_backproject_h2<K, A, float>);
+            fns[1] = reinterpret_cast<const void*>(k_backproject_h2<K, A, __half>);
+        } else {
+            fns[0] = reinterpret_cast<const void*>(k_backproject<T, K, A>);
+        }
+        for (const void* fn : fns) {
+            if (!fn) continue;
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+            if (e != hipSuccess) return e;
+        }
     }
     if (vol == nullptr) return hipSuccess;
     const dim3 grid(static_cast<unsigned>(g.nb * g.nb), static_cast<unsigned>((n_rows + K - 1) / K));
     if constexpr (std::is_same<T, __half>::value) {
-        hipLaunchKernelGGL((k_backproject_h2<K, A>), grid, dim3(kBpThreads), lds, st, g,
-                           static_cast<const __half*>(filt), n_rows, scale, vol, accumulate);
+        if (half_out)
+            hipLaunchKernelGGL((k_backproject_h2<K, A, __half>), grid, dim3(kBpThreads), lds, st, g,
+                               static_cast<const __half*>(filt), n_rows, scale, static_cast<__half*>(vol), accumulate);
+        else
+            hipLaunchKernelGGL((k_backproject_h2<K, A, float>), grid, dim3(kBpThreads), lds, st, g,
+                               static_cast<const __half*>(filt), n_rows, scale, static_cast<float*>(vol), accumulate);
     } else {
         hipLaunchKernelGGL((k_backproject<T, K, A>), grid, dim3(kBpThreads), lds, st, g, static_cast<const T*>(filt),
-                           n_rows, scale, vol, accumulate);
+                           n_rows, scale, static_cast<float*>(vol), accumulate);
     }
     return hipGetLastError();
 }
 
 template <typename T, int K>
-hipError_t launch_bp_a(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
+hipError_t launch_bp_a(const GeoTables& g, const void* filt, int n_rows, float scale, void* vol, bool half_out,
                        int accumulate, int A, size_t lds, hipStream_t st) {
     switch (A) {
-        case 8: return launch_bp_t<T, K, 8>(g, filt, n_rows, scale, vol, accumulate, lds, st);
-        case 16: return launch_bp_t<T, K, 16>(g, filt, n_rows, scale, vol, accumulate, lds, st);
-        case 32: return launch_bp_t<T, K, 32>(g, filt, n_rows, scale, vol, accumulate, lds, st);
-        case 64: return launch_bp_t<T, K, 64>(g, filt, n_rows, scale, vol, accumulate, lds, st);
+        case 8: return launch_bp_t<T, K, 8>(g, filt, n_rows, scale, vol, half_out, accumulate, lds, st);
+        case 16: return launch_bp_t<T, K, 16>(g, filt, n_rows, scale, vol, half_out, accumulate, lds, st);
+        case 32: return launch_bp_t<T, K, 32>(g, filt, n_rows, scale, vol, half_out, accumulate, lds, st);
+        case 64: return launch_bp_t<T, K, 64>(g, filt, n_rows, scale, vol, half_out, accumulate, lds, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_bp_k(const GeoTables& g, const void* filt, int n_rows, float scale, float* vol,
+hipError_t launch_bp_k(const GeoTables& g, const void* filt, int n_rows, float scale, void* vol, bool half_out,
                        int accumulate, int K, int A, size_t lds, hipStream_t st) {
     switch (K) {
-        case 1: return launch_bp_a<T, 1>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
-        case 2: return launch_bp_a<T, 2>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
-        case 4: return launch_bp_a<T, 4>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
-        case 8: return launch_bp_a<T, 8>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
-        case 16: return launch_bp_a<T, 16>(g, filt, n_rows, scale, vol, accumulate, A, lds, st);
+        case 1: return launch_bp_a<T, 1>(g, filt, n_rows, scale, vol, half_out, accumulate, A, lds, st);
+        case 2: return launch_bp_a<T, 2>(g, filt, n_rows, scale, vol, half_out, accumulate, A, lds, st);
+        case 4: return launch_bp_a<T, 4>(g, filt, n_rows, scale, vol, half_out, accumulate, A, lds, st);
+        case 8: return launch_bp_a<T, 8>(g, filt, n_rows, scale, vol, half_out, accumulate, A, lds, st);
+        case 16: return launch_bp_a<T, 16>(g, filt, n_rows, scale, vol, half_out, accumulate, A, lds, st);
     }
     return hipErrorInvalidValue;
 }
@@ -417,22 +434,25 @@ size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_b
 
 hipError_t prepare_backproject(tp_dtype dt, int slices_per_block, int angles_per_block) {
     GeoTables g{};
-    return launch_backproject(g, nullptr, dt, 0, 0.0f, nullptr, 0, slices_per_block, angles_per_block, nullptr);
+    return launch_backproject(g, nullptr, dt, 0, 0.0f, nullptr, TP_F32, 0, slices_per_block, angles_per_block,
+                              nullptr);
 }
 
 hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt, int n_rows, float scale,
-                              float* vol, int accumulate, int slices_per_block, int angles_per_block,
-                              hipStream_t st) {
+                              void* vol, tp_dtype vol_dt, int accumulate, int slices_per_block,
+                              int angles_per_block, hipStream_t st) {
     const size_t lds = bp_lds_bytes(dt, slices_per_block, angles_per_block);
+    const bool half_out = vol_dt == TP_F16;
+    if (vol_dt != TP_F32 && !half_out) return hipErrorInvalidValue;
     switch (dt) {
         case TP_F32:
-            return launch_bp_k<float>(g, filt, n_rows, scale, vol, accumulate, slices_per_block,
+            return launch_bp_k<float>(g, filt, n_rows, scale, vol, half_out, accumulate, slices_per_block,
                                       angles_per_block, lds, st);
         case TP_F16:
-            return launch_bp_k<__half>(g, filt, n_rows, scale, vol, accumulate, slices_per_block,
+            return launch_bp_k<__half>(g, filt, n_rows, scale, vol, half_out, accumulate, slices_per_block,
                                        angles_per_block, lds, st);
         case TP_BF16:
-            return launch_bp_k<uint16_t>(g, filt, n_rows, scale, vol, accumulate, slices_per_block,
+            return launch_bp_k<uint16_t>(g, filt, n_rows, scale, vol, half_out, accumulate, slices_per_block,
                                          angles_per_block, lds, st);
     }
     return hipErrorInvalidValue;

@@ -1173,7 +1173,7 @@ tp_status tp_backproject(const tp_plan* plan, const void* filt, tp_dtype in_dtyp
     const int K = plan->bp_k[in_dtype], A = plan->bp_a[in_dtype];
     if ((n_rows + K - 1) / K > 65535)
         return fail(TP_EINVAL, "n_rows=%d too large for slices_per_block=%d", n_rows, K);
-    hipError_t e = tp::launch_backproject(plan->geo, filt, in_dtype, n_rows, scale, vol, accumulate, K, A,
+    hipError_t e = tp::launch_backproject(plan->geo, filt, in_dtype, n_rows, scale, vol, TP_F32, accumulate, K, A,
                                           static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "backproject launch");
     return TP_OK;
@@ -1225,12 +1225,23 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
                               int32_t n_dark, const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
                               int32_t n_rows, tp_filter_kind kind, tp_dtype storage, void* workspace,
                               size_t workspace_bytes, float* vol, void* stream, void* const* events) {
+    return tp_fbp_chunk_out(plan, proj, proj_stride, dark, n_dark, flat, n_flat, frame_stride, n_rows, kind, storage,
+                            workspace, workspace_bytes, TP_F32, vol, stream, events);
+}
+
+tp_status tp_fbp_chunk_out(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride, const uint16_t* dark,
+                           int32_t n_dark, const uint16_t* flat, int32_t n_flat, int64_t frame_stride, int32_t n_rows,
+                           tp_filter_kind kind, tp_dtype storage, void* workspace, size_t workspace_bytes,
+                           tp_dtype vol_dtype, void* vol, void* stream, void* const* events) {
     if (!plan) return fail(TP_EINVAL, "plan is null");
     tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, plan->na, n_rows,
                             plan->n);
     if (s != TP_OK) return s;
     if (!valid_kind(kind)) return fail(TP_EUNSUPPORTED, "unknown filter kind %d", static_cast<int>(kind));
     if (!valid_dtype(storage)) return fail(TP_EINVAL, "bad storage dtype %d", storage);
+    if (vol_dtype != TP_F32 && vol_dtype != TP_F16) return fail(TP_EINVAL, "bad volume dtype %d", vol_dtype);
+    if (vol_dtype == TP_F16 && storage != TP_F16)
+        return fail(TP_EUNSUPPORTED, "FP16 slices need FP16 storage (the 16-bit mode)");
     if (!vol) return fail(TP_EINVAL, "vol is null");
     if (!workspace) return fail(TP_EINVAL, "workspace is null");
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(TP_EINVAL, "workspace not 256-byte aligned");
@@ -1261,8 +1272,8 @@ tp_status tp_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj, int64_t
     e = tp::launch_norm_filter(in, dmean, den, plan->na, n_rows, plan->n, ft, storage, filt, st);
     if (e != hipSuccess) return hip_fail(e, "norm_filter launch");
     if ((e = mark(2)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = tp::launch_backproject(plan->geo, filt, storage, n_rows, static_cast<float>(M_PI / plan->na), vol, 0, K, A,
-                               st);
+    e = tp::launch_backproject(plan->geo, filt, storage, n_rows, static_cast<float>(M_PI / plan->na), vol, vol_dtype,
+                               0, K, A, st);
     if (e != hipSuccess) return hip_fail(e, "backproject launch");
     if ((e = mark(3)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return TP_OK;

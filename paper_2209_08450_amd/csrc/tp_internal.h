@@ -143,8 +143,9 @@ hipError_t launch_filter(const void* in, tp_dtype in_dt, void* out, tp_dtype out
 hipError_t launch_norm_filter(const RawInput& in, const float* dmean, const float* den, int n_angles,
                               int n_rows, int n_det, const FilterTables& ft, tp_dtype out_dt, void* out,
                               hipStream_t st);
+// vol: FP32 slices (vol_dt TP_F32), or FP16 slices (TP_F16, FP16 rows only)
 hipError_t launch_backproject(const GeoTables& g, const void* filt, tp_dtype dt, int n_rows, float scale,
-                              float* vol, int accumulate, int slices_per_block, int angles_per_block,
+                              void* vol, tp_dtype vol_dt, int accumulate, int slices_per_block, int angles_per_block,
                               hipStream_t st);
 size_t backproject_lds_bytes(tp_dtype dt, int slices_per_block, int angles_per_block);
 // Sets the dynamic-LDS limit of one backprojection kernel instance (no launch).

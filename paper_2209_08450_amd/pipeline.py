@@ -66,13 +66,15 @@ class FileSource:
 
 
 class FileSink:
-    """Pipeline sink that writes each chunk's slices (float32 [rows][N][N]) into
-    one raw volume file with tp_io_write_slices; the file is created at its
-    full size first."""
+    """Pipeline sink that writes each chunk's slices ([rows][N][N], float32 or,
+    with ``elem_bytes=2``, FP16) into one raw volume file with
+    tp_io_write_slices; the file is created at its full size first."""
 
-    def __init__(self, path, n_rows: int, n_vox: int, threads: int = 16):
+    def __init__(self, path, n_rows: int, n_vox: int, threads: int = 16, elem_bytes: int = 4):
         self.path = str(path)
-        self.slice_bytes = int(n_vox) * int(n_vox) * 4
+        if elem_bytes not in (2, 4):
+            raise ValueError("elem_bytes must be 2 (FP16 slices) or 4 (float32)")
+        self.slice_bytes = int(n_vox) * int(n_vox) * int(elem_bytes)
         self.threads = int(threads)
         tp.io_create(self.path, int(n_rows) * self.slice_bytes)
 
@@ -111,7 +113,7 @@ class ChunkPipeline:
 
     def __init__(self, plan: "tp.Plan", max_rows: int, n_dark: int, n_flat: int, storage="f16",
                  use_graphs: bool = True, poison: bool = False, device=None, kind="ramp", method="linear",
-                 half_width: int = 0):
+                 half_width: int = 0, out_dtype="f32"):
         self.plan = plan
         self.kind = kind
         tp.filter_code(kind)  # reject unknown names early
@@ -119,6 +121,12 @@ class ChunkPipeline:
             raise ValueError(f"method must be 'linear' or 'fourier', not {method!r}")
         self.method = method
         self.half_width = int(half_width)
+        if out_dtype not in ("f32", "f16"):
+            raise ValueError(f"out_dtype must be 'f32' or 'f16', not {out_dtype!r}")
+        if out_dtype == "f16" and (method != "linear" or storage != "f16"):
+            raise ValueError("FP16 slices come from the linear method with FP16 storage (the 16-bit mode)")
+        self.out_dtype = out_dtype
+        odt = torch.float16 if out_dtype == "f16" else torch.float32
         if method == "fourier":
             plan.fourier_prepare(kind, self.half_width)  # tables before any capture
         self.device = torch.device(device or f"cuda:{torch.cuda.current_device()}")
@@ -140,11 +148,11 @@ class ChunkPipeline:
         self.pin_in = [pinned(na * r * n, i16) for _ in range(2)]
         self.pin_dark = [pinned(self.n_dark * r * n, i16) for _ in range(2)]
         self.pin_flat = [pinned(self.n_flat * r * n, i16) for _ in range(2)]
-        self.pin_out = [pinned(r * N * N, torch.float32) for _ in range(2)]
+        self.pin_out = [pinned(r * N * N, odt) for _ in range(2)]
         self.dev_in = [dev(na * r * n, i16) for _ in range(2)]
         self.dev_dark = [dev(self.n_dark * r * n, i16) for _ in range(2)]
         self.dev_flat = [dev(self.n_flat * r * n, i16) for _ in range(2)]
-        self.dev_out = [dev(r * N * N, torch.float32) for _ in range(2)]
+        self.dev_out = [dev(r * N * N, odt) for _ in range(2)]
         ws_bytes = plan.fourier_workspace_bytes(r) if method == "fourier" else plan.fbp_workspace_bytes(r, storage)
         self.ws = dev(max(256, ws_bytes), torch.uint8)
         # streams at default priority
@@ -174,7 +182,7 @@ class ChunkPipeline:
                                  workspace=self.ws, kind=self.kind, half_width=self.half_width)
         else:
             tp.fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], self.storage, out=v["dev_out"],
-                         workspace=self.ws, kind=self.kind)
+                         workspace=self.ws, kind=self.kind, out_dtype=self.out_dtype)
 
     def prepare(self, chunks):
         """Capture the graphs of every (chunk size, buffer) the run will use.
@@ -203,7 +211,8 @@ class ChunkPipeline:
         source(z0, z1, proj, dark, flat): fill the pinned uint16 views
             proj [n_angles][c][n_det], dark [n_dark][c][n_det], flat [n_flat][c][n_det]
             (int16 tensors holding uint16 bit patterns) with rows z0..z1.
-        sink(z0, z1, vol): consume the pinned float32 view vol [c][N][N]; it is
+        sink(z0, z1, vol): consume the pinned view vol [c][N][N] (float32, or FP16
+            with out_dtype 'f16'); it is
             reused for a later chunk once sink returns.
         """
         import time

@@ -71,6 +71,8 @@ _fbp_chunk = _proto("tp_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32,
                     _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp)
 _fbp_chunk_events = _proto("tp_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
                            _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp, ctypes.POINTER(_c_vp))
+_fbp_chunk_out = _proto("tp_fbp_chunk_out", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
+                        _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_i32, _c_vp, _c_vp, ctypes.POINTER(_c_vp))
 _fourier_ws = _proto("tp_fourier_workspace_bytes", _c_sz, _c_vp, _c_i32)
 _fourier_prepare = _proto("tp_fourier_prepare", _c_i32, _c_vp, _c_i32, _c_i32)
 _fourier_chunk = _proto("tp_fourier_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp, _c_i32, _c_i64,
@@ -430,10 +432,13 @@ def radon(plan: Plan, vol, out=None, workspace=None, stream=None):
 
 
 def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=None, stream=None, events=None,
-              kind="ramp"):
-    """Raw counts of a row chunk -> reconstructed slices [rows][N][N] (float32).
+              kind="ramp", out_dtype=None):
+    """Raw counts of a row chunk -> reconstructed slices [rows][N][N].
 
     ``kind``: filter window, 'ramp', 'shepp' or 'parzen' (or its code).
+
+    ``out_dtype``: 'f32' (default) or 'f16' (the 16-bit mode's FP16 slices,
+    storage 'f16' only); ``out``, when given, must have that type.
 
     ``events``: optional list of four recorded-once ``torch.cuda.Event`` objects
     (or None entries) marked before the dark/flat means, the fused
@@ -455,21 +460,19 @@ def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=N
     need = plan.fbp_workspace_bytes(n_rows, code)
     if workspace is None:
         workspace = _workspace(need, proj.device)
-    out = _out(out, (n_rows, plan.n_vox, plan.n_vox), torch.float32, proj)
-    if events is None:
-        _check(_fbp_chunk(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode,
-                          code, _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
-                          _dev(out, "out"), _stream_ptr(stream)))
-    else:
+    vcode = dtype_code("f32" if out_dtype is None else out_dtype)
+    tdt = torch.float16 if vcode == dtype_code("f16") else torch.float32
+    out = _out(out, (n_rows, plan.n_vox, plan.n_vox), tdt, proj)
+    arr = None
+    if events is not None:
         if len(events) != 4:
             raise ValueError("events must hold four entries")
         arr = (_c_vp * 4)(*[_c_vp(e.cuda_event) if e is not None else _c_vp() for e in events])
         if any(e is not None and not e.cuda_event for e in events):
             raise ValueError("record each event once before passing it (torch creates it lazily)")
-        _check(_fbp_chunk_events(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows,
-                                 kcode, code, _dev(workspace, "workspace"),
-                                 workspace.numel() * workspace.element_size(), _dev(out, "out"),
-                                 _stream_ptr(stream), arr))
+    _check(_fbp_chunk_out(plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode,
+                          code, _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(), vcode,
+                          _dev(out, "out"), _stream_ptr(stream), arr))
     return out
 
 

@@ -59,6 +59,42 @@ def test_pipeline_bitwise_equals_monolithic(env, graphs, poison, storage):
     assert np.array_equal(got, want)
 
 
+def test_pipeline_fp16_slices(env, tmp_path):
+    # the 16-bit mode end to end: FP16 rows and FP16 slices out of the
+    # pipeline (graphs, uneven chunks) equal the monolithic call's FP16 slices
+    # bitwise, those are its FP32 slices rounded once, and the file sink
+    # writes 2-byte voxels
+    import torch
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    P, D, F = to_dev(s.proj), to_dev(s.dark), to_dev(s.flat)
+    want32 = tp.fbp_chunk(plan, P, D, F, "f16")
+    want16 = tp.fbp_chunk(plan, P, D, F, "f16", out_dtype="f16")
+    assert want16.dtype == torch.float16
+    assert torch.equal(want16, want32.half())
+    chunks = pipeline.uneven_chunks(100, (7, 13, 32))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, storage="f16", use_graphs=True,
+                                out_dtype="f16")
+    got = np.full((100, 128, 128), np.nan, np.float16)
+    note("pipeline FP16 slices")
+    pl.run(chunks, _source(s), _sink(got))
+    assert np.array_equal(got, to_host(want16).astype(np.float16))
+    path = tmp_path / "vol16.raw"
+    sink = pipeline.FileSink(path, 100, 128, threads=4, elem_bytes=2)
+    pl.run(chunks, _source(s), sink)
+    sink.flush()
+    on_disk = np.fromfile(path, dtype=np.float16).reshape(100, 128, 128)
+    assert np.array_equal(on_disk, got)
+    want = oracle.fbp(s.proj, s.dark, s.flat, s.angles, s.center)
+    assert_parity(got.astype(np.float64), want, "f16", label="pipeline FP16 slices")
+    with pytest.raises(ValueError):
+        pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, storage="f32", out_dtype="f16")
+    with pytest.raises(tp.TpError):
+        tp.fbp_chunk(plan, P, D, F, "f32", out_dtype="f16")  # FP16 slices need FP16 rows
+    with pytest.raises(tp.TpError):
+        tp.fbp_chunk(plan, P, D, F, "f16", out_dtype="bf16")  # no BF16 slices
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_pipeline_matches_oracle(env, storage):
     # the pipelined volume, uneven chunks 7/13/32 through three streams with
