@@ -90,6 +90,8 @@ def test_plan_null_handles(tp):
     assert tp._backproject(nul, nul, 0, 1, 1.0, nul, 0, nul) == tp.TP_EINVAL
     assert tp._radon(nul, nul, 1, nul, nul, 0, nul) == tp.TP_EINVAL
     assert tp._radon_ws(nul, 4) == 0
+    assert tp._fbp_chunk_out(nul, nul, 0, nul, 1, nul, 1, 0, 1, tp.TP_RAMP, tp.TP_F16, nul, 0, tp.TP_F16, nul, nul,
+                             None) == tp.TP_EINVAL
     assert tp._plan_destroy(nul) == tp.TP_OK
 
 
