@@ -35,7 +35,8 @@
 // and voxel adds (1 - w) Q[j] + w Q[j+1] to the FP32 sum: half the VALU issue
 // of two mixed-precision FMAs, the same LDS bytes.  The weights' rounding
 // (at most 2^-12 of a bin's value) is the FP16 mode's only change to the
-// arithmetic; every product is exact and every sum FP32.
+// arithmetic; every product is exact and every sum FP32.  Its output slices
+// are FP32, or FP16 (each voxel's FP32 result rounded once) for 16-bit volumes.
 #include <type_traits>
 
 #include "tp_internal.h"
