@@ -38,6 +38,7 @@ __global__ void __launch_bounds__(256) k_peak_valu(float* __restrict__ out, int 
     half2_t x = {static_cast<_Float16>(a), static_cast<_Float16>(b)};
     half2_t y = {static_cast<_Float16>(b), static_cast<_Float16>(a)};
     if constexpr (FORM != TP_VALU_FMA_F32_SGPR) asm volatile("" : "+v"(va), "+v"(vb), "+v"(x), "+v"(y));
+#pragma unroll 8
     for (int it = 0; it < iters; ++it) {
         // an opaque FP16 operand each step, so its widening stays inside the FMA
         if constexpr (FORM == TP_VALU_FMA_MIX_F16) asm volatile("" : "+v"(x));
