@@ -847,8 +847,8 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     // which side of the image a bin's strip lies (angles near 0 and near pi
     // are mirror images), so each class is split by that sign.  Each of the 4
     // segments is sorted by the angle reduced modulo pi into [-pi/4, 3pi/4)
-    // (neighbours share a work-group) and padded with -1 to a multiple of 4
-    // entries, so no work-group of 4 angles straddles two segments.
+    // (neighbours share a work-group) and padded with -1 to a multiple of 8
+    // entries, so no work-group of 4 or 8 angles straddles two segments.
     auto key = [&](int a) {
         double t = std::fmod(g->angles[a] + M_PI / 4, M_PI);
         if (t < 0) t += M_PI;
@@ -867,7 +867,7 @@ tp_status tp_plan_create(const tp_geometry* g, tp_plan** out) {
     for (int q = 0; q < 4; ++q) {
         std::sort(seg[q].begin(), seg[q].end(), by_angle);
         order.insert(order.end(), seg[q].begin(), seg[q].end());
-        while (order.size() % 4) order.push_back(-1);
+        while (order.size() % 8) order.push_back(-1);
         if (q == 1) n_rows_major = static_cast<int>(order.size());
     }
     const int n_order = static_cast<int>(order.size());
