@@ -78,8 +78,112 @@ __device__ __forceinline__ float radon_weight(const RadonLine& ln, int t, int j,
     return (v >= 0 && v < N) ? wt : 0.0f;
 }
 
+// A work-group's share of the sweep: W angle slots of the plan's order (one
+// per wave), 64 bins from jb, K slices from z0; the wave's angle tables in LDS.
+struct RadonGroup {
+    int jb, jlast, e0, e_end, a, j, z0, nz;
+    unsigned live;  // which of the W slots hold an angle
+    bool active;    // this wave's slot holds one
+    float cs, sn, cmin, inv, start;
+    const int2* tc;  // (integer, fraction bits) per tile along the line
+    const int2* tl;  // the same for the line's tile
+};
+
+// Fills g_ and the tables (tabs: [W][2][nb] int2 in LDS) and the per-slot
+// strip parameters; false for a group of padding only (the whole
+// work-group returns, before any barrier).
+template <bool ROWS, int W>
+__device__ __forceinline__ bool radon_group(const GeoTables& g, int K, int n_rows, int2* tabs,
+                                            float (*s_par)[3], RadonGroup& r) {
+    const int nb = g.nb, na = g.na, half = g.N / 2;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int jgroups = (g.n + 63) >> 6;
+    r.jb = (blockIdx.x % jgroups) * 64;
+    r.jlast = min(r.jb + 63, g.n - 1);
+    const int grp = blockIdx.x / jgroups;
+    // this launch covers the angles that sweep rows (ROWS) or columns
+    r.e0 = ROWS ? grp * W : g.n_rows_major + grp * W;
+    r.e_end = ROWS ? min(g.n_rows_major, r.e0 + W) : min(g.n_order, r.e0 + W);
+    if (g.order[r.e0] < 0) return false;
+    const int e = r.e0 + wv;
+    // padding entries (-1) and entries past the class are inactive waves
+    r.active = e < r.e_end && g.order[e] >= 0;
+    unsigned live = 0;
+    for (int w = 0; w < W; ++w)
+        if (r.e0 + w < r.e_end && g.order[r.e0 + w] >= 0) live |= 1u << w;
+    r.live = __builtin_amdgcn_readfirstlane(live);
+    r.a = r.active ? g.order[e] : g.order[r.e0];
+    r.j = r.jb + lane;
+    r.z0 = blockIdx.y * K;
+    r.nz = min(K, n_rows - r.z0);
+    int2* tc = tabs + wv * 2 * nb;
+    int2* tl = tc + nb;
+    for (int b = lane; b < nb; b += 64) {
+        const int xi = g.xi[b * na + r.a], yi = g.yi[b * na + r.a];
+        const int xf = __float_as_int(g.xf[b * na + r.a]), yf = __float_as_int(g.yf[b * na + r.a]);
+        tc[b] = ROWS ? make_int2(xi, xf) : make_int2(yi, yf);
+        tl[b] = ROWS ? make_int2(yi, yf) : make_int2(xi, xf);
+    }
+    r.tc = tc;
+    r.tl = tl;
+    r.cs = g.cs[r.a];
+    r.sn = g.sn[r.a];
+    const float cmaj = ROWS ? r.cs : r.sn;  // coefficient of the swept coordinate
+    r.cmin = ROWS ? r.sn : r.cs;            // coefficient of the line coordinate
+    r.inv = 1.0f / cmaj;
+    // left end of the window of voxels whose coordinate can fall in [j-1, j+1)
+    r.start = static_cast<float>(half) - 1.0f / fabsf(cmaj) - 0.01f;
+    if (lane == 0) {
+        s_par[wv][0] = r.cmin;
+        s_par[wv][1] = r.inv;
+        s_par[wv][2] = r.start;
+    }
+    return true;
+}
+
+// Strip of line m: the candidate windows of every live slot's first and last
+// bin (candidate starts are monotone in the bin), one voxel of margin for the
+// FP32 estimates, clipped to the image.  Returns its width (<= 0: no bin of
+// the group reaches the image on this line).
+template <int W>
+__device__ __forceinline__ int radon_strip(const GeoTables& g, const RadonGroup& r, const float (*s_par)[3], int m,
+                                           int& xmin) {
+    const int N = g.N, half = N / 2;
+    int lo = 1 << 30, hi = -(1 << 30);
+    for (int w = 0; w < W; ++w) {
+        if (!((r.live >> w) & 1u)) continue;
+        const float cm = s_par[w][0], iv = s_par[w][1], st = s_par[w][2];
+        const float um = static_cast<float>(m - half) * cm + g.center_f;
+        const int l0 = -coord_floor(-__builtin_fmaf(static_cast<float>(r.jb) - um, iv, st));
+        const int l1 = -coord_floor(-__builtin_fmaf(static_cast<float>(r.jlast) - um, iv, st));
+        lo = min(lo, min(l0, l1));
+        hi = max(hi, max(l0, l1) + kCand - 1);
+    }
+    xmin = max(lo - 1, 0);
+    return min(hi + 1, N - 1) - xmin + 1;
+}
+
+// Whether some line's strip is wider than kRadonStrip (sparse angle sets):
+// such a work-group is summed by k_radon_wide instead.  A barrier (the slot
+// parameters written by radon_group are read here).
+template <int W>
+__device__ __forceinline__ bool radon_group_wide(const GeoTables& g, const RadonGroup& r, const float (*s_par)[3]) {
+    __syncthreads();
+    int wide = 0;
+    for (int m = static_cast<int>(threadIdx.x); m < g.N; m += 64 * W) {
+        int xmin;
+        wide |= radon_strip<W>(g, r, s_par, m, xmin) > kRadonStrip;
+    }
+    return __syncthreads_or(wide) != 0;
+}
+
+// Occupancy the fast kernel's registers allow: 6 waves per SIMD for 16 and
+// 32 slices (80 VGPRs; three work-groups of eight waves per CU), 8 for 8.
+template <int K> constexpr int radon_waves() { return K >= 16 ? 6 : 8; }
+
 template <int K, bool ROWS, int W>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(radon_waves<K>(), radon_waves<K>())))
 k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restrict__ sino) {
     constexpr int S = kRadonStrip;
     constexpr int KQ = K / 4;         // float4 chunks of slices per position
@@ -90,83 +194,30 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
     extern __shared__ __align__(16) unsigned char smem[];
     // per angle slot: coefficient of the line coordinate, 1 / swept coefficient, window start
     __shared__ float s_par[W][3];
-    // strip bounds of NT lines, two chunks in flight: xmin | width << 16 (0: not staged)
+    // strip bounds of NT lines, two chunks in flight: xmin | width << 16 (0: nothing to sum)
     __shared__ unsigned s_bnd[2][NT];
-    const int nb = g.nb, na = g.na, N = g.N, half = N / 2;
+    const int N = g.N, half = N / 2;
     float4* strip = reinterpret_cast<float4*>(smem);                // [2 buffers][KQ][S]
     int2* tabs = reinterpret_cast<int2*>(strip + 2 * KQ * S);       // [W waves][2][nb]
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int jgroups = (g.n + 63) >> 6;
-    const int jb = (blockIdx.x % jgroups) * 64;
-    const int grp = blockIdx.x / jgroups;
-    // this launch covers the angles that sweep rows (ROWS) or columns
-    const int e0 = ROWS ? grp * W : g.n_rows_major + grp * W;
-    const int e_end = ROWS ? min(g.n_rows_major, e0 + W) : min(g.n_order, e0 + W);
-    if (g.order[e0] < 0) return;  // a group of padding only (whole work-group, before any barrier)
-    const int e = e0 + wv;
-    // padding entries (-1) and entries past the class are inactive waves
-    const bool active = e < e_end && g.order[e] >= 0;
-    // which of the work-group's W angle slots hold an angle
-    unsigned live = 0;
-    for (int w = 0; w < W; ++w)
-        if (e0 + w < e_end && g.order[e0 + w] >= 0) live |= 1u << w;
-    live = __builtin_amdgcn_readfirstlane(live);
-    const int a = active ? g.order[e] : g.order[e0];
-    const int j = jb + lane;
-    const int z0 = blockIdx.y * K;
-    const int nz = min(K, n_rows - z0);
-    // tables of this wave's angle: the candidate's tile (along the line) and
-    // the line's tile, integer and fraction parts
-    int2* tc = tabs + wv * 2 * nb;  // (integer, fraction bits) per tile
-    int2* tl = tc + nb;
-    for (int b = lane; b < nb; b += 64) {
-        const int xi = g.xi[b * na + a], yi = g.yi[b * na + a];
-        const int xf = __float_as_int(g.xf[b * na + a]), yf = __float_as_int(g.yf[b * na + a]);
-        tc[b] = ROWS ? make_int2(xi, xf) : make_int2(yi, yf);
-        tl[b] = ROWS ? make_int2(yi, yf) : make_int2(xi, xf);
-    }
-    const float cs = g.cs[a], sn = g.sn[a];
-    const float cmaj = ROWS ? cs : sn;   // coefficient of the swept coordinate
-    const float cmin = ROWS ? sn : cs;   // coefficient of the line coordinate
-    const float inv = 1.0f / cmaj;
-    // left end of the window of voxels whose coordinate can fall in [j-1, j+1)
-    const float start = static_cast<float>(half) - 1.0f / fabsf(cmaj) - 0.01f;
-    if (lane == 0) {
-        s_par[wv][0] = cmin;
-        s_par[wv][1] = inv;
-        s_par[wv][2] = start;
-    }
+    RadonGroup r;
+    if (!radon_group<ROWS, W>(g, K, n_rows, tabs, s_par, r)) return;
+    if (radon_group_wide<W>(g, r, s_par)) return;
+    const int j = r.j, nz = r.nz;
     const int64_t slab = static_cast<int64_t>(N) * N;
     // a line is a row of the volume (ROWS) or of its transpose: contiguous
-    const float* vz = vol + static_cast<int64_t>(z0) * slab;
-    const int jlast = min(jb + 63, g.n - 1);
+    const float* vz = vol + static_cast<int64_t>(r.z0) * slab;
 
-    // Strip bounds of the lines of a chunk (one line per thread): the
-    // candidate windows of every live slot's first and last bin (candidate
-    // starts are monotone in the bin), one voxel of margin for the FP32
-    // estimates.  A line whose strip is wider than S is read from global memory.
     auto line_bounds = [&](int chunk) {
         const int m = chunk * NT + static_cast<int>(threadIdx.x);
         if (m < N) {
-            int lo = 1 << 30, hi = -(1 << 30);
-            for (int w = 0; w < W; ++w) {
-                if (!((live >> w) & 1u)) continue;
-                const float cm = s_par[w][0], iv = s_par[w][1], st = s_par[w][2];
-                const float um = static_cast<float>(m - half) * cm + g.center_f;
-                const int l0 = -coord_floor(-__builtin_fmaf(static_cast<float>(jb) - um, iv, st));
-                const int l1 = -coord_floor(-__builtin_fmaf(static_cast<float>(jlast) - um, iv, st));
-                lo = min(lo, min(l0, l1));
-                hi = max(hi, max(l0, l1) + kCand - 1);
-            }
-            const int xmin = max(lo - 1, 0), xmax = min(hi + 1, N - 1);
-            const int width = xmax - xmin + 1;
+            int xmin;
+            const int width = radon_strip<W>(g, r, s_par, m, xmin);
             s_bnd[chunk & 1][threadIdx.x] =
-                (width > 0 && width <= S) ? static_cast<unsigned>(xmin) | (static_cast<unsigned>(width) << 16) : 0u;
+                width > 0 ? static_cast<unsigned>(xmin) | (static_cast<unsigned>(width) << 16) : 0u;
         }
     };
 
-    // Staging: thread -> (position px of the strip, half pg of the slices).
+    // Staging: thread -> (position px of the strip, share pg of the slices).
     // The next-but-one line is loaded into registers while the current line
     // is summed, and written to the free strip buffer one line later.
     const int px = static_cast<int>(threadIdx.x) & (S - 1);
@@ -199,7 +250,6 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0f;
 
-    __syncthreads();  // s_par, tables
     line_bounds(0);
     if (N > NT) line_bounds(1);
     __syncthreads();
@@ -222,38 +272,32 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
         // bounds of chunk c + 1 at the chunk's first line: its buffer held
         // chunk c - 1, whose last entry was read two lines ago
         if (m % NT == 0 && m > 0 && (m / NT + 1) * NT < N) line_bounds(m / NT + 1);
-        if (active && j < g.n) {
-            const RadonLine ln = radon_line(m, j, half, cmin, inv, start, g.center_f, tl);
+        // a line no bin of the group reaches adds nothing
+        if (r.active && j < g.n && (bm >> 16)) {
+            const RadonLine ln = radon_line(m, j, half, r.cmin, r.inv, r.start, g.center_f, r.tl);
             float wt[kCand];
             int vcs[kCand];
 #pragma unroll
-            for (int t = 0; t < kCand; ++t) wt[t] = radon_weight<ROWS>(ln, t, j, N, cs, sn, tc, vcs[t]);
-            if (bm >> 16) {
-                const int xmin = static_cast<int>(bm & 0xffffu);
-                const float4* sb = strip + buf * KQ * S;
+            for (int t = 0; t < kCand; ++t) wt[t] = radon_weight<ROWS>(ln, t, j, N, r.cs, r.sn, r.tc, vcs[t]);
+            const int xmin = static_cast<int>(bm & 0xffffu);
+            const float4* sb = strip + buf * KQ * S;
+            int xo[kCand];
+#pragma unroll
+            for (int t = 0; t < kCand; ++t) xo[t] = min(max(vcs[t] - xmin, 0), S - 1);
+            // chunk by chunk (few reads in flight); each slice still adds its
+            // candidates in order
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                float4 v[kCand];
+#pragma unroll
+                for (int t = 0; t < kCand; ++t) v[t] = sb[q * S + xo[t]];
 #pragma unroll
                 for (int t = 0; t < kCand; ++t) {
-                    const int xo = min(max(vcs[t] - xmin, 0), S - 1);
-                    const float4* src = sb + xo;
-                    float val[K];
-#pragma unroll
-                    for (int q = 0; q < KQ; ++q) reinterpret_cast<float4*>(val)[q] = src[q * S];
                     // zero weights add exact zeros: no branch
-#pragma unroll
-                    for (int k = 0; k < K; ++k) acc[k] = __builtin_fmaf(wt[t], val[k], acc[k]);
-                }
-            } else {
-#pragma unroll
-                for (int t = 0; t < kCand; ++t) {
-                    if (wt[t] != 0.0f) {
-                        const float* p = vz + static_cast<int64_t>(m) * N + vcs[t];
-#pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            int kk = min(k, nz - 1);
-                            asm volatile("" : "+s"(kk));
-                            acc[k] = __builtin_fmaf(wt[t], p[kk * slab], acc[k]);
-                        }
-                    }
+                    acc[4 * q + 0] = __builtin_fmaf(wt[t], v[t].x, acc[4 * q + 0]);
+                    acc[4 * q + 1] = __builtin_fmaf(wt[t], v[t].y, acc[4 * q + 1]);
+                    acc[4 * q + 2] = __builtin_fmaf(wt[t], v[t].z, acc[4 * q + 2]);
+                    acc[4 * q + 3] = __builtin_fmaf(wt[t], v[t].w, acc[4 * q + 3]);
                 }
             }
         }
@@ -261,11 +305,55 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
         bm = bm1;
         bm1 = bm2;
     }
-    if (active && j < g.n) {
+    if (r.active && j < g.n) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (k < nz) sino[(static_cast<int64_t>(z0 + k) * na + a) * g.n + j] = acc[k];
+            if (k < nz) sino[(static_cast<int64_t>(r.z0 + k) * g.na + r.a) * g.n + j] = acc[k];
     }
+}
+
+// The work-groups k_radon leaves (a strip wider than kRadonStrip on some
+// line): each candidate is read from global memory, with the same arithmetic
+// and order (zero weights skipped: they would add exact zeros).
+template <int K, bool ROWS, int W>
+__global__ void __launch_bounds__(64 * W) k_radon_wide(GeoTables g, const float* __restrict__ vol, int n_rows,
+                                                      float* __restrict__ sino) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float s_par[W][3];
+    int2* tabs = reinterpret_cast<int2*>(smem);  // [W waves][2][nb]
+    RadonGroup r;
+    if (!radon_group<ROWS, W>(g, K, n_rows, tabs, s_par, r)) return;
+    if (!radon_group_wide<W>(g, r, s_par)) return;
+    const int N = g.N, half = N / 2, j = r.j, nz = r.nz;
+    const int64_t slab = static_cast<int64_t>(N) * N;
+    const float* vz = vol + static_cast<int64_t>(r.z0) * slab;
+    if (!r.active || j >= g.n) return;  // no barrier below
+    float acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0f;
+    for (int m = 0; m < N; ++m) {
+        const RadonLine ln = radon_line(m, j, half, r.cmin, r.inv, r.start, g.center_f, r.tl);
+#pragma unroll
+        for (int t = 0; t < kCand; ++t) {
+            int vc;
+            const float wt = radon_weight<ROWS>(ln, t, j, N, r.cs, r.sn, r.tc, vc);
+            if (wt != 0.0f) {
+                // byte offset of the voxel in its slice, a scalar base per slice
+                const uint32_t off = (static_cast<uint32_t>(m) * static_cast<uint32_t>(N) +
+                                      static_cast<uint32_t>(vc)) * 4u;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    int kk = min(k, nz - 1);
+                    asm volatile("" : "+s"(kk));
+                    const char* sp = reinterpret_cast<const char*>(vz + static_cast<int64_t>(kk) * slab);
+                    acc[k] = __builtin_fmaf(wt, *reinterpret_cast<const float*>(sp + off), acc[k]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (k < nz) sino[(static_cast<int64_t>(r.z0 + k) * g.na + r.a) * g.n + j] = acc[k];
 }
 
 }  // namespace
@@ -298,14 +386,23 @@ hipError_t launch_radon_k(const GeoTables& g, const float* vol, int n_rows, floa
     const int jgroups = (g.n + 63) / 64;
     const int groups = ROWS ? (g.n_rows_major + W - 1) / W : (g.n_order - g.n_rows_major + W - 1) / W;
     if (groups == 0) return hipSuccess;
-    const size_t lds = sizeof(float) * 2 * K * kRadonStrip + sizeof(int2) * 2 * W * static_cast<size_t>(g.nb);
+    const size_t tabs = sizeof(int2) * 2 * W * static_cast<size_t>(g.nb);
+    const size_t lds = sizeof(float) * 2 * K * kRadonStrip + tabs;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon<K, ROWS, W>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
         if (e != hipSuccess) return e;
     }
+    if (tabs > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_radon_wide<K, ROWS, W>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(tabs));
+        if (e != hipSuccess) return e;
+    }
     const dim3 grid(static_cast<unsigned>(jgroups * groups), static_cast<unsigned>((n_rows + K - 1) / K));
     hipLaunchKernelGGL((k_radon<K, ROWS, W>), grid, dim3(64 * W), lds, st, g, vol, n_rows, sino);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_radon_wide<K, ROWS, W>), grid, dim3(64 * W), tabs, st, g, vol, n_rows, sino);
     return hipGetLastError();
 }
 
