@@ -34,7 +34,11 @@ namespace {
 // Cost on gfx950: besides the 3 FMAs per update, the candidate arithmetic is
 // mostly half-rate VALU (conversions, fract, compare/select), so 32 slices
 // share it; the strip loads use one scalar base per slice, fixed for the
-// kernel, and a 32-bit vector offset (no per-load address arithmetic).
+// kernel, and a 32-bit vector offset (no per-load address arithmetic).  The
+// LDS reads of the candidates bound the kernel: the third candidate weighs
+// only where the window holds three voxels (a quarter of the lanes at
+// typical angles), so it is read under that lane mask and the other lanes
+// make no LDS request.
 constexpr int kCand = 3;
 constexpr int kRadonStrip = 128;
 
@@ -285,19 +289,30 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
 #pragma unroll
             for (int t = 0; t < kCand; ++t) xo[t] = min(max(vcs[t] - xmin, 0), S - 1);
             // chunk by chunk (few reads in flight); each slice still adds its
-            // candidates in order
+            // candidates in order: the first two here, the third below
 #pragma unroll
             for (int q = 0; q < KQ; ++q) {
-                float4 v[kCand];
+                float4 v[2];
 #pragma unroll
-                for (int t = 0; t < kCand; ++t) v[t] = sb[q * S + xo[t]];
+                for (int t = 0; t < 2; ++t) v[t] = sb[q * S + xo[t]];
 #pragma unroll
-                for (int t = 0; t < kCand; ++t) {
-                    // zero weights add exact zeros: no branch
+                for (int t = 0; t < 2; ++t) {
                     acc[4 * q + 0] = __builtin_fmaf(wt[t], v[t].x, acc[4 * q + 0]);
                     acc[4 * q + 1] = __builtin_fmaf(wt[t], v[t].y, acc[4 * q + 1]);
                     acc[4 * q + 2] = __builtin_fmaf(wt[t], v[t].z, acc[4 * q + 2]);
                     acc[4 * q + 3] = __builtin_fmaf(wt[t], v[t].w, acc[4 * q + 3]);
+                }
+            }
+            // the third candidate weighs only where the window holds three
+            // voxels: the other lanes read nothing
+            if (wt[2] != 0.0f) {
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) {
+                    const float4 v = sb[q * S + xo[2]];
+                    acc[4 * q + 0] = __builtin_fmaf(wt[2], v.x, acc[4 * q + 0]);
+                    acc[4 * q + 1] = __builtin_fmaf(wt[2], v.y, acc[4 * q + 1]);
+                    acc[4 * q + 2] = __builtin_fmaf(wt[2], v.z, acc[4 * q + 2]);
+                    acc[4 * q + 3] = __builtin_fmaf(wt[2], v.w, acc[4 * q + 3]);
                 }
             }
         }
