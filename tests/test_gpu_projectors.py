@@ -205,7 +205,7 @@ def test_radon_mass_conservation(tp):
 
 
 def test_radon_sparse_angles_use_global_fallback(tp):
-    # 8 angles over 180 degrees on a 512^2 image: the strip a work-group's 4
+    # 8 angles over 180 degrees on a 512^2 image: the strip a work-group's
     # angles cross is far wider than the LDS buffer, so candidates are read
     # from global memory; results must match the oracle all the same
     N = n = 512
@@ -216,6 +216,26 @@ def test_radon_sparse_angles_use_global_fallback(tp):
     note("radon sparse angles (global fallback)")
     got = to_host(tp.radon(plan, to_dev(x)))
     assert_parity(got, oracle.radon(x.astype(np.float64), ang, n / 2 + 0.3, n), "f32", label="radon sparse")
+
+
+def test_radon_mixed_narrow_and_wide_strips(tp):
+    # 40 angles within 0.1 rad (narrow strips, summed through LDS) and 8
+    # spread over 2 rad (strips wider than the LDS buffer, summed from global
+    # memory) in one plan, ragged bins (330 = 5 x 64 + 10): both kernels of one
+    # call write their own work-groups.  20 slices use groups of 8 angles, 3
+    # slices groups of 4; the slices both calls share are bitwise equal.
+    N, n = 300, 330
+    rng = np.random.default_rng(37)
+    ang = np.concatenate([0.2 + 0.1 * rng.random(40), np.linspace(0.9, 2.9, 8)])
+    c = 161.3
+    plan = tp.Plan(ang, n, c, N)
+    x = rng.standard_normal((20, N, N)).astype(np.float32)
+    note("radon mixed narrow/wide strips, 20 slices")
+    got = to_host(tp.radon(plan, to_dev(x)))
+    assert_parity(got, oracle.radon(x.astype(np.float64), ang, c, n), "f32", label="radon mixed strips")
+    note("radon mixed narrow/wide strips, 3 slices")
+    got3 = to_host(tp.radon(plan, to_dev(x[:3])))
+    assert np.array_equal(got3, got[:3])
 
 
 def test_unsorted_nonuniform_angles(tp):
