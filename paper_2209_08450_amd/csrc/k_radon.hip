@@ -424,10 +424,21 @@ hipError_t launch_radon_k(const GeoTables& g, const float* vol, int n_rows, floa
 template <int K>
 hipError_t launch_radon_both(const GeoTables& g, const float* vol, const float* volT, int n_rows, float* sino,
                              hipStream_t st) {
-    constexpr int W8 = K >= 16 ? 8 : 4;
-    hipError_t e = launch_radon_k<K, true, W8>(g, vol, n_rows, sino, st);
+    // Eight angles per strip unless their tile tables (16 x nb int2) would
+    // take the work-group past the 160 KB of LDS (slices above ~30976 voxels
+    // wide); both kernels of an axis must group the angles alike.
+    if constexpr (K >= 16) {
+        const size_t lds8 = sizeof(float) * 2 * K * kRadonStrip + sizeof(int2) * 2 * 8 * static_cast<size_t>(g.nb) +
+                            sizeof(float) * 3 * 8 + sizeof(unsigned) * 2 * 64 * 8;
+        if (lds8 <= 160 * 1024) {
+            hipError_t e = launch_radon_k<K, true, 8>(g, vol, n_rows, sino, st);
+            if (e != hipSuccess) return e;
+            return launch_radon_k<K, false, 8>(g, volT, n_rows, sino, st);
+        }
+    }
+    hipError_t e = launch_radon_k<K, true, 4>(g, vol, n_rows, sino, st);
     if (e != hipSuccess) return e;
-    return launch_radon_k<K, false, W8>(g, volT, n_rows, sino, st);
+    return launch_radon_k<K, false, 4>(g, volT, n_rows, sino, st);
 }
 
 }  // namespace
@@ -440,7 +451,8 @@ size_t radon_workspace_bytes(const GeoTables& g, int n_rows) {
 // volume, so their lines are contiguous too.  32 slices per work-group
 // amortise each candidate's coordinate; smaller chunks use 16 or 8.  Eight
 // angles share a strip (half the staging per update of four) when a thread
-// then still stages whole float4 chunks (16 or more slices).
+// then still stages whole float4 chunks (16 or more slices) and their tables
+// fit the LDS.
 hipError_t launch_radon(const GeoTables& g, const float* vol, int n_rows, float* sino, float* workspace,
                         hipStream_t st) {
     const float* volT = vol;

@@ -238,6 +238,45 @@ def test_radon_mixed_narrow_and_wide_strips(tp):
     assert np.array_equal(got3, got[:3])
 
 
+def test_radon_widest_slices_group_four_angles(tp):
+    # 32000-voxel slices: with 32-slice groups the tile tables of 8 angles
+    # would take a work-group past the 160 KB of LDS, so the projector groups
+    # 4 angles there.  17 slices of a sparse volume (70 GB; every angle sweeps
+    # rows, so no transposed copy); 4 angles within 1.5 mrad (one group whose
+    # strips fit LDS) and 2 angles 0.05 rad apart (one group of wide strips,
+    # read from global memory).  Each voxel's weights are the FP64 oracle's
+    # system-matrix entries: its backprojection of a one-hot sinogram at that
+    # voxel (scale 1, the exact transpose).
+    import torch
+    N, n = 32000, 8192  # the detector is limited by the filter's pad length
+    rows = 17
+    ang = np.array([0.1, 0.1005, 0.101, 0.1015, 0.5, 0.55])
+    c = n / 2 + 0.25
+    plan = tp.Plan(ang, n, c, N)
+    assert plan.radon_workspace_bytes(rows) == 0
+    pts = [(0, 16000, 16000, 1.0), (3, 13300, 18700, 2.5), (16, 18500, 14100, -1.5), (9, 17000, 15500, 0.75)]
+    note("radon 17 x 32000^2 sparse, 6 angles x 8192 bins")
+    torch.cuda.empty_cache()
+    x = torch.zeros((rows, N, N), dtype=torch.float32, device="cuda")
+    for z, iy, ix, v in pts:
+        x[z, iy, ix] = v
+    got = tp.radon(plan, x).cpu().numpy().astype(np.float64)
+    del x
+    torch.cuda.empty_cache()
+    want = np.zeros((rows, len(ang), n))
+    for z, iy, ix, v in pts:
+        for a, t in enumerate(ang):
+            s = (ix - N // 2) * math.cos(t) + (iy - N // 2) * math.sin(t) + c
+            for j in range(math.floor(s) - 1, math.floor(s) + 3):
+                if 0 <= j < n:
+                    q = np.zeros((len(ang), n))
+                    q[a, j] = 1.0
+                    want[z, a, j] += v * oracle.backproject_points(q, ang, c, N, [ix], [iy], scale=1.0)[0]
+    assert np.count_nonzero(want) >= 2 * len(ang) * len(pts) - 4
+    # FP32 weights from the split coordinate: a few ulp of the weights
+    assert np.max(np.abs(got - want)) < 1e-5 * 2.5
+
+
 def test_unsorted_nonuniform_angles(tp):
     # arbitrary order, full circle, repeated angle: the plan's grouping of
     # angles by sweep axis must not change either projector's results
