@@ -28,9 +28,11 @@ namespace {
 // words), so each voxel is fetched once per work-group instead of once per
 // bin and angle.  The strip of line m + 2 is loaded into registers while line
 // m is summed and written to the free buffer one line later: one barrier per
-// line.  A strip wider than kRadonStrip (sparse angle sets) is read from
-// global memory instead, with the same arithmetic and order.  No atomics:
-// every output is summed by one lane, lines ascending, candidates ascending.
+// line.  A work-group with a strip wider than kRadonStrip on some line
+// (sparse angle sets) is summed instead by k_radon_wide, which reads every
+// candidate from global memory with the same arithmetic and order.  No
+// atomics: every output is summed by one lane, lines ascending, candidates
+// ascending.
 // Cost on gfx950: besides the 3 FMAs per update, the candidate arithmetic is
 // mostly half-rate VALU (conversions, fract, compare/select), so 32 slices
 // share it; the strip loads use one scalar base per slice, fixed for the
@@ -93,8 +95,8 @@ struct RadonGroup {
     const int2* tl;  // the same for the line's tile
 };
 
-// Fills g_ and the tables (tabs: [W][2][nb] int2 in LDS) and the per-slot
-// strip parameters; false for a group of padding only (the whole
+// Fills r, this wave's angle tables (tabs: [W][2][nb] int2 in LDS) and its
+// slot's strip parameters; false for a group of padding only (the whole
 // work-group returns, before any barrier).
 template <bool ROWS, int W>
 __device__ __forceinline__ bool radon_group(const GeoTables& g, int K, int n_rows, int2* tabs,
