@@ -71,7 +71,8 @@ template <bool ROWS>
 __device__ __forceinline__ float radon_weight(const RadonLine& ln, int t, int j, int N, float cs, float sn,
                                               const int2* tc, int& vc) {
     const int v = ln.lo + t;
-    vc = min(max(v, 0), N - 1);
+    // clamp to [0, N - 1] in one instruction (the compiler emits max + min)
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(vc) : "v"(v), "s"(N - 1));
     const int bv = vc >> 5;
     const float dv = static_cast<float>(vc & 31);
     const int2 e = tc[bv];
@@ -209,6 +210,9 @@ k_radon(GeoTables g, const float* __restrict__ vol, int n_rows, float* __restric
     if (!radon_group<ROWS, W>(g, K, n_rows, tabs, s_par, r)) return;
     if (radon_group_wide<W>(g, r, s_par)) return;
     const int j = r.j, nz = r.nz;
+    // the angle's coefficients in vector registers: an FMA with a scalar
+    // operand issues at half rate
+    asm volatile("" : "+v"(r.cs), "+v"(r.sn), "+v"(r.cmin), "+v"(r.inv), "+v"(r.start));
     const int64_t slab = static_cast<int64_t>(N) * N;
     // a line is a row of the volume (ROWS) or of its transpose: contiguous
     const float* vz = vol + static_cast<int64_t>(r.z0) * slab;
