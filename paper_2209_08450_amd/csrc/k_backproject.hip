@@ -115,8 +115,16 @@ __device__ __forceinline__ void tile_of(int wg, int nb, int& bx, int& by) {
 // better padded.)
 constexpr int bin_pitch(int bin) { return (bin >= 64 && (bin / 16) % 2 == 0) ? bin + 16 : bin; }
 
+// Lowest occupancy the register allocator must keep for the FP32-arithmetic
+// kernel.  16 slices x 8 angles take 30.8 KB of LDS, room for 5 work-groups
+// (5 waves per SIMD) per CU; the allocator alone gives that tile 98 registers
+// (4 waves), and bounded to 5 waves it needs no spill.  Larger tiles are held
+// to fewer work-groups by their LDS, smaller ones use few registers: they keep
+// the default.
+constexpr int bp_min_waves(int K, int A) { return (K == 16 && A == 8) ? 5 : 1; }
+
 template <typename T, int K, int A>
-__global__ void __launch_bounds__(kBpThreads)
+__global__ void __launch_bounds__(kBpThreads) __attribute__((amdgpu_waves_per_eu(bp_min_waves(K, A))))
 k_backproject(GeoTables g, const T* __restrict__ filt, int n_rows, float scale, float* __restrict__ vol,
               int accumulate) {
     using U = typename Lds<T>::U;
