@@ -70,6 +70,8 @@ def parse():
                     help="instead: the host-to-host three-stream pipeline over uneven chunks "
                          "(defaults become 3000 angles x 2048 rows x 4096 columns, FP16 storage)")
     ap.add_argument("--pattern", default="32,64,128", help="chunk sizes of the pipeline mode")
+    ap.add_argument("--buffers", type=int, default=3,
+                    help="pipeline: pinned and device buffers per direction (2: the paper's double buffering)")
     ap.add_argument("--out-dtype", default="f32", choices=("f32", "f16"),
                     help="pipeline mode: precision of the output slices (f16: the 16-bit mode, FP16 storage only)")
     ap.add_argument("--io-dir", default="",
@@ -496,7 +498,8 @@ def main():
         if lamino is None:
             del scan, vol
             torch.cuda.empty_cache()
-        pipe = pipeline_run(dev, 4096, 3000, 2048, "f16", (32, 64, 128), "linear", args.filter, "", log)
+        pipe = pipeline_run(dev, 4096, 3000, 2048, "f16", (32, 64, 128), "linear", args.filter, "", log,
+                            buffers=args.buffers)
         pipe = {k: pipe[k] for k in ("value", "unit", "config", "s_host_to_host", "s_compute_only_resident",
                                       "compute_over_host_to_host", "h2d_GB", "d2h_GB", "vs_fp64_oracle_sampled",
                                       "bitwise_equal_to_resident_compute")}
@@ -1125,7 +1128,7 @@ def cfg5_check_rows(chunks, rows: int, n_even: int = 10):
     return sorted(set(zs))
 
 
-def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, points=256, out_dtype="f32"):
+def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, points=256, out_dtype="f32", buffers=3):
     """Host-pinned to host-pinned reconstruction through the three-stream
     pipeline (copy-in, compute, copy-out) over uneven chunks, with per-chunk
     graphs and the autotuned backprojection tiling; the same chunks are also
@@ -1246,7 +1249,8 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         io = paths
 
     pl = pipeline.ChunkPipeline(plan, max_rows=max(pattern), n_dark=dark_h.shape[0], n_flat=flat_h.shape[0],
-                                storage=st, use_graphs=True, kind=kind, method=method, out_dtype=out_dtype)
+                                storage=st, use_graphs=True, kind=kind, method=method, out_dtype=out_dtype,
+                                buffers=buffers)
     pl.prepare(chunks)
     log(f"pipeline: {len(chunks)} chunks, {pl.stats.graphs_captured} graphs; running")
     t_run = time.perf_counter()
@@ -1291,7 +1295,7 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
                                f"{FILTER_NAMES[kind]}, "
                                + ("Fourier-domain backprojection" if fourier else "linear-interpolation backprojection"),
                    "storage": None if fourier else st, "slices_out": out_dtype,
-                   "chunks": list(pattern), "n_chunks": len(chunks),
+                   "chunks": list(pattern), "n_chunks": len(chunks), "buffers": buffers,
                    "graphs": stats.graphs_captured, "bp_tuning": None if fourier else [k, a]},
         "s_host_to_host" if not io else "s_file_to_file": round(stats.seconds, 3),
         "s_compute_only_resident": round(t_compute, 3),
@@ -1328,7 +1332,7 @@ def main_pipeline(args):
     st = args.storage.split(",")[0] if args.storage != "f16,f32,bf16" else "f16"
     pattern = tuple(int(v) for v in args.pattern.split(","))
     out = pipeline_run(dev, n, na, args.rows, st, pattern, args.method, args.filter, args.io_dir, log,
-                       out_dtype=args.out_dtype)
+                       out_dtype=args.out_dtype, buffers=args.buffers)
     print(json.dumps(out), flush=True)
 
 

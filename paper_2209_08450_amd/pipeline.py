@@ -1,17 +1,21 @@
 """Asynchronous chunk pipeline (paper Section 2.3).
 
 Chunks of detector rows (uneven sizes allowed) flow host -> device -> host
-through three HIP streams: copy-in, compute, copy-out.  Two pinned host
-buffers and two device buffers on each side let the copy-in of chunk k+1 and
-the copy-out of chunk k-1 overlap the reconstruction of chunk k, as in the
-paper's scheme; instead of a full synchronisation after every chunk, events
-order exactly the hazards that exist:
+through three HIP streams: copy-in, compute, copy-out.  B pinned host
+buffers and B device buffers on each side (B = 2 is the paper's double
+buffering) let the copy-in of chunk k+1 and the copy-out of chunk k-1 overlap
+the reconstruction of chunk k; instead of a full synchronisation after every
+chunk, events order exactly the hazards that exist (chunk k uses buffer k%B):
 
-  copy-in(k)   waits compute(k-2)   (device input buffer k%2 free)
-  compute(k)   waits copy-in(k) and copy-out(k-2) (device output buffer free)
-  copy-out(k)  waits compute(k) and the sink's release of chunk k-2's pinned
+  copy-in(k)   waits compute(k-B)   (device input buffer free)
+  compute(k)   waits copy-in(k) and copy-out(k-B) (device output buffer free)
+  copy-out(k)  waits compute(k) and the sink's release of chunk k-B's pinned
                output buffer
-  host fill(k) waits copy-in(k-2)   (pinned input buffer free)
+  host fill(k) waits copy-in(k-B)   (pinned input buffer free)
+
+With uneven chunks a third buffer pays: after a large chunk, the next two
+small ones would otherwise wait for its copy-out (and the host fill of the
+chunk after them behind it), leaving the GPU idle.
 
 Each chunk's three kernels (dark/flat means, fused normalise + filter,
 backprojection) are captured once per (chunk size, buffer) as a HIP graph and
@@ -100,7 +104,7 @@ class PipelineStats:
 
 
 class ChunkPipeline:
-    """Three-stream, double-buffered FBP over row chunks.
+    """Three-stream, multi-buffered FBP over row chunks.
 
     plan: tp.Plan of the scan geometry; max_rows: largest chunk; n_dark/n_flat:
     frames per chunk; storage: 'f16' / 'f32' / 'bf16' for the filtered rows;
@@ -108,13 +112,18 @@ class ChunkPipeline:
     device and pinned buffers with NaN before each use (a missing dependency
     then shows as NaN in the result).  method: 'linear' (tp_fbp_chunk) or
     'fourier' (tp_fourier_fbp_chunk; storage is then unused and half_width
-    sets its Gaussian's truncation radius).
+    sets its Gaussian's truncation radius).  buffers: pinned and device buffers
+    per direction (each holds one chunk of max_rows; 2 is the paper's double
+    buffering, the default 3 keeps the GPU busy behind uneven chunks).
     """
 
     def __init__(self, plan: "tp.Plan", max_rows: int, n_dark: int, n_flat: int, storage="f16",
                  use_graphs: bool = True, poison: bool = False, device=None, kind="ramp", method="linear",
-                 half_width: int = 0, out_dtype="f32"):
+                 half_width: int = 0, out_dtype="f32", buffers: int = 3):
         self.plan = plan
+        if int(buffers) < 2:
+            raise ValueError(f"buffers must be at least 2, not {buffers}")
+        self.nbuf = nb = int(buffers)
         self.kind = kind
         tp.filter_code(kind)  # reject unknown names early
         if method not in ("linear", "fourier"):
@@ -145,14 +154,14 @@ class ChunkPipeline:
         def dev(numel, dtype):
             return torch.empty(numel, dtype=dtype, device=self.device)
 
-        self.pin_in = [pinned(na * r * n, i16) for _ in range(2)]
-        self.pin_dark = [pinned(self.n_dark * r * n, i16) for _ in range(2)]
-        self.pin_flat = [pinned(self.n_flat * r * n, i16) for _ in range(2)]
-        self.pin_out = [pinned(r * N * N, odt) for _ in range(2)]
-        self.dev_in = [dev(na * r * n, i16) for _ in range(2)]
-        self.dev_dark = [dev(self.n_dark * r * n, i16) for _ in range(2)]
-        self.dev_flat = [dev(self.n_flat * r * n, i16) for _ in range(2)]
-        self.dev_out = [dev(r * N * N, odt) for _ in range(2)]
+        self.pin_in = [pinned(na * r * n, i16) for _ in range(nb)]
+        self.pin_dark = [pinned(self.n_dark * r * n, i16) for _ in range(nb)]
+        self.pin_flat = [pinned(self.n_flat * r * n, i16) for _ in range(nb)]
+        self.pin_out = [pinned(r * N * N, odt) for _ in range(nb)]
+        self.dev_in = [dev(na * r * n, i16) for _ in range(nb)]
+        self.dev_dark = [dev(self.n_dark * r * n, i16) for _ in range(nb)]
+        self.dev_flat = [dev(self.n_flat * r * n, i16) for _ in range(nb)]
+        self.dev_out = [dev(r * N * N, odt) for _ in range(nb)]
         ws_bytes = plan.fourier_workspace_bytes(r) if method == "fourier" else plan.fbp_workspace_bytes(r, storage)
         self.ws = dev(max(256, ws_bytes), torch.uint8)
         # streams at default priority
@@ -192,7 +201,7 @@ class ChunkPipeline:
         """
         if not self.use_graphs:
             return
-        for b, c in sorted({(k % 2, z1 - z0) for k, (z0, z1) in enumerate(chunks)}):
+        for b, c in sorted({(k % self.nbuf, z1 - z0) for k, (z0, z1) in enumerate(chunks)}):
             if (b, c) in self._graphs:
                 continue
             v = self._views(b, c)
@@ -224,10 +233,11 @@ class ChunkPipeline:
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
         ev = lambda: torch.cuda.Event()  # noqa: E731
-        h2d_done = [None, None]
-        comp_done = [None, None]
-        d2h_done = [None, None]
-        out_free = [threading.Event(), threading.Event()]
+        nb = self.nbuf
+        h2d_done = [None] * nb
+        comp_done = [None] * nb
+        d2h_done = [None] * nb
+        out_free = [threading.Event() for _ in range(nb)]
         for e in out_free:
             e.set()
         work = queue.Queue()
@@ -253,7 +263,7 @@ class ChunkPipeline:
             for k, (z0, z1) in enumerate(chunks):
                 if errors:
                     break
-                b, c = k % 2, z1 - z0
+                b, c = k % nb, z1 - z0
                 v = self._views(b, c)
                 # host fill of pinned input b: its previous copy-in must be done
                 if h2d_done[b] is not None:

@@ -41,21 +41,25 @@ def _sink(result):
     return put
 
 
-@pytest.mark.parametrize("graphs,poison,storage", [(True, False, "f16"), (False, True, "f16"),
-                                                   (True, True, "f32"), (True, False, "bf16")])
-def test_pipeline_bitwise_equals_monolithic(env, graphs, poison, storage):
+@pytest.mark.parametrize("graphs,poison,storage,buffers", [(True, False, "f16", 2), (False, True, "f16", 2),
+                                                           (True, True, "f32", 2), (True, False, "bf16", 2),
+                                                           (True, True, "f16", 3), (False, True, "f32", 4)])
+def test_pipeline_bitwise_equals_monolithic(env, graphs, poison, storage, buffers):
+    # poisoned buffers (NaN before each use) expose a missing dependency; with
+    # more buffers the hazards move to chunk k - buffers
     tp, pipeline, _, s = env
     plan = tp.Plan(s.angles, 128, s.center)
     want = _monolithic(tp, plan, s, storage)
     chunks = pipeline.uneven_chunks(100, (7, 13, 32))
     pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, storage=storage, use_graphs=graphs,
-                                poison=poison)
+                                poison=poison, buffers=buffers)
     got = np.full((100, 128, 128), np.nan, np.float32)
-    note(f"pipeline graphs={graphs} poison={poison} {storage}")
+    note(f"pipeline graphs={graphs} poison={poison} {storage} buffers={buffers}")
     st = pl.run(chunks, _source(s), _sink(got))
     assert st.chunks == len(chunks) and st.rows == 100
     if graphs:
         assert st.graph_replays == len(chunks)
+        assert st.graphs_captured == len({(k % buffers, z1 - z0) for k, (z0, z1) in enumerate(chunks)})
     assert np.array_equal(got, want)
 
 
@@ -190,7 +194,7 @@ def test_graph_replays_repeat_with_eager_work_between(env):
         # eager work and synchronisation of the program between replays
         _monolithic(tp, plan, s, "f32")
         torch.cuda.synchronize()
-    assert pl.stats.graphs_captured == len({(k % 2, z1 - z0) for k, (z0, z1) in enumerate(chunks)})
+    assert pl.stats.graphs_captured == len({(k % pl.nbuf, z1 - z0) for k, (z0, z1) in enumerate(chunks)})
 
 
 def test_source_failure_names_chunk_and_pipeline_recovers(env):

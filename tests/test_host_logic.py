@@ -22,6 +22,15 @@ def test_uneven_chunks_cover_rows_once():
         pipeline.uneven_chunks(10, (0,))
 
 
+def test_pipeline_needs_two_buffers():
+    # fewer than two buffers per direction cannot overlap anything: refused
+    # before any plan or device memory is touched
+    pipeline = pytest.importorskip("paper_2209_08450_amd.pipeline")
+    for bad in (0, 1):
+        with pytest.raises(ValueError, match="buffers"):
+            pipeline.ChunkPipeline(None, max_rows=8, n_dark=1, n_flat=1, buffers=bad)
+
+
 def test_tuner_legal_candidates():
     c16 = tune.candidates("f16")
     c32 = tune.candidates("f32")
