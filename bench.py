@@ -77,9 +77,10 @@ def parse():
     ap.add_argument("--io-dir", default="",
                     help="pipeline mode: read the scan from and write the volume to raw files in this directory "
                          "(native reader/writer threads; the files are written first and deleted afterwards)")
-    ap.add_argument("--method", default="linear", choices=("linear", "fourier"),
-                    help="backprojector of the pipeline mode: linear interpolation (tp_fbp_chunk) or the "
-                         "Fourier-domain method (tp_fourier_fbp_chunk)")
+    ap.add_argument("--method", default="linear", choices=("linear", "fourier", "lprec"),
+                    help="backprojector of the pipeline mode: linear interpolation (tp_fbp_chunk), the "
+                         "Fourier-domain method (tp_fourier_fbp_chunk) or the log-polar method "
+                         "(tp_lprec_fbp_chunk; 2048^3 in 32-row chunks by default)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the pipeline section (3000 angles x 2048 rows x 4096 columns host to host, chunks "
                          "32/64/128, FP16 storage)")
@@ -1152,8 +1153,12 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
     torch.cuda.synchronize()
     plan = tp.Plan(scan.angles, n, center)
     fourier = method == "fourier"
+    lprec = method == "lprec"
     if fourier:
         plan.fourier_prepare(kind, 0)
+        k = a = None
+    elif lprec:
+        plan.lprec_prepare(kind)
         k = a = None
     else:
         k, a = tune.tune_backproject(plan, st, rows=16, use_cache=False)
@@ -1167,6 +1172,9 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         if fourier:
             tp.fourier_fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], out=out,
                                  workspace=ws, kind=kind)
+        elif lprec:
+            tp.lprec_fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], out=out,
+                               workspace=ws, kind=kind)
         else:
             tp.fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], st, out=out,
                          workspace=ws, kind=kind, out_dtype=out_dtype)
@@ -1175,7 +1183,12 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
     out_bytes = 2 if out_dtype == "f16" else 4
     # compute only, inputs resident on the device, same chunks
     vol_c = torch.empty((max(pattern), n, n), dtype=odt, device=dev)
-    ws_bytes = plan.fourier_workspace_bytes(max(pattern)) if fourier else plan.fbp_workspace_bytes(max(pattern), st)
+    if fourier:
+        ws_bytes = plan.fourier_workspace_bytes(max(pattern))
+    elif lprec:
+        ws_bytes = plan.lprec_workspace_bytes(max(pattern))
+    else:
+        ws_bytes = plan.fbp_workspace_bytes(max(pattern), st)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     resident = {}
     for z0, z1 in chunks[:3]:
@@ -1267,12 +1280,14 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         del vol_file
     bitwise = all(np.array_equal(kept[z], resident[z]) for z in early_z)
     rng = np.random.default_rng(0)
-    npts = min(points, 64) if fourier else points  # the Fourier oracle sums L + 1 terms per voxel and angle
+    # the Fourier-domain and log-polar methods are checked against the exact sum of
+    # trigonometric interpolants, which sums L + 1 terms per voxel and angle
+    npts = min(points, 64) if (fourier or lprec) else points
     per_slice, g_all, w_all = [], [], []
     log(f"oracle at {npts} voxels of each of {len(check_z)} slices")
     for z in check_z:
         ix, iy = rng.integers(0, n, npts), rng.integers(0, n, npts)
-        ref = oracle.fourier_fbp_points if fourier else oracle.fbp_points
+        ref = oracle.fourier_fbp_points if (fourier or lprec) else oracle.fbp_points
         want = ref(proj_h[:, z].view(np.uint16), dark_h[:, z].view(np.uint16), flat_h[:, z].view(np.uint16),
                    plan.angles, center, n, ix, iy, kind=kind)
         got = kept[z][iy, ix].astype(np.float64)
@@ -1293,10 +1308,11 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
         "data": "synthetic",
         "config": {"workload": f"fbp {n}x{n}x{rows} from {na} angles x {rows} rows x {n} cols 12-bit ellipsoid scan, "
                                f"{FILTER_NAMES[kind]}, "
-                               + ("Fourier-domain backprojection" if fourier else "linear-interpolation backprojection"),
-                   "storage": None if fourier else st, "slices_out": out_dtype,
+                               + ("Fourier-domain backprojection" if fourier else
+                                  "log-polar backprojection" if lprec else "linear-interpolation backprojection"),
+                   "storage": None if (fourier or lprec) else st, "slices_out": out_dtype,
                    "chunks": list(pattern), "n_chunks": len(chunks), "buffers": buffers,
-                   "graphs": stats.graphs_captured, "bp_tuning": None if fourier else [k, a]},
+                   "graphs": stats.graphs_captured, "bp_tuning": None if (fourier or lprec) else [k, a]},
         "s_host_to_host" if not io else "s_file_to_file": round(stats.seconds, 3),
         "s_compute_only_resident": round(t_compute, 3),
         "compute_over_host_to_host": round(t_compute / stats.seconds, 3),
@@ -1327,10 +1343,15 @@ def main_pipeline(args):
     torch.cuda.set_device(dev)
     # defaults: 3000 angles x 4096 columns host to host; with --io-dir the 2048^3
     # scan (its files and the volume take ~52 GB of storage)
-    n = args.n if (args.n != 2048 or args.io_dir) else 4096
-    na = args.angles if (args.angles != 2048 or args.io_dir) else 3000
+    # (the log-polar method: 2048^3 in 32-row chunks, its grid at 4096 columns
+    # from 3000 angles exceeds the angle transform's length)
+    lp = args.method == "lprec"
+    n = args.n if (args.n != 2048 or args.io_dir or lp) else 4096
+    na = args.angles if (args.angles != 2048 or args.io_dir or lp) else 3000
     st = args.storage.split(",")[0] if args.storage != "f16,f32,bf16" else "f16"
     pattern = tuple(int(v) for v in args.pattern.split(","))
+    if lp and args.pattern == "32,64,128":
+        pattern = (32,)
     out = pipeline_run(dev, n, na, args.rows, st, pattern, args.method, args.filter, args.io_dir, log,
                        out_dtype=args.out_dtype, buffers=args.buffers)
     print(json.dumps(out), flush=True)

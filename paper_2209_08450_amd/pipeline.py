@@ -110,26 +110,32 @@ class ChunkPipeline:
     frames per chunk; storage: 'f16' / 'f32' / 'bf16' for the filtered rows;
     kind: filter window ('ramp', 'shepp', 'parzen'); use_graphs: capture each (size, buffer) once and replay it; poison: fill
     device and pinned buffers with NaN before each use (a missing dependency
-    then shows as NaN in the result).  method: 'linear' (tp_fbp_chunk) or
+    then shows as NaN in the result).  method: 'linear' (tp_fbp_chunk),
     'fourier' (tp_fourier_fbp_chunk; storage is then unused and half_width
-    sets its Gaussian's truncation radius).  buffers: pinned and device buffers
+    sets its Gaussian's truncation radius) or 'lprec' (tp_lprec_fbp_chunk,
+    equally spaced angles; lprec = (spans, oversampling, origin margin), zeros
+    for the defaults; one pass per chunk).  The Fourier-domain and log-polar
+    methods carry two slices as one complex sequence: chunks of even sizes keep
+    the pairs of one monolithic call.  buffers: pinned and device buffers
     per direction (each holds one chunk of max_rows; 2 is the paper's double
     buffering, the default 3 keeps the GPU busy behind uneven chunks).
     """
 
     def __init__(self, plan: "tp.Plan", max_rows: int, n_dark: int, n_flat: int, storage="f16",
                  use_graphs: bool = True, poison: bool = False, device=None, kind="ramp", method="linear",
-                 half_width: int = 0, out_dtype="f32", buffers: int = 3):
+                 half_width: int = 0, out_dtype="f32", buffers: int = 3, lprec=(0, 0.0, 0.0)):
         self.plan = plan
         if int(buffers) < 2:
             raise ValueError(f"buffers must be at least 2, not {buffers}")
         self.nbuf = nb = int(buffers)
         self.kind = kind
         tp.filter_code(kind)  # reject unknown names early
-        if method not in ("linear", "fourier"):
-            raise ValueError(f"method must be 'linear' or 'fourier', not {method!r}")
+        if method not in ("linear", "fourier", "lprec"):
+            raise ValueError(f"method must be 'linear', 'fourier' or 'lprec', not {method!r}")
         self.method = method
         self.half_width = int(half_width)
+        spans, lp_os, lp_eps = lprec
+        self.lprec = (int(spans), float(lp_os), float(lp_eps))
         if out_dtype not in ("f32", "f16"):
             raise ValueError(f"out_dtype must be 'f32' or 'f16', not {out_dtype!r}")
         if out_dtype == "f16" and (method != "linear" or storage != "f16"):
@@ -138,6 +144,8 @@ class ChunkPipeline:
         odt = torch.float16 if out_dtype == "f16" else torch.float32
         if method == "fourier":
             plan.fourier_prepare(kind, self.half_width)  # tables before any capture
+        elif method == "lprec":
+            plan.lprec_prepare(kind, *self.lprec)
         self.device = torch.device(device or f"cuda:{torch.cuda.current_device()}")
         self.max_rows = int(max_rows)
         self.n_dark, self.n_flat = int(n_dark), int(n_flat)
@@ -162,7 +170,14 @@ class ChunkPipeline:
         self.dev_dark = [dev(self.n_dark * r * n, i16) for _ in range(nb)]
         self.dev_flat = [dev(self.n_flat * r * n, i16) for _ in range(nb)]
         self.dev_out = [dev(r * N * N, odt) for _ in range(nb)]
-        ws_bytes = plan.fourier_workspace_bytes(r) if method == "fourier" else plan.fbp_workspace_bytes(r, storage)
+        if method == "fourier":
+            ws_bytes = plan.fourier_workspace_bytes(r)
+        elif method == "lprec":
+            ws_bytes = plan.lprec_workspace_bytes(r, *self.lprec)
+            if ws_bytes == 0:
+                raise ValueError("the log-polar method needs equally spaced angles theta_0 + a pi / n_angles")
+        else:
+            ws_bytes = plan.fbp_workspace_bytes(r, storage)
         self.ws = dev(max(256, ws_bytes), torch.uint8)
         # streams at default priority
         self.s_h2d = torch.cuda.Stream(device=self.device)
@@ -189,6 +204,10 @@ class ChunkPipeline:
         if self.method == "fourier":
             tp.fourier_fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], out=v["dev_out"],
                                  workspace=self.ws, kind=self.kind, half_width=self.half_width)
+        elif self.method == "lprec":
+            spans, lp_os, lp_eps = self.lprec
+            tp.lprec_fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], out=v["dev_out"],
+                               workspace=self.ws, kind=self.kind, spans=spans, os=lp_os, eps=lp_eps)
         else:
             tp.fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], self.storage, out=v["dev_out"],
                          workspace=self.ws, kind=self.kind, out_dtype=self.out_dtype)

@@ -159,6 +159,31 @@ def test_pipeline_fourier_bitwise_equals_monolithic(env):
     assert pl.stats.graphs_captured > 0
 
 
+@pytest.mark.parametrize("graphs,buffers", [(True, 3), (False, 2)])
+def test_pipeline_lprec_bitwise_equals_monolithic(env, graphs, buffers):
+    # the log-polar backprojector behind the same streams: even chunk sizes
+    # keep the slice pairs of one monolithic call (one pass per chunk there,
+    # one pass over all rows here); poisoned buffers expose a missing dependency
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    want = to_host(tp.lprec_fbp_chunk(plan, to_dev(s.proj), to_dev(s.dark), to_dev(s.flat), kind="shepp"))
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, kind="shepp", method="lprec",
+                                use_graphs=graphs, poison=True, buffers=buffers)
+    got = np.full((100, 128, 128), np.nan, np.float32)
+    note(f"pipeline lprec graphs={graphs} buffers={buffers}")
+    st = pl.run(pipeline.uneven_chunks(100, (32, 16)), _source(s), _sink(got))
+    assert st.rows == 100
+    assert np.array_equal(got, want)
+
+
+def test_pipeline_lprec_needs_equal_angles(env):
+    tp, pipeline, _, s = env
+    ang = s.angles.copy()
+    ang[3] += 1e-3  # no longer theta_0 + a pi / n_angles
+    plan = tp.Plan(ang, 128, s.center)
+    with pytest.raises((ValueError, RuntimeError)):
+        pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, method="lprec")
+
 def test_pipeline_files_to_file_bitwise_equals_monolithic(env, tmp_path):
     # storage on both ends: the source reads row chunks from raw projection-major
     # files, the sink writes slices into one volume file (native reader and
