@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--buffers", type=int, default=3,
                     help="pipeline: pinned and device buffers per direction (2: the paper's double buffering)")
     ap.add_argument("--out-dtype", default="f32", choices=("f32", "f16"),
-                    help="pipeline mode: precision of the output slices (f16: the 16-bit mode, FP16 storage only)")
+                    help="pipeline mode: precision of the output slices (f16: 16-bit volumes; linear method with FP16 storage, or the Fourier-domain method)")
     ap.add_argument("--io-dir", default="",
                     help="pipeline mode: read the scan from and write the volume to raw files in this directory "
                          "(native reader/writer threads; the files are written first and deleted afterwards)")
@@ -1171,7 +1171,7 @@ def pipeline_run(dev, n, na, rows, st, pattern, method, kind, io_dir, log, point
     def compute(z0, z1, out, ws):
         if fourier:
             tp.fourier_fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], out=out,
-                                 workspace=ws, kind=kind)
+                                 workspace=ws, kind=kind, out_dtype=out_dtype)
         elif lprec:
             tp.lprec_fbp_chunk(plan, scan.proj[:, z0:z1], scan.dark[:, z0:z1], scan.flat[:, z0:z1], out=out,
                                workspace=ws, kind=kind)

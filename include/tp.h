@@ -374,6 +374,19 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan,
                                       int32_t n_rows, tp_filter_kind kind, int32_t half_width,
                                       void* workspace, size_t workspace_bytes,
                                       float* vol, void* stream, void* const* events);
+/* As tp_fourier_fbp_chunk_events, with the slices stored as `vol_dtype`:
+ * TP_F32, or TP_F16 for 16-bit volumes (paper, Section 3: FP16
+ * reconstructions take half the memory; each voxel's FP32 result is rounded
+ * once to nearest even, so the FP16 slices equal the FP32 slices rounded).
+ * vol: device buffer of n_rows * N * N elements of that type.  Any other
+ * vol_dtype fails with TP_EUNSUPPORTED before anything is enqueued. */
+tp_status tp_fourier_fbp_chunk_out(const tp_plan* plan,
+                                   const uint16_t* proj, int64_t proj_stride,
+                                   const uint16_t* dark, int32_t n_dark,
+                                   const uint16_t* flat, int32_t n_flat, int64_t frame_stride,
+                                   int32_t n_rows, tp_filter_kind kind, int32_t half_width,
+                                   void* workspace, size_t workspace_bytes,
+                                   tp_dtype vol_dtype, void* vol, void* stream, void* const* events);
 
 /* --------------------------------------------------------------------------
  * Log-polar-based filtered backprojection ("LpRec"; paper, Section 2.2: the

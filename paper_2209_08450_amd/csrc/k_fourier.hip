@@ -44,6 +44,16 @@ constexpr float kFrWaveHalfDiag = 4.9497475f;  // 3.5 sqrt(2): the same for a wa
 
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, 0.0f - a.y); }
 
+// Store one voxel: FP32, or the FP32 value rounded once to FP16.  The value is
+// fenced into a register first: otherwise the compiler contracts the product
+// that forms it with the conversion (one mixed-precision multiply rounding the
+// exact product to FP16), which differs from the FP32 slice rounded at ties.
+__device__ __forceinline__ void fr_store(float* p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void fr_store(__half* p, int64_t i, float v) {
+    asm volatile("" : "+v"(v));
+    p[i] = __float2half_rn(v);
+}
+
 int fr_block(int L) {
     int b = L / 16;
     if (b < 64) b = 64;
@@ -296,9 +306,10 @@ k_fr_rows(const float2* __restrict__ grid, const float2* __restrict__ tw, Fourie
 // are dealt to the 8 XCDs in turn), so their shared 128-byte lines are read
 // from that XCD's L2.
 // ---------------------------------------------------------------------------
+template <typename OutT>
 __global__ void __launch_bounds__(1024)
 k_fr_cols(const float2* __restrict__ cols, const float2* __restrict__ tw, FourierTables t, int pairs, int rows,
-          float* __restrict__ vol) {
+          OutT* __restrict__ vol) {
     extern __shared__ float2 buf[];
     const int tid = threadIdx.x, B = blockDim.x;
     const int M = t.M, N = t.N, hN = N / 2;
@@ -316,16 +327,16 @@ k_fr_cols(const float2* __restrict__ cols, const float2* __restrict__ tw, Fourie
     const float fy = t.D[iy];
     const int z0 = 2 * p;
     const bool has1 = z0 + 1 < rows;
-    float* o0 = vol + (static_cast<int64_t>(z0) * N + iy) * N;
-    float* o1 = o0 + static_cast<int64_t>(N) * N;
+    OutT* o0 = vol + (static_cast<int64_t>(z0) * N + iy) * N;
+    OutT* o1 = o0 + static_cast<int64_t>(N) * N;
     for (int m = tid; m < M; m += B) {
         const int x = m < M / 2 ? m : m - M;
         const int ix = x + hN;
         if (ix >= 0 && ix < N) {
             const float2 v = buf[m];  // conj of the inverse transform: (re, -im)
             const float f = t.D[ix] * fy;
-            o0[ix] = v.x * f;
-            if (has1) o1[ix] = (0.0f - v.y) * f;
+            fr_store(o0, ix, v.x * f);  // FP16 slices: the FP32 value rounded once
+            if (has1) fr_store(o1, ix, (0.0f - v.y) * f);
         }
     }
 }
@@ -426,10 +437,10 @@ k_fr_rows_reg(const float2* __restrict__ grid, const float2* __restrict__ tw, Fo
     }
 }
 
-template <int M>
+template <int M, typename OutT>
 __global__ void __launch_bounds__(M / kRegPts)
 k_fr_cols_reg(const float2* __restrict__ cols, const float2* __restrict__ tw, FourierTables t, int pairs, int rows,
-              float* __restrict__ vol) {
+              OutT* __restrict__ vol) {
     // two neighbouring image rows (iy, iy + 1) per work-group: 16-byte loads
     extern __shared__ float2 lds[];
     constexpr int B = M / kRegPts;
@@ -452,8 +463,8 @@ k_fr_cols_reg(const float2* __restrict__ cols, const float2* __restrict__ tw, Fo
     }
     const int z0 = 2 * p;
     const bool has1 = z0 + 1 < rows;
-    float* o0 = vol + (static_cast<int64_t>(z0) * N + iy) * N;
-    float* o1 = o0 + static_cast<int64_t>(N) * N;
+    OutT* o0 = vol + (static_cast<int64_t>(z0) * N + iy) * N;
+    OutT* o1 = o0 + static_cast<int64_t>(N) * N;
     // each row is transformed and stored before the next one is transformed
     auto finish = [&](float2 (&v)[kRegPts], int row) {
         reg_fft<M>(v, lds, tw, tid);
@@ -465,8 +476,8 @@ k_fr_cols_reg(const float2* __restrict__ cols, const float2* __restrict__ tw, Fo
             const int ix = x0 + hN;
             if (ix >= 0 && ix < N) {
                 const float f = t.D[ix] * fy;
-                o0[row * N + ix] = v[s].x * f;
-                if (has1) o1[row * N + ix] = (0.0f - v[s].y) * f;
+                fr_store(o0, row * N + ix, v[s].x * f);
+                if (has1) fr_store(o1, row * N + ix, (0.0f - v[s].y) * f);
             }
         }
     };
@@ -562,16 +573,18 @@ hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const
     return hipGetLastError();
 }
 
-hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
-                               float* vol, hipStream_t st) {
+namespace {
+template <typename OutT>
+hipError_t launch_fourier_cols_t(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
+                                 OutT* vol, hipStream_t st) {
     const int64_t groups = static_cast<int64_t>(pairs) * ((t.N + 15) / 16);
     const dim3 g(static_cast<unsigned>(((groups + 7) / 8) * 8 * 16));
     const dim3 g2(static_cast<unsigned>(((groups + 7) / 8) * 8 * 8));  // two rows per work-group
 #define TP_FR_REG(MM)                                                                                      \
     case MM: {                                                                                            \
-        const hipError_t e = fr_lds(k_fr_cols_reg<MM>, reg_lds(MM));                                      \
+        const hipError_t e = fr_lds(k_fr_cols_reg<MM, OutT>, reg_lds(MM));                                \
         if (e != hipSuccess) return e;                                                                    \
-        hipLaunchKernelGGL((k_fr_cols_reg<MM>), g2, dim3(MM / kRegPts), reg_lds(MM), st, cols, tw_M, t, pairs, \
+        hipLaunchKernelGGL((k_fr_cols_reg<MM, OutT>), g2, dim3(MM / kRegPts), reg_lds(MM), st, cols, tw_M, t, pairs, \
                            rows, vol);                                                                    \
         return hipGetLastError();                                                                         \
     }
@@ -584,10 +597,18 @@ hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const
     }
 #undef TP_FR_REG
     const size_t lds = static_cast<size_t>(t.M) * sizeof(float2);
-    hipError_t e = fr_lds(k_fr_cols, lds);
+    hipError_t e = fr_lds(k_fr_cols<OutT>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fr_cols, g, dim3(fr_block(t.M)), lds, st, cols, tw_M, t, pairs, rows, vol);
+    hipLaunchKernelGGL(k_fr_cols<OutT>, g, dim3(fr_block(t.M)), lds, st, cols, tw_M, t, pairs, rows, vol);
     return hipGetLastError();
+}
+}  // namespace
+
+// vol: FP32 slices, or FP16 (`half_out`: each voxel's FP32 value rounded once).
+hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
+                               void* vol, bool half_out, hipStream_t st) {
+    if (half_out) return launch_fourier_cols_t(t, tw_M, cols, pairs, rows, static_cast<__half*>(vol), st);
+    return launch_fourier_cols_t(t, tw_M, cols, pairs, rows, static_cast<float*>(vol), st);
 }
 
 }  // namespace tp

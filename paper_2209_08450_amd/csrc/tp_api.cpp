@@ -1344,7 +1344,18 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj,
                                       int64_t frame_stride, int32_t n_rows, tp_filter_kind kind, int32_t half_width,
                                       void* workspace, size_t workspace_bytes, float* vol, void* stream,
                                       void* const* events) {
+    return tp_fourier_fbp_chunk_out(plan, proj, proj_stride, dark, n_dark, flat, n_flat, frame_stride, n_rows, kind,
+                                    half_width, workspace, workspace_bytes, TP_F32, vol, stream, events);
+}
+
+tp_status tp_fourier_fbp_chunk_out(const tp_plan* plan, const uint16_t* proj, int64_t proj_stride,
+                                   const uint16_t* dark, int32_t n_dark, const uint16_t* flat, int32_t n_flat,
+                                   int64_t frame_stride, int32_t n_rows, tp_filter_kind kind, int32_t half_width,
+                                   void* workspace, size_t workspace_bytes, tp_dtype vol_dtype, void* vol,
+                                   void* stream, void* const* events) {
     if (!plan) return fail(TP_EINVAL, "plan is null");
+    if (vol_dtype != TP_F32 && vol_dtype != TP_F16)
+        return fail(TP_EUNSUPPORTED, "vol_dtype %d: FP32 or FP16 slices only", static_cast<int>(vol_dtype));
     tp_status s = check_raw(proj, dark, n_dark, flat, n_flat, &proj_stride, &frame_stride, plan->na, n_rows,
                             plan->n);
     if (s != TP_OK) return s;
@@ -1405,8 +1416,10 @@ tp_status tp_fourier_fbp_chunk_events(const tp_plan* plan, const uint16_t* proj,
         e = tp::launch_fourier_rows(t, fm.tw, grid, pp, cols, st);
         if (e != hipSuccess) return hip_fail(e, "Fourier row-transform launch");
         if ((e = mark(4)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        e = tp::launch_fourier_cols(t, fm.tw, cols, pp, rows, vol + static_cast<int64_t>(r0) * plan->N * plan->N,
-                                    st);
+        const size_t esize = vol_dtype == TP_F16 ? 2 : 4;
+        e = tp::launch_fourier_cols(t, fm.tw, cols, pp, rows,
+                                    static_cast<char*>(vol) + static_cast<int64_t>(r0) * plan->N * plan->N * esize,
+                                    vol_dtype == TP_F16, st);
         if (e != hipSuccess) return hip_fail(e, "Fourier column-transform launch");
         if ((e = mark(5)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         first = false;

@@ -161,7 +161,7 @@ hipError_t launch_fourier_grid(const FourierTables& t, const float2* spec, int p
 hipError_t launch_fourier_rows(const FourierTables& t, const float2* tw_M, const float2* grid, int pairs,
                                float2* cols, hipStream_t st);
 hipError_t launch_fourier_cols(const FourierTables& t, const float2* tw_M, const float2* cols, int pairs, int rows,
-                               float* vol, hipStream_t st);
+                               void* vol, bool half_out, hipStream_t st);
 
 int lamino_slices_per_block();
 

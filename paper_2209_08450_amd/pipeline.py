@@ -138,8 +138,9 @@ class ChunkPipeline:
         self.lprec = (int(spans), float(lp_os), float(lp_eps))
         if out_dtype not in ("f32", "f16"):
             raise ValueError(f"out_dtype must be 'f32' or 'f16', not {out_dtype!r}")
-        if out_dtype == "f16" and (method != "linear" or storage != "f16"):
-            raise ValueError("FP16 slices come from the linear method with FP16 storage (the 16-bit mode)")
+        if out_dtype == "f16" and (method == "lprec" or (method == "linear" and storage != "f16")):
+            raise ValueError("FP16 slices come from the linear method with FP16 storage (the 16-bit mode) "
+                             "or from the Fourier-domain method")
         self.out_dtype = out_dtype
         odt = torch.float16 if out_dtype == "f16" else torch.float32
         if method == "fourier":
@@ -203,7 +204,8 @@ class ChunkPipeline:
     def _compute(self, v):
         if self.method == "fourier":
             tp.fourier_fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], out=v["dev_out"],
-                                 workspace=self.ws, kind=self.kind, half_width=self.half_width)
+                                 workspace=self.ws, kind=self.kind, half_width=self.half_width,
+                                 out_dtype=self.out_dtype)
         elif self.method == "lprec":
             spans, lp_os, lp_eps = self.lprec
             tp.lprec_fbp_chunk(self.plan, v["dev_in"], v["dev_dark"], v["dev_flat"], out=v["dev_out"],

@@ -80,6 +80,9 @@ _fourier_chunk = _proto("tp_fourier_fbp_chunk", _c_i32, _c_vp, _c_vp, _c_i64, _c
 _fourier_chunk_events = _proto("tp_fourier_fbp_chunk_events", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
                                _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_vp, _c_vp,
                                ctypes.POINTER(_c_vp))
+_fourier_chunk_out = _proto("tp_fourier_fbp_chunk_out", _c_i32, _c_vp, _c_vp, _c_i64, _c_vp, _c_i32, _c_vp,
+                            _c_i32, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_sz, _c_i32, _c_vp, _c_vp,
+                            ctypes.POINTER(_c_vp))
 
 
 class LprecGrid(ctypes.Structure):
@@ -477,8 +480,10 @@ def fbp_chunk(plan: Plan, proj, dark, flat, storage="f32", out=None, workspace=N
 
 
 def fourier_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, stream=None, events=None,
-                      kind="ramp", half_width: int = 0):
-    """Raw counts of a row chunk -> Fourier-domain FBP slices [rows][N][N] (float32).
+                      kind="ramp", half_width: int = 0, out_dtype="f32"):
+    """Raw counts of a row chunk -> Fourier-domain FBP slices [rows][N][N]
+    (float32, or float16 with ``out_dtype`` 'f16': each voxel's FP32 value
+    rounded once; tp_fourier_fbp_chunk_out).
 
     Same inputs as ``fbp_chunk``; the backprojection uses the trigonometric
     interpolant of each padded filtered row, evaluated by gridding polar
@@ -504,11 +509,18 @@ def fourier_fbp_chunk(plan: Plan, proj, dark, flat, out=None, workspace=None, st
     kcode = filter_code(kind)
     if workspace is None:
         workspace = _workspace(plan.fourier_workspace_bytes(n_rows), proj.device)
-    out = _out(out, (n_rows, plan.n_vox, plan.n_vox), torch.float32, proj)
+    if out_dtype not in ("f32", "f16"):
+        raise ValueError(f"out_dtype must be 'f32' or 'f16', not {out_dtype!r}")
+    half = out_dtype == "f16"
+    out = _out(out, (n_rows, plan.n_vox, plan.n_vox), torch.float16 if half else torch.float32, proj)
     args = (plan.handle, pp, ps, dp, int(dark.shape[0]), fp, int(flat.shape[0]), fs, n_rows, kcode, int(half_width),
             _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(), _dev(out, "out"),
             _stream_ptr(stream))
-    if events is None:
+    if half:
+        if events is not None:
+            raise ValueError("stage events are for FP32 slices")
+        _check(_fourier_chunk_out(*args[:13], dtype_code("f16"), *args[13:], None))
+    elif events is None:
         _check(_fourier_chunk(*args))
     else:
         if len(events) != 6:

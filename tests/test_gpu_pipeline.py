@@ -184,6 +184,29 @@ def test_pipeline_lprec_needs_equal_angles(env):
     with pytest.raises((ValueError, RuntimeError)):
         pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, method="lprec")
 
+def test_fourier_fp16_slices_and_pipeline(env):
+    # 16-bit volumes from the Fourier-domain path: each voxel's FP32 value
+    # rounded once (bitwise the FP32 slices rounded), and the same slices out
+    # of the pipeline with poisoned buffers; the log-polar path refuses them
+    import torch
+    tp, pipeline, _, s = env
+    plan = tp.Plan(s.angles, 128, s.center)
+    P, D, F = to_dev(s.proj), to_dev(s.dark), to_dev(s.flat)
+    want32 = tp.fourier_fbp_chunk(plan, P, D, F, kind="parzen")
+    want16 = tp.fourier_fbp_chunk(plan, P, D, F, kind="parzen", out_dtype="f16")
+    assert want16.dtype == torch.float16
+    assert torch.equal(want16, want32.half())
+    pl = pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, kind="parzen", method="fourier",
+                                out_dtype="f16", poison=True)
+    got = np.full((100, 128, 128), np.nan, np.float16)
+    note("pipeline fourier f16 slices")
+    pl.run(pipeline.uneven_chunks(100, (32, 16)), _source(s), _sink(got))
+    assert np.array_equal(got, want16.cpu().numpy())
+    with pytest.raises(ValueError):
+        tp.fourier_fbp_chunk(plan, P, D, F, out_dtype="bf16")
+    with pytest.raises(ValueError):
+        pipeline.ChunkPipeline(plan, max_rows=32, n_dark=3, n_flat=4, method="lprec", out_dtype="f16")
+
 def test_pipeline_files_to_file_bitwise_equals_monolithic(env, tmp_path):
     # storage on both ends: the source reads row chunks from raw projection-major
     # files, the sink writes slices into one volume file (native reader and
